@@ -1,0 +1,158 @@
+/*
+ * pcx.h -- C ABI of the MI355X nullspace-free Maxwell eigensolver.
+ *
+ * Problem (Huang et al., "Eigenvalue Problems of Discrete Curl Operators on
+ * Various Lattices for Simulating Three Dimensional Photonic Crystals",
+ * arXiv:1806.10284): the Yee-discretised double-curl generalized eigenproblem
+ *     C* C x = lambda B x                                   (Section 3, eq. GEP)
+ * on a Bravais lattice with quasi-periodic (Bloch) boundary conditions
+ * (Section 1.2, eq. quasi_periodic), reduced to the nullspace-free standard
+ * eigenproblem (Section 5.2, Theorem 5.2, eq. NFSEP)
+ *     A_r y = Sigma_r Q_r* B^{-1} Q_r Sigma_r y = lambda y,  x = B^{-1} Q_r Sigma_r y,
+ * where Q_r Sigma_r = (I_3 (x) T) W is applied with FFTs (Algorithms 5.1, 5.2).
+ *
+ * Conventions
+ * -----------
+ * - Every call returns PCX_OK (0) or a negative pcx_status; pcx_last_error()
+ *   then returns a thread-local message.  No exception or abort crosses the ABI.
+ * - Host pointers are plain C arrays owned by the caller.  "device" pointers
+ *   are HIP device allocations owned by the caller (for example torch tensors);
+ *   the library never frees them.  The plan owns its own workspaces.
+ * - Complex numbers are interleaved (re, im): double2 for PCX_FP64 and float2
+ *   for PCX_FP32 (torch.complex128 / torch.complex64).
+ * - Real-space field layout ("e-layout", Section 3, vec()): component l of a
+ *   3n vector occupies [l*n, (l+1)*n) with index a + n1*(b + n2*c), the x index
+ *   a fastest.  Component 1 lives at the Yee point (a+1/2, b, c), 2 at
+ *   (a, b+1/2, c), 3 at (a, b, c+1/2).
+ * - Fourier layout of the 2n vectors y (Section 5.2, y = [y_1; y_2]): block q
+ *   occupies [q*n, (q+1)*n) with the mode index (i*n2 + j)*n3 + k (the column
+ *   order of T, eq. T).  Mode (i,j,k) is the plane wave exp(i g.p) with
+ *   g = 2 pi M^{-1}(kappa + (i,j,k)), M the lattice rows in grid units
+ *   (L1 = (n1,0,0), L2 = (s1,n2,0), L3 = (s2,s3,n3)).
+ * - A block of nvec vectors is stored vector after vector (vector v at offset
+ *   v * 2n for y-blocks, v * 3n for real-space blocks).
+ * - kappa[l] = k . a_l is the Bloch phase per lattice vector (the Bloch wave
+ *   vector is 2 pi k); pcx_kappa_from_bloch converts a Cartesian Bloch vector.
+ * - All launches go to the HIP stream given at plan creation; calls that return
+ *   host results synchronise that stream.  Calls on one plan must not overlap.
+ */
+#ifndef PCX_H
+#define PCX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pcx_status {
+    PCX_OK = 0,
+    PCX_E_ARG = -1,      /* bad argument (null pointer, size out of range, bad enum) */
+    PCX_E_SIZE = -2,     /* a grid size is not a product of 2, 3, 5 or exceeds PCX_MAX_N */
+    PCX_E_LATTICE = -3,  /* degenerate lattice or one violating the primitive-cell condition */
+    PCX_E_NOCONV = -4,   /* eigensolver hit max_iter; lambda and residuals are still filled */
+    PCX_E_OOM = -5,      /* device allocation failed */
+    PCX_E_DEVICE = -6    /* a HIP runtime call failed */
+} pcx_status;
+
+enum { PCX_FP64 = 0, PCX_FP32 = 1 };                 /* arithmetic / storage precision */
+enum { PCX_EPS_YEE3 = 0, PCX_EPS_VOXEL = 1 };        /* permittivity layouts */
+enum { PCX_MODE_FP64 = 0, PCX_MODE_FP32_REFINE = 1, PCX_MODE_FP32 = 2 };
+
+#define PCX_MAX_N 256      /* largest supported n1, n2, n3 */
+#define PCX_MAX_BLOCK 64   /* largest LOBPCG block */
+
+/* Section 2.2 (eq. transvec): the rotated and angle-corrected lattice. */
+typedef struct pcx_geom {
+    int n[3];            /* grid n1, n2, n3 */
+    int m[3];            /* grid offsets m1, m2, m3 (round half up) */
+    int rho[3];          /* 1 where the obtuse case (Case II) was used for m1, m2, m3 */
+    int shift[3];        /* signed offsets s = m - rho*n: a2_x = s1 dx, a3_x = s2 dx, a3_y = s3 dy */
+    double delta[3];     /* mesh sizes dx, dy, dz */
+    double avec_rot[9];  /* row-major 3x3 whose columns are the corrected a1, a2, a3 */
+    double cos_angles[3];/* corrected cos(gamma), cos(beta), cos(alpha) */
+} pcx_geom;
+
+/* Section 2.2.  avec: row-major 3x3 whose COLUMNS are the user's primitive
+ * vectors a~1, a~2, a~3 (any Cartesian frame).  Pure host computation.
+ * Errors: PCX_E_ARG (null/n<1), PCX_E_SIZE (n not 2,3,5-smooth or > PCX_MAX_N),
+ * PCX_E_LATTICE (dependent vectors, or an offset outside 0 <= m <= n). */
+int pcx_geometry(const double avec[9], int n1, int n2, int n3, pcx_geom *out);
+
+/* kappa_l = kvec . a~_l / (2 pi), kvec = the Bloch vector 2 pi k (Section 1.2). Host. */
+int pcx_kappa_from_bloch(const double avec[9], const double kvec[3], double kappa[3]);
+
+typedef struct pcx_plan pcx_plan;
+
+/* Creates a plan for one grid/lattice.  max_vectors bounds nvec in the apply
+ * calls (workspace sizing; 0 selects PCX_MAX_BLOCK).  hip_stream: a hipStream_t
+ * (NULL = default stream).  Selects device = the current HIP device.
+ * Errors: PCX_E_ARG, PCX_E_OOM, PCX_E_DEVICE. */
+int pcx_plan_create(const pcx_geom *g, int max_vectors, void *hip_stream, pcx_plan **out);
+void pcx_plan_destroy(pcx_plan *p);
+
+/* B = diag(eps) of Section 3.  eps: HOST array of doubles, 3n values in the
+ * e-layout (PCX_EPS_YEE3) or n voxel values broadcast to the three Yee edges
+ * owned by each grid point (PCX_EPS_VOXEL).  Every value must be finite and > 0
+ * (else PCX_E_ARG).  Copied to the device (1/eps in FP64 and FP32). */
+int pcx_plan_set_eps(pcx_plan *p, const double *eps, int layout);
+
+/* z = A_r y (eq. NFSEP) for nvec vectors.  y, z: device, 2n complex each, in
+ * `precision`; y and z may not overlap.  Errors: PCX_E_ARG (nvec out of
+ * [1, max_vectors], eps not set), PCX_E_DEVICE. */
+int pcx_apply_Ar(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z, int nvec);
+
+/* u = Q_r Sigma_r y = (I_3 (x) T)(W y) (Section 5.1): 2n -> 3n real space. Device. */
+int pcx_apply_QS(pcx_plan *p, const double kappa[3], int precision, const void *y, void *u, int nvec);
+
+/* z = Sigma_r Q_r* u = W^H (I_3 (x) T*) u: 3n real space -> 2n. Device. */
+int pcx_apply_QS_adjoint(pcx_plan *p, const double kappa[3], int precision, const void *u, void *z, int nvec);
+
+/* x = B^{-1} Q_r Sigma_r y (Theorem 5.2): the GEP eigenvector for an NFSEP one. Device. */
+int pcx_eigvec(pcx_plan *p, const double kappa[3], int precision, const void *y, void *x, int nvec);
+
+typedef struct pcx_opts {
+    int mode;            /* PCX_MODE_FP64 | PCX_MODE_FP32_REFINE | PCX_MODE_FP32 */
+    int block;           /* LOBPCG block size >= nev (0: nev + max(2, nev/4)) */
+    int max_iter;        /* total iterations over both phases */
+    double tol;          /* converged when ||A_r y - lambda y|| <= tol * lambda (||y|| = 1) */
+    double tol_fp32;     /* FP32_REFINE: leave the FP32 phase at this residual */
+    unsigned long long seed;  /* start block */
+    int precondition;    /* 1: precondition with Lambda_q^{-1} (the Sigma_r^{-2} scaling) */
+    int verbose;         /* 1: print one line per iteration to stderr */
+} pcx_opts;
+
+void pcx_opts_default(pcx_opts *o);
+
+typedef struct pcx_stats {
+    int iterations, iterations_fp32;
+    long long matvecs, matvecs_fp32;   /* single-vector A_r applications */
+    double seconds;                    /* wall time of pcx_solve */
+    double seconds_matvec;             /* of which in A_r applications (stream-synchronised) */
+    double residual[PCX_MAX_BLOCK];    /* final relative residual per returned band */
+    int converged;                     /* bands with residual <= tol */
+} pcx_stats;
+
+/* Smallest nev positive eigenvalues of C*C x = lambda B x at Bloch phases kappa
+ * (Section 5.2: block LOBPCG on A_r, Rayleigh-Ritz in FP64 on the host).
+ * lambda: host, nev doubles, ascending.  y_out: device, nev * 2n complex128
+ * (orthonormal NFSEP vectors) or NULL.  x_out: device, nev * 3n complex128
+ * GEP eigenvectors x = B^{-1} Q_r Sigma_r y (so x* B x = lambda), or NULL.
+ * opts may be NULL (defaults), stats may be NULL.
+ * Errors: PCX_E_ARG (nev < 1, block > PCX_MAX_BLOCK or > 2n - 2, eps not set),
+ * PCX_E_NOCONV (lambda and stats filled), PCX_E_OOM, PCX_E_DEVICE. */
+int pcx_solve(pcx_plan *p, const double kappa[3], int nev, const pcx_opts *opts,
+              double *lambda, void *y_out, void *x_out, pcx_stats *stats);
+
+/* Eigenvalue gradient (not in the paper: first-order perturbation of the
+ * Hermitian-definite pencil): for x = B^{-1} Q_r Sigma_r y with ||y|| = 1,
+ * d lambda / d B_pp = -|x_p|^2.  grad = sum_t weight[t] * d lambda_t / d B.
+ * x: device, nvec * 3n complex128 (as returned by pcx_solve), weight: host nvec
+ * doubles, grad: device doubles, 3n (PCX_EPS_YEE3) or n summed over the three
+ * components (PCX_EPS_VOXEL).  Overwrites grad. */
+int pcx_grad_eps(pcx_plan *p, int nvec, const void *x, const double *weight, void *grad, int layout);
+
+const char *pcx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCX_H */

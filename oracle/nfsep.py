@@ -17,8 +17,9 @@ Readings:
     not normalise Pi_1, Pi_2; the value that does is the one above.
   * When Lambda is (nearly) parallel to the all-ones vector the paper's
     construction degenerates (Lambda_p -> 0).  For Lambda_p^2 < TAU Lambda_q we
-    replace the all-ones vector by the unit vector e_m, m = argmin |Lambda_m|
-    (first index on ties); this is another orthonormal basis of the same
+    replace the all-ones vector by the unit vector e_m, m = the first index with
+    |Lambda_m|^2 <= (1 + 1e-8) min_l |Lambda_l|^2 (ties within rounding go to the
+    lowest index); this is another orthonormal basis of the same
     2-dimensional range space, so A_r's eigenvalues are unchanged.
   * A mode with Lambda_q = 0 (only at kappa in Z^3, one mode) has no range
     space: W = 0 there (the Gamma-point mask; A_r then has the two extra zero
@@ -61,7 +62,8 @@ def mixing(lam: np.ndarray) -> np.ndarray:
         bad = (~masked) & (~good)
         if np.any(bad):
             a2 = np.abs(lam) ** 2
-            m = np.argmin(a2, axis=0)
+            mn = a2.min(axis=0)
+            m = np.argmax(a2 <= mn * (1.0 + 1e-8), axis=0)
             for mm in range(3):
                 sel = bad & (m == mm)
                 if not np.any(sel):

@@ -52,7 +52,9 @@ class Spectrum:
 
 
 def _turn_exp_minus_one(t):
-    """exp(i 2 pi t) - 1 without cancellation: -2 sin^2(pi t) + i sin(2 pi t)."""
+    """exp(i 2 pi t) - 1 without cancellation: -2 sin^2(pi t) + i sin(2 pi t).
+    The turn is first reduced to [-1/2, 1/2] (exact), so a whole turn gives exactly 0."""
+    t = t - np.round(t)
     s = np.sin(np.pi * t)
     return -2.0 * s * s + 1j * np.sin(2.0 * np.pi * t)
 

@@ -1,0 +1,101 @@
+"""ctypes declarations of the C ABI in include/pcx.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcx.so")
+
+PCX_OK, PCX_E_ARG, PCX_E_SIZE, PCX_E_LATTICE, PCX_E_NOCONV, PCX_E_OOM, PCX_E_DEVICE = 0, -1, -2, -3, -4, -5, -6
+PCX_FP64, PCX_FP32 = 0, 1
+PCX_EPS_YEE3, PCX_EPS_VOXEL = 0, 1
+PCX_MODE_FP64, PCX_MODE_FP32_REFINE, PCX_MODE_FP32 = 0, 1, 2
+PCX_MAX_N = 256
+PCX_MAX_BLOCK = 64
+
+c_int3 = ctypes.c_int * 3
+c_double3 = ctypes.c_double * 3
+c_double9 = ctypes.c_double * 9
+
+
+class PcxGeom(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int3), ("m", c_int3), ("rho", c_int3), ("shift", c_int3),
+        ("delta", c_double3), ("avec_rot", c_double9), ("cos_angles", c_double3),
+    ]
+
+
+class PcxOpts(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int), ("block", ctypes.c_int), ("max_iter", ctypes.c_int),
+        ("tol", ctypes.c_double), ("tol_fp32", ctypes.c_double),
+        ("seed", ctypes.c_ulonglong), ("precondition", ctypes.c_int), ("verbose", ctypes.c_int),
+    ]
+
+
+class PcxStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int), ("iterations_fp32", ctypes.c_int),
+        ("matvecs", ctypes.c_longlong), ("matvecs_fp32", ctypes.c_longlong),
+        ("seconds", ctypes.c_double), ("seconds_matvec", ctypes.c_double),
+        ("residual", ctypes.c_double * PCX_MAX_BLOCK), ("converged", ctypes.c_int),
+    ]
+
+
+class PcxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pcx error {code}: {msg}")
+        self.code = code
+
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("pcx_geometry", ctypes.c_int, [c_double9, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(PcxGeom)]),
+    ("pcx_kappa_from_bloch", ctypes.c_int, [c_double9, c_double3, c_double3]),
+    ("pcx_plan_create", ctypes.c_int, [ctypes.POINTER(PcxGeom), ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    ("pcx_plan_destroy", None, [ctypes.c_void_p]),
+    ("pcx_plan_set_eps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    ("pcx_apply_Ar", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int]),
+    ("pcx_apply_QS", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int]),
+    ("pcx_apply_QS_adjoint", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_int]),
+    ("pcx_eigvec", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int]),
+    ("pcx_opts_default", None, [ctypes.POINTER(PcxOpts)]),
+    ("pcx_solve", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.POINTER(PcxOpts),
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PcxStats)]),
+    ("pcx_grad_eps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int]),
+    ("pcx_last_error", ctypes.c_char_p, []),
+]
+
+EXPORTED = [s[0] for s in _SIGS]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpcx.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1806_10284_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int):
+    if code != PCX_OK:
+        msg = load().pcx_last_error()
+        raise PcxError(code, msg.decode() if msg else "")
+    return code

@@ -1,0 +1,185 @@
+"""Python binding of the pcx C ABI: the same calls, with torch tensors for device memory.
+
+Every computation runs in libpcx.so (HIP kernels on the current device); this module only
+checks shapes/dtypes and passes pointers and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _avec9(avec) -> L.c_double9:
+    a = np.ascontiguousarray(np.asarray(avec, dtype=np.float64).reshape(3, 3))
+    return L.c_double9(*a.reshape(-1).tolist())
+
+
+def pcx_geometry(avec, n1: int, n2: int, n3: int) -> L.PcxGeom:
+    """Section 2.2: corrected, rotated lattice (columns of ``avec`` are the user's vectors)."""
+    lib = L.load()
+    g = L.PcxGeom()
+    L.check(lib.pcx_geometry(_avec9(avec), int(n1), int(n2), int(n3), ctypes.byref(g)))
+    return g
+
+
+def pcx_kappa_from_bloch(avec, kvec) -> np.ndarray:
+    lib = L.load()
+    out = L.c_double3()
+    L.check(lib.pcx_kappa_from_bloch(_avec9(avec), L.c_double3(*[float(x) for x in kvec]), out))
+    return np.array(list(out))
+
+
+def geom_dict(g: L.PcxGeom) -> dict:
+    return {"n": tuple(g.n), "m": tuple(g.m), "rho": tuple(g.rho), "shift": tuple(g.shift),
+            "delta": tuple(g.delta), "avec_rot": np.array(list(g.avec_rot)).reshape(3, 3),
+            "cos_angles": tuple(g.cos_angles)}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _kappa3(kappa) -> L.c_double3:
+    k = [float(x) for x in kappa]
+    if len(k) != 3:
+        raise ValueError("kappa must have 3 entries")
+    return L.c_double3(*k)
+
+
+@dataclass
+class SolveStats:
+    iterations: int
+    iterations_fp32: int
+    matvecs: int
+    matvecs_fp32: int
+    seconds: float
+    seconds_matvec: float
+    residual: np.ndarray
+    converged: int
+
+
+class Plan:
+    """pcx_plan: one lattice/grid on the current HIP device and torch stream."""
+
+    def __init__(self, geom: L.PcxGeom, max_vectors: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("pcx needs a HIP device (torch.cuda.is_available() is False)")
+        self._lib = L.load()
+        self.geom = geom
+        self.n = int(geom.n[0]) * int(geom.n[1]) * int(geom.n[2])
+        ptr = ctypes.c_void_p()
+        L.check(self._lib.pcx_plan_create(ctypes.byref(geom), int(max_vectors), _stream_handle(), ctypes.byref(ptr)))
+        self._ptr = ptr
+        self.max_vectors = max_vectors or L.PCX_MAX_BLOCK
+
+    def close(self):
+        if getattr(self, "_ptr", None) and self._ptr.value:
+            self._lib.pcx_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- permittivity
+    def pcx_plan_set_eps(self, eps, layout: int = L.PCX_EPS_YEE3):
+        e = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(-1))
+        want = 3 * self.n if layout == L.PCX_EPS_YEE3 else self.n
+        if e.size != want:
+            raise ValueError(f"eps has {e.size} values, expected {want}")
+        L.check(self._lib.pcx_plan_set_eps(self._ptr, e.ctypes.data_as(ctypes.c_void_p), int(layout)))
+
+    # -- operators
+    def _check_block(self, t, per_vec: int, precision: int, name: str) -> int:
+        torch = _torch()
+        dt = torch.complex128 if precision == L.PCX_FP64 else torch.complex64
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != dt:
+            raise ValueError(f"{name} must be {dt}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() % per_vec or t.numel() == 0:
+            raise ValueError(f"{name} must hold whole vectors of {per_vec} entries")
+        return t.numel() // per_vec
+
+    def _apply(self, fn, kappa, precision, x, out, nin, nout):
+        nv = self._check_block(x, nin, precision, "input")
+        nv2 = self._check_block(out, nout, precision, "output")
+        if nv != nv2:
+            raise ValueError("input and output hold different numbers of vectors")
+        L.check(fn(self._ptr, _kappa3(kappa), int(precision), ctypes.c_void_p(x.data_ptr()),
+                   ctypes.c_void_p(out.data_ptr()), nv))
+        return out
+
+    def pcx_apply_Ar(self, kappa, y, z, precision=None):
+        precision = self._prec_of(y) if precision is None else precision
+        return self._apply(self._lib.pcx_apply_Ar, kappa, precision, y, z, 2 * self.n, 2 * self.n)
+
+    def pcx_apply_QS(self, kappa, y, u, precision=None):
+        precision = self._prec_of(y) if precision is None else precision
+        return self._apply(self._lib.pcx_apply_QS, kappa, precision, y, u, 2 * self.n, 3 * self.n)
+
+    def pcx_apply_QS_adjoint(self, kappa, u, z, precision=None):
+        precision = self._prec_of(u) if precision is None else precision
+        return self._apply(self._lib.pcx_apply_QS_adjoint, kappa, precision, u, z, 3 * self.n, 2 * self.n)
+
+    def pcx_eigvec(self, kappa, y, x, precision=None):
+        precision = self._prec_of(y) if precision is None else precision
+        return self._apply(self._lib.pcx_eigvec, kappa, precision, y, x, 2 * self.n, 3 * self.n)
+
+    @staticmethod
+    def _prec_of(t):
+        torch = _torch()
+        return L.PCX_FP64 if t.dtype == torch.complex128 else L.PCX_FP32
+
+    # -- eigensolver
+    def pcx_solve(self, kappa, nev: int, *, mode=L.PCX_MODE_FP64, block=0, max_iter=400, tol=1e-9,
+                  tol_fp32=1e-3, seed=12345, precondition=True, verbose=False, want_y=True, want_x=False,
+                  raise_on_noconv=True):
+        """Returns (lambda[nev] numpy, y (nev, 2n) complex128 or None, x (nev, 3n) complex128 or None, stats)."""
+        torch = _torch()
+        opts = L.PcxOpts()
+        self._lib.pcx_opts_default(ctypes.byref(opts))
+        opts.mode, opts.block, opts.max_iter = int(mode), int(block), int(max_iter)
+        opts.tol, opts.tol_fp32, opts.seed = float(tol), float(tol_fp32), int(seed)
+        opts.precondition, opts.verbose = int(bool(precondition)), int(bool(verbose))
+        lam = np.zeros(nev, dtype=np.float64)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        y = torch.empty((nev, 2 * self.n), dtype=torch.complex128, device=dev) if (want_y or want_x) else None
+        x = torch.empty((nev, 3 * self.n), dtype=torch.complex128, device=dev) if want_x else None
+        st = L.PcxStats()
+        code = self._lib.pcx_solve(self._ptr, _kappa3(kappa), int(nev), ctypes.byref(opts),
+                                   lam.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.c_void_p(y.data_ptr()) if y is not None else None,
+                                   ctypes.c_void_p(x.data_ptr()) if x is not None else None, ctypes.byref(st))
+        stats = SolveStats(st.iterations, st.iterations_fp32, st.matvecs, st.matvecs_fp32, st.seconds,
+                           st.seconds_matvec, np.array(list(st.residual))[:nev], st.converged)
+        if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
+            L.check(code)
+        return lam, (y if want_y else None), x, stats
+
+    def pcx_grad_eps(self, x, weight, layout: int = L.PCX_EPS_YEE3):
+        """-sum_t weight[t] |x_t|^2 per Yee point (or per voxel): d(sum_t w_t lambda_t)/d eps."""
+        torch = _torch()
+        nv = self._check_block(x, 3 * self.n, L.PCX_FP64, "x")
+        w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64).reshape(-1))
+        if w.size != nv:
+            raise ValueError("one weight per eigenvector is needed")
+        out = torch.empty(3 * self.n if layout == L.PCX_EPS_YEE3 else self.n, dtype=torch.float64, device=x.device)
+        L.check(self._lib.pcx_grad_eps(self._ptr, nv, ctypes.c_void_p(x.data_ptr()), w.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.c_void_p(out.data_ptr()), int(layout)))
+        return out

@@ -1,0 +1,766 @@
+// Nullspace-free matvec A_r y = W^H (I3 (x) T*) B^{-1} (I3 (x) T) W y on gfx950.
+//
+// T is the Fourier basis of Section 4.2 (eq. T): mode nu = (i,j,k) is the plane wave
+// exp(i g.p), g = 2 pi t with turns
+//     t_x = (kappa1 + i)/n1,  t_y = (kappa2 + j - s1 t_x)/n2,  t_z = (kappa3 + k - s2 t_x - s3 t_y)/n3,
+// and T q is evaluated as in Algorithm 5.2: an inverse DFT along z, the twiddle
+// exp(2 pi i c phi3(i,j)), an inverse DFT along y, the twiddle exp(2 pi i b phi2(i)), an
+// inverse DFT along x and the twiddle exp(2 pi i a phi1), with
+//     phi1 = kappa1/n1, phi2(i) = (kappa2 - s1 t_x)/n2, phi3(i,j) = (kappa3 - s2 t_x - s3 t_y)/n3.
+// T* reverses the order with conjugate twiddles (Algorithm 5.1).  W (3 x 2 per mode) is the
+// SVD factor Q_r Sigma_r of Section 5.1 (eqs. range_basis1/2).
+//
+// One matvec is three kernels over HBM-resident data:
+//   k_plane_fwd  (plane i):   y -> W y -> z-IDFT -> twiddle -> y-IDFT -> twiddle  -> t[l][i][c][b]
+//   k_xline      (x lines):   t -> x-IDFT -> (1/(n eps)) -> x-DFT                 -> t (in place)
+//   k_plane_adj  (plane i):   t -> twiddle* -> y-DFT -> twiddle* -> z-DFT -> W^H   -> z
+// The x twiddles exp(+-2 pi i a phi1) cancel around the diagonal 1/eps and are not applied.
+// Every 1-D transform is a mixed-radix (8,4,2,3,5) Stockham FFT done in LDS by the whole
+// work-group; every global read and write is coalesced along the unit-stride index.
+#include "pcx_internal.h"
+
+namespace pcx {
+
+#define DEV __device__ __forceinline__
+
+// ------------------------------------------------------------------ complex helpers
+template <typename R>
+DEV cx<R> mk(R a, R b) {
+    cx<R> z;
+    z.x = a;
+    z.y = b;
+    return z;
+}
+template <typename R>
+DEV cx<R> operator+(cx<R> a, cx<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R>
+DEV cx<R> operator-(cx<R> a, cx<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <typename R>
+DEV cx<R> cmul(cx<R> a, cx<R> b) { return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename R>
+DEV cx<R> cmulc(cx<R> a, cx<R> b) { return mk<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }  // a * conj(b)
+template <typename R>
+DEV cx<R> cscale(cx<R> a, R s) { return mk<R>(a.x * s, a.y * s); }
+template <typename R>
+DEV cx<R> times_i(cx<R> a, int sign) { return sign > 0 ? mk<R>(-a.y, a.x) : mk<R>(a.y, -a.x); }  // sign*i*a
+template <typename R>
+DEV cx<R> conjc(cx<R> a) { return mk<R>(a.x, -a.y); }
+
+template <typename R, typename S>
+DEV cx<R> cvt(cx<S> a) { return mk<R>((R)a.x, (R)a.y); }
+
+DEV void sincospi_r(double x, double* s, double* c) { sincospi(x, s, c); }
+DEV void sincospi_r(float x, float* s, float* c) { sincospif(x, s, c); }
+
+// exp(2 pi i * turns) with the turn reduced in FP64 first
+template <typename R>
+DEV cx<R> cis_turns(double turns) {
+    double r = turns - rint(turns);
+    R s, c;
+    sincospi_r((R)(2.0 * r), &s, &c);
+    return mk<R>(c, s);
+}
+
+// ------------------------------------------------------------------ radix butterflies
+// y_q = sum_r x_r exp(sign 2 pi i r q / RAD)
+template <typename R, int RAD>
+struct Bfly;
+
+template <typename R>
+struct Bfly<R, 2> {
+    static DEV void run(cx<R>* v, int) {
+        cx<R> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    }
+};
+
+template <typename R>
+struct Bfly<R, 4> {
+    static DEV void run(cx<R>* v, int s) {
+        cx<R> a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], d = times_i(v[1] - v[3], s);
+        v[0] = a + c;
+        v[2] = a - c;
+        v[1] = b + d;
+        v[3] = b - d;
+    }
+};
+
+template <typename R>
+struct Bfly<R, 3> {
+    static DEV void run(cx<R>* v, int s) {
+        const R c1 = (R)-0.5;
+        const R s1 = (R)0.86602540378443864676;
+        cx<R> t = v[1] + v[2];
+        cx<R> d = times_i(v[1] - v[2], s);
+        cx<R> m = v[0] + cscale(t, c1);
+        v[0] = v[0] + t;
+        v[1] = m + cscale(d, s1);
+        v[2] = m - cscale(d, s1);
+    }
+};
+
+template <typename R>
+struct Bfly<R, 5> {
+    static DEV void run(cx<R>* v, int s) {
+        const R c1 = (R)0.30901699437494742410;   // cos(2 pi / 5)
+        const R c2 = (R)-0.80901699437494742410;  // cos(4 pi / 5)
+        const R s1 = (R)0.95105651629515357212;   // sin(2 pi / 5)
+        const R s2 = (R)0.58778525229247312917;   // sin(4 pi / 5)
+        cx<R> t1 = v[1] + v[4], t2 = v[2] + v[3];
+        cx<R> d1 = times_i(v[1] - v[4], s), d2 = times_i(v[2] - v[3], s);
+        cx<R> a = v[0] + cscale(t1, c1) + cscale(t2, c2);
+        cx<R> b = v[0] + cscale(t1, c2) + cscale(t2, c1);
+        cx<R> p = cscale(d1, s1) + cscale(d2, s2);
+        cx<R> q = cscale(d1, s2) - cscale(d2, s1);
+        v[0] = v[0] + t1 + t2;
+        v[1] = a + p;
+        v[4] = a - p;
+        v[2] = b + q;
+        v[3] = b - q;
+    }
+};
+
+template <typename R>
+struct Bfly<R, 8> {
+    static DEV void run(cx<R>* v, int s) {
+        const R h = (R)0.70710678118654752440;
+        cx<R> e[4] = {v[0], v[2], v[4], v[6]};
+        cx<R> o[4] = {v[1], v[3], v[5], v[7]};
+        Bfly<R, 4>::run(e, s);
+        Bfly<R, 4>::run(o, s);
+        // o_q *= exp(s 2 pi i q / 8)
+        cx<R> o1 = cscale(o[1] + times_i(o[1], s), h);
+        cx<R> o2 = times_i(o[2], s);
+        cx<R> o3 = cscale(times_i(o[3], s) - o[3], h);
+        v[0] = e[0] + o[0];
+        v[4] = e[0] - o[0];
+        v[1] = e[1] + o1;
+        v[5] = e[1] - o1;
+        v[2] = e[2] + o2;
+        v[6] = e[2] - o2;
+        v[3] = e[3] + o3;
+        v[7] = e[3] - o3;
+    }
+};
+
+// ------------------------------------------------------------------ Stockham pass in LDS
+// nlines transforms of length N, element stride es and line stride ls (in elements), in place.
+// Butterfly b -> (line = b % nlines, j = b / nlines) so neighbouring lanes touch neighbouring
+// lines (unit stride for the strided axis).  Pass with radix RAD after the radices whose
+// product is Ns (Stockham autosort): inputs j + r N/RAD, twiddle w^{r (j mod Ns)},
+// w = exp(sign 2 pi i / (Ns RAD)); outputs (j / Ns) Ns RAD + j mod Ns + r Ns.
+template <typename R, int RAD, int MAXB>
+DEV void stockham_pass(cx<R>* buf, int N, int Ns, int nlines, int es, int ls, const cx<R>* tw, int sign) {
+    const int NR = N / RAD;
+    const int total = NR * nlines;
+    const int twstep = N / (Ns * RAD);
+    cx<R> v[MAXB][RAD];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const int b = threadIdx.x + t * kThreads;
+        if (b < total) {
+            const int line = b % nlines;
+            const int j = b / nlines;
+            const cx<R>* src = buf + line * ls + j * es;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) v[t][r] = src[r * NR * es];
+            const int k = j % Ns;
+            if (k) {
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) {
+                    cx<R> w = tw[r * k * twstep];
+                    if (sign < 0) w.y = -w.y;
+                    v[t][r] = cmul(v[t][r], w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const int b = threadIdx.x + t * kThreads;
+        if (b < total) {
+            const int line = b % nlines;
+            const int j = b / nlines;
+            const int k = j % Ns;
+            Bfly<R, RAD>::run(v[t], sign);
+            cx<R>* dst = buf + line * ls + ((j / Ns) * Ns * RAD + k) * es;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) dst[r * Ns * es] = v[t][r];
+        }
+    }
+    __syncthreads();
+}
+
+// EPT >= ceil(N * nlines / kThreads)
+template <typename R, int EPT>
+DEV void fft_lines(cx<R>* buf, const FftPlan& fp, int nlines, int es, int ls, const cx<R>* tw, int sign) {
+    int Ns = 1;
+    for (int p = 0; p < fp.npass; ++p) {
+        const int rad = fp.rad[p];
+        switch (rad) {
+            case 8: stockham_pass<R, 8, (EPT + 7) / 8>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
+            case 4: stockham_pass<R, 4, (EPT + 3) / 4>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
+            case 2: stockham_pass<R, 2, (EPT + 1) / 2>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
+            case 3: stockham_pass<R, 3, (EPT + 2) / 3>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
+            default: stockham_pass<R, 5, (EPT + 4) / 5>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
+        }
+        Ns *= rad;
+    }
+}
+
+// ------------------------------------------------------------------ per-mode symbols (FP64)
+// exp(i 2 pi t) - 1 = 2 s (-s + i c) with (s, c) = (sin, cos)(pi t)
+DEV cx<double> lam_from_halfturn(double s, double c, double inv_delta) {
+    return mk<double>(-2.0 * s * s * inv_delta, 2.0 * s * c * inv_delta);
+}
+DEV cx<double> lam_of_turn(double t, double inv_delta) {
+    double r = t - rint(t);
+    double s, c;
+    sincospi(r, &s, &c);
+    return lam_from_halfturn(s, c, inv_delta);
+}
+
+DEV double abs2(cx<double> a) { return a.x * a.x + a.y * a.y; }
+
+// Row l of W (Section 5.1): W[:,0] = (Lq 1 - Lambda conj(Ls)) / Lp, W[:,1] = sqrt(Lq) (1 x conj Lambda) / Lp,
+// Lp^2 = sum_{a<b} |Lambda_a - Lambda_b|^2; for Lp^2 < tau Lq the reference vector 1 is replaced by
+// e_m, m = first index with |Lambda_m|^2 <= (1 + 1e-8) min |Lambda|^2.
+DEV void w_row(cx<double> L0, cx<double> L1, cx<double> L2, int l, cx<double>* w1, cx<double>* w2) {
+    const double a0 = abs2(L0), a1 = abs2(L1), a2 = abs2(L2);
+    const double Lq = a0 + a1 + a2;
+    const double Lp2 = abs2(L0 - L1) + abs2(L0 - L2) + abs2(L1 - L2);
+    const double sq = sqrt(Lq);
+    const cx<double> Ll = (l == 0) ? L0 : (l == 1 ? L1 : L2);
+    // components of conj(Lambda)
+    const cx<double> v0 = conjc(L0), v1 = conjc(L1), v2 = conjc(L2);
+    if (Lp2 >= kMixTau * Lq) {
+        const double inv = 1.0 / sqrt(Lp2);
+        const cx<double> Ls = L0 + L1 + L2;
+        cx<double> c1 = mk<double>(Lq, 0.0) - cmulc(Ll, Ls);
+        cx<double> cr = (l == 0) ? (v2 - v1) : (l == 1 ? (v0 - v2) : (v1 - v0));
+        *w1 = cscale(c1, inv);
+        *w2 = cscale(cr, sq * inv);
+    } else {
+        const double mn = fmin(a0, fmin(a1, a2)) * (1.0 + 1e-8);
+        const int m = (a0 <= mn) ? 0 : ((a1 <= mn) ? 1 : 2);
+        const double am = (m == 0) ? a0 : (m == 1 ? a1 : a2);
+        const cx<double> Lm = (m == 0) ? L0 : (m == 1 ? L1 : L2);
+        const double inv = 1.0 / sqrt(Lq - am);
+        cx<double> c1 = mk<double>(l == m ? Lq : 0.0, 0.0) - cmulc(Ll, Lm);
+        // e_m x v: e0 -> (0, -v2, v1); e1 -> (v2, 0, -v0); e2 -> (-v1, v0, 0)
+        cx<double> zero = mk<double>(0.0, 0.0);
+        cx<double> cr;
+        if (m == 0) cr = (l == 0) ? zero : (l == 1 ? zero - v2 : v1);
+        else if (m == 1) cr = (l == 0) ? v2 : (l == 1 ? zero : zero - v0);
+        else cr = (l == 0) ? zero - v1 : (l == 1 ? v0 : zero);
+        *w1 = cscale(c1, inv);
+        *w2 = cscale(cr, sq * inv);
+    }
+}
+
+// ------------------------------------------------------------------ plane set-up (shared by both plane kernels)
+// LDS layout of a plane kernel (dynamic shared memory):
+//   plane  cx<R>[n2 * (n3 + 1)]      row j (or b) has n3 (+1 pad) entries
+//   twz    cx<R>[n3]  LUT exp(+2 pi i m / n3)
+//   twy    cx<R>[n2]  LUT exp(+2 pi i m / n2)
+//   twb    cx<R>[n2]  exp(2 pi i b phi2(i))
+//   halfz  cx<double>[n3]  exp(i pi k / n3)
+//   rowz   cx<double>[n2]  exp(i pi phi3(i, j))
+//   lamy   cx<double>[n2]  Lambda_2(i, j)
+//   phi3   double[n2]
+//   kstar  int[n2]   masked k of row j (or -1)
+template <typename R>
+struct PlaneLds {
+    cx<R>* plane;
+    cx<R>* twz;
+    cx<R>* twy;
+    cx<R>* twb;
+    cx<double>* halfz;
+    cx<double>* rowz;
+    cx<double>* lamy;
+    double* phi3;
+    int* kstar;
+};
+
+template <typename R>
+__host__ DEV size_t plane_lds_bytes(int n2, int n3) {
+    size_t b = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + n3 + 2 * n2);
+    b = (b + 15) & ~(size_t)15;
+    b += sizeof(cx<double>) * (n3 + 2 * n2) + sizeof(double) * n2 + sizeof(int) * n2;
+    return b;
+}
+
+template <typename R>
+DEV PlaneLds<R> plane_lds(char* base, int n2, int n3) {
+    PlaneLds<R> L;
+    L.plane = (cx<R>*)base;
+    L.twz = L.plane + (size_t)n2 * (n3 + 1);
+    L.twy = L.twz + n3;
+    L.twb = L.twy + n2;
+    size_t off = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + n3 + 2 * n2);
+    off = (off + 15) & ~(size_t)15;
+    L.halfz = (cx<double>*)(base + off);
+    L.rowz = L.halfz + n3;
+    L.lamy = L.rowz + n2;
+    L.phi3 = (double*)(L.lamy + n2);
+    L.kstar = (int*)(L.phi3 + n2);
+    return L;
+}
+
+// Fills the tables for plane i; returns Lambda_1(i) and whether t_x(i) is whole.
+template <typename R>
+DEV void plane_setup(const Grid& g, const DeviceTables& tb, int i, PlaneLds<R>& L, cx<double>* lamx_out) {
+    const int n2 = g.n2, n3 = g.n3;
+    const double tx = (g.kap[0] + (double)i) / (double)g.n1;
+    const bool tx_whole = (tx == rint(tx));
+    const cx<R>* twz_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[2] : (const cx<R>*)tb.tw32[2];
+    const cx<R>* twy_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[1] : (const cx<R>*)tb.tw32[1];
+    const double phi2 = (g.kap[1] - (double)g.s1 * tx) / (double)n2;
+    for (int q = threadIdx.x; q < n3; q += kThreads) {
+        L.twz[q] = twz_g[q];
+        L.halfz[q] = tb.halfz[q];
+    }
+    for (int j = threadIdx.x; j < n2; j += kThreads) {
+        L.twy[j] = twy_g[j];
+        L.twb[j] = cis_turns<R>((double)j * phi2);
+        const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)n2;
+        L.lamy[j] = lam_of_turn(ty, 1.0 / g.dlt[1]);
+        const double p3 = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)n3;
+        L.phi3[j] = p3;
+        double s, c;
+        sincospi(p3, &s, &c);
+        L.rowz[j] = mk<double>(c, s);
+        int ks = -1;
+        const double Rz = (g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty;   // t_z = (k + Rz) / n3
+        if (tx_whole && ty == rint(ty) && Rz == rint(Rz)) {
+            long kk = (-(long)rint(Rz)) % n3;
+            if (kk < 0) kk += n3;
+            ks = (int)kk;
+        }
+        L.kstar[j] = ks;
+    }
+    *lamx_out = lam_of_turn(tx, 1.0 / g.dlt[0]);
+}
+
+// Lambda_3 at (j, k) from the tables: exp(i pi t_z) = exp(i pi k / n3) exp(i pi phi3(i, j))
+template <typename R>
+DEV cx<double> lam_z(const PlaneLds<R>& L, int j, int k, double inv_dz) {
+    cx<double> h = cmul(L.halfz[k], L.rowz[j]);
+    return lam_from_halfturn(h.y, h.x, inv_dz);
+}
+
+// ------------------------------------------------------------------ kernel 1: W y, then z and y inverse DFTs
+// y: [v][2][n1][n2][n3]   ->   t: [v][3][n1][n3][n2]
+template <typename R, int EPT>
+__global__ void __launch_bounds__(kThreads) k_plane_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
+                                                         cx<R>* __restrict__ t) {
+    extern __shared__ __align__(16) char lds[];
+    const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+    const int i = blockIdx.x;
+    const int v = blockIdx.y;
+    const long n = (long)n1 * n2 * n3;
+    const int np = n2 * n3;
+    const int ld = n3 + 1;
+    PlaneLds<R> L = plane_lds<R>(lds, n2, n3);
+    cx<double> lamx;
+    plane_setup<R>(g, tb, i, L, &lamx);
+    __syncthreads();
+
+    // this thread's elements e = tid + s * kThreads of the plane: (j, k) = (e / n3, e % n3)
+    cx<R> y1[EPT], y2[EPT], twc[EPT];
+    const cx<R>* yb = y + (long)v * 2 * n + (long)i * np;
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * kThreads;
+        if (e < np) {
+            y1[s] = yb[e];
+            y2[s] = yb[n + e];
+            const int j = e / n3, c = e % n3;
+            twc[s] = cis_turns<R>((double)c * L.phi3[j]);
+        }
+    }
+    const double idz = 1.0 / g.dlt[2];
+    for (int l = 0; l < 3; ++l) {
+        // u_l = W_l1 y1 + W_l2 y2 into the plane [j][k]
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * kThreads;
+            if (e < np) {
+                const int j = e / n3, k = e % n3;
+                cx<R> u = mk<R>(0, 0);
+                if (L.kstar[j] != k) {
+                    cx<double> w1, w2;
+                    w_row(lamx, L.lamy[j], lam_z(L, j, k, idz), l, &w1, &w2);
+                    u = cmul(cvt<R>(w1), y1[s]) + cmul(cvt<R>(w2), y2[s]);
+                }
+                L.plane[j * ld + k] = u;
+            }
+        }
+        __syncthreads();
+        fft_lines<R, EPT>(L.plane, g.fz, n2, 1, ld, L.twz, +1);        // k -> c along rows j
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * kThreads;
+            if (e < np) {
+                const int j = e / n3, c = e % n3;
+                L.plane[j * ld + c] = cmul(L.plane[j * ld + c], twc[s]);
+            }
+        }
+        __syncthreads();
+        fft_lines<R, EPT>(L.plane, g.fy, n3, ld, 1, L.twy, +1);        // j -> b along columns c
+        // write t[v][l][i][c][b] = plane[b][c] * exp(2 pi i b phi2)
+        cx<R>* tb_out = t + ((long)v * 3 + l) * n + (long)i * np;
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * kThreads;
+            if (e < np) {
+                const int c = e / n2, b = e % n2;
+                tb_out[e] = cmul(L.plane[b * ld + c], L.twb[b]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ kernel 3: y and z forward DFTs, then W^H
+// t: [v][3][n1][n3][n2]  ->  z: [v][2][n1][n2][n3]
+template <typename R, int EPT>
+__global__ void __launch_bounds__(kThreads) k_plane_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
+                                                         cx<R>* __restrict__ z) {
+    extern __shared__ __align__(16) char lds[];
+    const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+    const int i = blockIdx.x;
+    const int v = blockIdx.y;
+    const long n = (long)n1 * n2 * n3;
+    const int np = n2 * n3;
+    const int ld = n3 + 1;
+    PlaneLds<R> L = plane_lds<R>(lds, n2, n3);
+    cx<double> lamx;
+    plane_setup<R>(g, tb, i, L, &lamx);
+    __syncthreads();
+
+    cx<R> acc1[EPT], acc2[EPT], twc[EPT];
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * kThreads;
+        acc1[s] = mk<R>(0, 0);
+        acc2[s] = mk<R>(0, 0);
+        if (e < np) {
+            const int j = e / n3, c = e % n3;
+            twc[s] = cis_turns<R>((double)c * L.phi3[j]);
+        }
+    }
+    const double idz = 1.0 / g.dlt[2];
+    for (int l = 0; l < 3; ++l) {
+        const cx<R>* tin = t + ((long)v * 3 + l) * n + (long)i * np;
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * kThreads;
+            if (e < np) {
+                const int c = e / n2, b = e % n2;
+                L.plane[b * ld + c] = cmulc(tin[e], L.twb[b]);
+            }
+        }
+        __syncthreads();
+        fft_lines<R, EPT>(L.plane, g.fy, n3, ld, 1, L.twy, -1);        // b -> j along columns c
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * kThreads;
+            if (e < np) {
+                const int j = e / n3, c = e % n3;
+                L.plane[j * ld + c] = cmulc(L.plane[j * ld + c], twc[s]);
+            }
+        }
+        __syncthreads();
+        fft_lines<R, EPT>(L.plane, g.fz, n2, 1, ld, L.twz, -1);        // c -> k along rows j
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * kThreads;
+            if (e < np) {
+                const int j = e / n3, k = e % n3;
+                if (L.kstar[j] != k) {
+                    cx<double> w1, w2;
+                    w_row(lamx, L.lamy[j], lam_z(L, j, k, idz), l, &w1, &w2);
+                    const cx<R> val = L.plane[j * ld + k];
+                    acc1[s] = acc1[s] + cmulc(val, cvt<R>(w1));
+                    acc2[s] = acc2[s] + cmulc(val, cvt<R>(w2));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    cx<R>* zb = z + (long)v * 2 * n + (long)i * np;
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * kThreads;
+        if (e < np) {
+            zb[e] = acc1[s];
+            zb[n + e] = acc2[s];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernel 2: x-line transforms
+// Tile = TB consecutive (c, b) positions q = c * n2 + b, all i.
+// MODE 0: t -> IDFT_x -> * inv_eps/n -> DFT_x -> t            (matvec, in place)
+// MODE 1: t -> IDFT_x -> * exp(2 pi i a phi1) n^{-1/2} (* inv_eps if given) -> u (e-layout)
+// MODE 2: u (e-layout) -> * exp(-2 pi i a phi1) n^{-1/2} -> DFT_x -> t
+template <typename R, int EPT, int MODE>
+__global__ void __launch_bounds__(kThreads) k_xline(Grid g, DeviceTables tb, const R* __restrict__ scale,
+                                                     cx<R>* __restrict__ t, cx<R>* __restrict__ u, int TB) {
+    extern __shared__ __align__(16) char lds[];
+    const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+    const long n = (long)n1 * n2 * n3;
+    const long np = (long)n2 * n3;
+    const int v = blockIdx.y;
+    const long q0 = (long)blockIdx.x * TB;
+    const int qn = (int)((np - q0) < TB ? (np - q0) : TB);
+    const int ld = n1 + 1;
+    cx<R>* buf = (cx<R>*)lds;
+    cx<R>* twx = buf + (size_t)TB * ld;
+    cx<R>* twa = twx + n1;
+    const cx<R>* twx_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[0] : (const cx<R>*)tb.tw32[0];
+    const double phi1 = g.kap[0] / (double)n1;
+    for (int a = threadIdx.x; a < n1; a += kThreads) {
+        twx[a] = twx_g[a];
+        if (MODE != 0) twa[a] = cis_turns<R>((double)a * phi1);
+    }
+    const R rsq = (R)(1.0 / sqrt((double)n));
+    const int tot = n1 * qn;
+    for (int l = 0; l < 3; ++l) {
+        cx<R>* tl = t + ((long)v * 3 + l) * n;
+        cx<R>* ul = u + ((long)v * 3 + l) * n;
+        __syncthreads();
+        if (MODE != 2) {
+            // load t[i][q0 + ql] -> buf[ql][i]
+            for (int e = threadIdx.x; e < tot; e += kThreads) {
+                const int ii = e / qn, ql = e % qn;
+                buf[ql * ld + ii] = tl[(long)ii * np + q0 + ql];
+            }
+            __syncthreads();
+            fft_lines<R, EPT>(buf, g.fx, qn, 1, ld, twx, +1);            // i -> a
+        } else {
+            // load u[(q0 + ql) * n1 + a] -> buf[ql][a] with the conjugate x twiddle
+            for (int e = threadIdx.x; e < tot; e += kThreads) {
+                const int ql = e / n1, a = e % n1;
+                cx<R> val = ul[(q0 + ql) * n1 + a];
+                buf[ql * ld + a] = cscale(cmulc(val, twa[a]), rsq);
+            }
+            __syncthreads();
+        }
+        if (MODE == 0) {
+            const R* sl = scale + (long)l * n;
+            for (int e = threadIdx.x; e < tot; e += kThreads) {
+                const int ql = e / n1, a = e % n1;
+                buf[ql * ld + a] = cscale(buf[ql * ld + a], sl[(q0 + ql) * n1 + a]);
+            }
+            __syncthreads();
+        }
+        if (MODE == 1) {
+            const R* sl = scale ? scale + (long)l * n : nullptr;
+            for (int e = threadIdx.x; e < tot; e += kThreads) {
+                const int ql = e / n1, a = e % n1;
+                R f = rsq;
+                if (sl) f *= sl[(q0 + ql) * n1 + a];
+                ul[(q0 + ql) * n1 + a] = cscale(cmul(buf[ql * ld + a], twa[a]), f);
+            }
+            continue;
+        }
+        fft_lines<R, EPT>(buf, g.fx, qn, 1, ld, twx, -1);                // a -> i
+        for (int e = threadIdx.x; e < tot; e += kThreads) {
+            const int ii = e / qn, ql = e % qn;
+            tl[(long)ii * np + q0 + ql] = buf[ql * ld + ii];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ preconditioner diagonal
+__global__ void k_precond(Grid g, DeviceTables tb, double* __restrict__ out) {
+    const long n = (long)g.n1 * g.n2 * g.n3;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int k = (int)(e % g.n3);
+        const int j = (int)((e / g.n3) % g.n2);
+        const int i = (int)(e / ((long)g.n2 * g.n3));
+        const double tx = (g.kap[0] + (double)i) / (double)g.n1;
+        const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)g.n2;
+        const double Rz = (g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty;
+        const double tz = ((g.kap[2] + (double)k) - (double)g.s2 * tx - (double)g.s3 * ty) / (double)g.n3;
+        bool masked = false;
+        if (tx == rint(tx) && ty == rint(ty) && Rz == rint(Rz)) {
+            long kk = (-(long)rint(Rz)) % g.n3;
+            if (kk < 0) kk += g.n3;
+            masked = (kk == k);
+        }
+        double Lq = abs2(lam_of_turn(tx, 1.0 / g.dlt[0])) + abs2(lam_of_turn(ty, 1.0 / g.dlt[1])) +
+                    abs2(lam_of_turn(tz, 1.0 / g.dlt[2]));
+        out[e] = masked ? 0.0 : 1.0 / Lq;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static int ept_for(long elems) {
+    long e = (elems + kThreads - 1) / kThreads;
+    int p = 1;
+    while (p < e) p <<= 1;
+    return p;
+}
+
+static int xline_tile(int n1) {
+    // enough lines per tile to give every thread a few elements, and whole 64-wide segments
+    int tb = 64;
+    if (n1 <= 16) tb = 128;
+    return tb;
+}
+
+template <typename R>
+static size_t xline_lds_bytes(int n1, int TB) {
+    return sizeof(cx<R>) * ((size_t)TB * (n1 + 1) + 2 * n1);
+}
+
+#define PCX_EPT_DISPATCH(EPTV, CALL) \
+    switch (EPTV) {                  \
+        case 1: CALL(1); break;      \
+        case 2: CALL(2); break;      \
+        case 4: CALL(4); break;      \
+        case 8: CALL(8); break;      \
+        case 16: CALL(16); break;    \
+        case 32: CALL(32); break;    \
+        case 64: CALL(64); break;    \
+        default: return hipErrorInvalidValue; \
+    }
+
+template <typename R>
+static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, int nvec,
+                            hipStream_t st) {
+    dim3 grid(g.n1, nvec);
+    const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
+    const int ept = ept_for((long)g.n2 * g.n3);
+#define CALLF(E) hipLaunchKernelGGL((k_plane_fwd<R, E>), grid, dim3(kThreads), lds, st, g, tb, y, t)
+    PCX_EPT_DISPATCH(ept, CALLF)
+#undef CALLF
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, int nvec,
+                            hipStream_t st) {
+    dim3 grid(g.n1, nvec);
+    const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
+    const int ept = ept_for((long)g.n2 * g.n3);
+#define CALLA(E) hipLaunchKernelGGL((k_plane_adj<R, E>), grid, dim3(kThreads), lds, st, g, tb, t, z)
+    PCX_EPT_DISPATCH(ept, CALLA)
+#undef CALLA
+    return hipGetLastError();
+}
+
+template <typename R, int MODE>
+static hipError_t xline(const Grid& g, const DeviceTables& tb, const R* scale, cx<R>* t, cx<R>* u, int nvec,
+                        hipStream_t st) {
+    const int TB = xline_tile(g.n1);
+    const long np = (long)g.n2 * g.n3;
+    dim3 grid((unsigned)((np + TB - 1) / TB), nvec);
+    const size_t lds = xline_lds_bytes<R>(g.n1, TB);
+    const int ept = ept_for((long)g.n1 * TB);
+#define CALLX(E) hipLaunchKernelGGL((k_xline<R, E, MODE>), grid, dim3(kThreads), lds, st, g, tb, scale, t, u, TB)
+    PCX_EPT_DISPATCH(ept, CALLX)
+#undef CALLX
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y, cx<R>* z,
+                           cx<R>* t, int nvec, hipStream_t st) {
+    hipError_t e = plane_fwd<R>(g, tb, y, t, nvec, st);
+    if (e != hipSuccess) return e;
+    e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
+    if (e != hipSuccess) return e;
+    return plane_adj<R>(g, tb, t, z, nvec, st);
+}
+
+template <typename R>
+hipError_t launch_QS(const Grid& g, const DeviceTables& tb, const R* inv_eps, const cx<R>* y, cx<R>* u, cx<R>* t,
+                     int nvec, hipStream_t st) {
+    hipError_t e = plane_fwd<R>(g, tb, y, t, nvec, st);
+    if (e != hipSuccess) return e;
+    return xline<R, 1>(g, tb, inv_eps, t, u, nvec, st);
+}
+
+template <typename R>
+hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>* u, cx<R>* z, cx<R>* t, int nvec,
+                             hipStream_t st) {
+    hipError_t e = xline<R, 2>(g, tb, nullptr, t, const_cast<cx<R>*>(u), nvec, st);
+    if (e != hipSuccess) return e;
+    return plane_adj<R>(g, tb, t, z, nvec, st);
+}
+
+hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st) {
+    const long n = (long)g.n1 * g.n2 * g.n3;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_precond, dim3(blocks), dim3(256), 0, st, g, tb, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t set_lds_limits() {
+    const int maxb = 160 * 1024;
+#define SETP(E)                                                                                            \
+    do {                                                                                                   \
+        hipError_t e1 = hipFuncSetAttribute((const void*)k_plane_fwd<R, E>,                                \
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, maxb);             \
+        if (e1 != hipSuccess) return e1;                                                                   \
+        e1 = hipFuncSetAttribute((const void*)k_plane_adj<R, E>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                 maxb);                                                                    \
+        if (e1 != hipSuccess) return e1;                                                                   \
+        e1 = hipFuncSetAttribute((const void*)k_xline<R, E, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                 maxb);                                                                    \
+        if (e1 != hipSuccess) return e1;                                                                   \
+        e1 = hipFuncSetAttribute((const void*)k_xline<R, E, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                 maxb);                                                                    \
+        if (e1 != hipSuccess) return e1;                                                                   \
+        e1 = hipFuncSetAttribute((const void*)k_xline<R, E, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                 maxb);                                                                    \
+        if (e1 != hipSuccess) return e1;                                                                   \
+    } while (0)
+    SETP(1);
+    SETP(2);
+    SETP(4);
+    SETP(8);
+    SETP(16);
+    SETP(32);
+    SETP(64);
+#undef SETP
+    return hipSuccess;
+}
+
+hipError_t configure_kernels() {
+    hipError_t e = set_lds_limits<float>();
+    if (e != hipSuccess) return e;
+    return set_lds_limits<double>();
+}
+
+size_t plane_kernel_lds(int n2, int n3, int fp64) {
+    return fp64 ? plane_lds_bytes<double>(n2, n3) : plane_lds_bytes<float>(n2, n3);
+}
+size_t xline_kernel_lds(int n1, int fp64) {
+    const int TB = xline_tile(n1);
+    return fp64 ? xline_lds_bytes<double>(n1, TB) : xline_lds_bytes<float>(n1, TB);
+}
+int xline_kernel_tile(int n1) { return xline_tile(n1); }
+
+template hipError_t launch_apply_Ar<float>(const Grid&, const DeviceTables&, const float*, const cx<float>*,
+                                           cx<float>*, cx<float>*, int, hipStream_t);
+template hipError_t launch_apply_Ar<double>(const Grid&, const DeviceTables&, const double*, const cx<double>*,
+                                            cx<double>*, cx<double>*, int, hipStream_t);
+template hipError_t launch_QS<float>(const Grid&, const DeviceTables&, const float*, const cx<float>*, cx<float>*,
+                                     cx<float>*, int, hipStream_t);
+template hipError_t launch_QS<double>(const Grid&, const DeviceTables&, const double*, const cx<double>*,
+                                      cx<double>*, cx<double>*, int, hipStream_t);
+template hipError_t launch_QS_adjoint<float>(const Grid&, const DeviceTables&, const cx<float>*, cx<float>*,
+                                             cx<float>*, int, hipStream_t);
+template hipError_t launch_QS_adjoint<double>(const Grid&, const DeviceTables&, const cx<double>*, cx<double>*,
+                                              cx<double>*, int, hipStream_t);
+
+}  // namespace pcx

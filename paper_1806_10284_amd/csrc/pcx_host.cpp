@@ -1,0 +1,433 @@
+// Host side of the C ABI: lattice geometry (Section 2.2), plans and the apply entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "pcx_host.h"
+
+namespace pcx {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? PCX_E_OOM : PCX_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- Section 2.2
+// floor when the fractional part is below 1/2, ceil otherwise; arguments within 1e-9 of an
+// integer are taken as that integer.
+static long round_half_up(double x) {
+    const double r = std::round(x);
+    if (std::fabs(x - r) < 1e-9) return (long)r;
+    const double f = std::floor(x);
+    return (x - f) < 0.5 ? (long)f : (long)std::ceil(x);
+}
+
+static bool smooth235(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+bool make_fft_plan(int n, FftPlan* fp) {
+    if (!smooth235(n) || n > PCX_MAX_N) return false;
+    fp->n = n;
+    fp->npass = 0;
+    int m = n;
+    while (m % 8 == 0) { fp->rad[fp->npass++] = 8; m /= 8; }
+    while (m % 4 == 0) { fp->rad[fp->npass++] = 4; m /= 4; }
+    while (m % 2 == 0) { fp->rad[fp->npass++] = 2; m /= 2; }
+    while (m % 3 == 0) { fp->rad[fp->npass++] = 3; m /= 3; }
+    while (m % 5 == 0) { fp->rad[fp->npass++] = 5; m /= 5; }
+    return fp->npass <= kMaxPasses;
+}
+
+static double col_norm(const double* a, int c) {
+    return std::sqrt(a[0 * 3 + c] * a[0 * 3 + c] + a[1 * 3 + c] * a[1 * 3 + c] + a[2 * 3 + c] * a[2 * 3 + c]);
+}
+static double col_dot(const double* a, int c, int d) {
+    return a[0 * 3 + c] * a[0 * 3 + d] + a[1 * 3 + c] * a[1 * 3 + d] + a[2 * 3 + c] * a[2 * 3 + d];
+}
+
+}  // namespace pcx
+
+using namespace pcx;
+
+extern "C" const char* pcx_last_error(void) { return g_err.c_str(); }
+
+extern "C" int pcx_geometry(const double avec[9], int n1, int n2, int n3, pcx_geom* out) {
+    if (!avec || !out) return fail(PCX_E_ARG, "pcx_geometry: null pointer");
+    if (n1 < 1 || n2 < 1 || n3 < 1) return fail(PCX_E_ARG, "pcx_geometry: grid sizes must be positive");
+    for (int n : {n1, n2, n3})
+        if (!smooth235(n) || n > PCX_MAX_N)
+            return fail(PCX_E_SIZE, "pcx_geometry: grid size %d is not a product of 2, 3, 5 up to %d", n, PCX_MAX_N);
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(avec[i])) return fail(PCX_E_ARG, "pcx_geometry: non-finite lattice vector");
+    const double L1 = col_norm(avec, 0), L2 = col_norm(avec, 1), L3 = col_norm(avec, 2);
+    if (!(L1 > 0 && L2 > 0 && L3 > 0)) return fail(PCX_E_LATTICE, "pcx_geometry: zero lattice vector");
+    const double det = avec[0] * (avec[4] * avec[8] - avec[5] * avec[7]) -
+                       avec[1] * (avec[3] * avec[8] - avec[5] * avec[6]) +
+                       avec[2] * (avec[3] * avec[7] - avec[4] * avec[6]);
+    if (std::fabs(det) < 1e-12 * L1 * L2 * L3)
+        return fail(PCX_E_LATTICE, "pcx_geometry: lattice vectors are linearly dependent");
+    const double cgp = col_dot(avec, 0, 1) / (L1 * L2);
+    const double cbp = col_dot(avec, 0, 2) / (L1 * L3);
+    const double cap = col_dot(avec, 1, 2) / (L2 * L3);
+    const double dx = L1 / n1;
+    long m1, m2, m3;
+    int r1, r2, r3;
+    double cg, cb, ca;
+    if (cgp >= 0.0) {
+        r1 = 0;
+        m1 = round_half_up(L2 * cgp / dx);
+        cg = m1 * dx / L2;
+    } else {
+        r1 = 1;
+        m1 = round_half_up((L1 + L2 * cgp) / dx);
+        cg = (m1 * dx - L1) / L2;
+    }
+    if (std::fabs(cg) >= 1.0) return fail(PCX_E_LATTICE, "pcx_geometry: a2 does not fit in the cell along x");
+    const double sg = std::sqrt(1.0 - cg * cg);
+    const double l2 = L2 * sg;
+    const double dy = l2 / n2;
+    if (cbp >= 0.0) {
+        r2 = 0;
+        m2 = round_half_up(L3 * cbp / dx);
+        cb = m2 * dx / L3;
+    } else {
+        r2 = 1;
+        m2 = round_half_up((L1 + L3 * cbp) / dx);
+        cb = (m2 * dx - L1) / L3;
+    }
+    if (std::fabs(cb) > 1.0) return fail(PCX_E_LATTICE, "pcx_geometry: a3 does not fit in the cell along x");
+    const double dp = cap - cg * cb;
+    if (dp >= 0.0) {
+        r3 = 0;
+        m3 = round_half_up(L3 * dp / (dy * sg));
+        ca = m3 * dy * sg / L3 + cg * cb;
+    } else {
+        r3 = 1;
+        m3 = round_half_up((L2 * sg * sg + L3 * dp) / (dy * sg));
+        ca = (m3 * dy * sg - L2 * sg * sg) / L3 + cg * cb;
+    }
+    if (!(0 <= m1 && m1 <= n1 && 0 <= m2 && m2 <= n1 && 0 <= m3 && m3 <= n2))
+        return fail(PCX_E_LATTICE, "pcx_geometry: primitive-cell condition violated (m = %ld, %ld, %ld)", m1, m2, m3);
+    const long s1 = m1 - (long)r1 * n1, s2 = m2 - (long)r2 * n1, s3 = m3 - (long)r3 * n2;
+    if (std::labs(s3) >= n2) return fail(PCX_E_LATTICE, "pcx_geometry: a3 does not fit in the cell along y");
+    const double disc = 1.0 - cg * cg - cb * cb - ca * ca + 2.0 * cg * cb * ca;
+    if (!(disc > 0.0)) return fail(PCX_E_LATTICE, "pcx_geometry: corrected lattice is degenerate");
+    const double l3 = L3 * std::sqrt(disc) / sg;
+    pcx_geom g;
+    std::memset(&g, 0, sizeof(g));
+    g.n[0] = n1; g.n[1] = n2; g.n[2] = n3;
+    g.m[0] = (int)m1; g.m[1] = (int)m2; g.m[2] = (int)m3;
+    g.rho[0] = r1; g.rho[1] = r2; g.rho[2] = r3;
+    g.shift[0] = (int)s1; g.shift[1] = (int)s2; g.shift[2] = (int)s3;
+    g.delta[0] = dx; g.delta[1] = dy; g.delta[2] = l3 / n3;
+    const double R[9] = {L1, L2 * cg, L3 * cb, 0.0, L2 * sg, L3 * (ca - cg * cb) / sg, 0.0, 0.0, l3};
+    std::memcpy(g.avec_rot, R, sizeof(R));
+    g.cos_angles[0] = cg; g.cos_angles[1] = cb; g.cos_angles[2] = ca;
+    *out = g;
+    return PCX_OK;
+}
+
+extern "C" int pcx_kappa_from_bloch(const double avec[9], const double kvec[3], double kappa[3]) {
+    if (!avec || !kvec || !kappa) return fail(PCX_E_ARG, "pcx_kappa_from_bloch: null pointer");
+    for (int l = 0; l < 3; ++l) {
+        const double d = avec[0 * 3 + l] * kvec[0] + avec[1 * 3 + l] * kvec[1] + avec[2 * 3 + l] * kvec[2];
+        kappa[l] = d / (2.0 * M_PI);
+    }
+    return PCX_OK;
+}
+
+// ---------------------------------------------------------------- plans
+
+namespace pcx {
+
+static void host_twiddles(int n, std::vector<cx<double>>& out) {
+    out.resize(n);
+    for (int m = 0; m < n; ++m) {
+        // exp(2 pi i m / n) with the angle reduced to (-pi, pi]
+        long mm = m;
+        if (2 * mm > n) mm -= n;
+        const double a = 2.0 * M_PI * (double)mm / (double)n;
+        out[m].x = std::cos(a);
+        out[m].y = std::sin(a);
+    }
+}
+
+static hipError_t g_config_status = hipErrorNotReady;
+
+static int ensure_configured() {
+    if (g_config_status == hipErrorNotReady) {
+        g_config_status = configure_kernels();
+        if (g_config_status == hipSuccess) g_config_status = configure_block_kernels();
+    }
+    if (g_config_status != hipSuccess) return hip_fail(g_config_status, "kernel configuration");
+    return PCX_OK;
+}
+
+int Plan::grow(void** buf, size_t* have, size_t need) {
+    if (*have >= need) return PCX_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc(buf, need);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    *have = need;
+    return PCX_OK;
+}
+
+Grid Plan::grid(const double kappa[3]) const {
+    Grid g;
+    g.n1 = geom.n[0];
+    g.n2 = geom.n[1];
+    g.n3 = geom.n[2];
+    g.s1 = geom.shift[0];
+    g.s2 = geom.shift[1];
+    g.s3 = geom.shift[2];
+    for (int l = 0; l < 3; ++l) {
+        g.kap[l] = kappa[l];
+        g.dlt[l] = geom.delta[l];
+    }
+    g.fx = fx;
+    g.fy = fy;
+    g.fz = fz;
+    return g;
+}
+
+}  // namespace pcx
+
+extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_stream, pcx_plan** out) {
+    if (!g || !out) return fail(PCX_E_ARG, "pcx_plan_create: null pointer");
+    *out = nullptr;
+    if (max_vectors == 0) max_vectors = PCX_MAX_BLOCK;
+    if (max_vectors < 1 || max_vectors > 4096) return fail(PCX_E_ARG, "pcx_plan_create: max_vectors out of range");
+    FftPlan fx, fy, fz;
+    if (!make_fft_plan(g->n[0], &fx) || !make_fft_plan(g->n[1], &fy) || !make_fft_plan(g->n[2], &fz))
+        return fail(PCX_E_SIZE, "pcx_plan_create: grid sizes must be 2,3,5-smooth and <= %d", PCX_MAX_N);
+    for (int l = 0; l < 3; ++l)
+        if (!(g->delta[l] > 0) || !std::isfinite(g->delta[l])) return fail(PCX_E_ARG, "pcx_plan_create: bad delta");
+    if (std::abs(g->shift[2]) >= g->n[1]) return fail(PCX_E_LATTICE, "pcx_plan_create: bad shift");
+    // LDS budget of the plane kernels (FP64 must fit for the FP64 paths; checked per call)
+    int rc = ensure_configured();
+    if (rc) return rc;
+    Plan* p = new Plan();
+    p->geom = *g;
+    p->fx = fx;
+    p->fy = fy;
+    p->fz = fz;
+    p->n = (long)g->n[0] * g->n[1] * g->n[2];
+    p->max_vectors = max_vectors;
+    p->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    // twiddle tables
+    std::vector<cx<double>> h[3];
+    for (int a = 0; a < 3; ++a) host_twiddles(g->n[a], h[a]);
+    std::vector<cx<double>> half(g->n[2]);
+    for (int k = 0; k < g->n[2]; ++k) {
+        const double ang = M_PI * (double)k / (double)g->n[2];
+        half[k].x = std::cos(ang);
+        half[k].y = std::sin(ang);
+    }
+    size_t tot64 = 0, tot32 = 0;
+    for (int a = 0; a < 3; ++a) {
+        tot64 += h[a].size();
+        tot32 += h[a].size();
+    }
+    tot64 += half.size();
+    e = hipMalloc(&p->tables_mem, tot64 * sizeof(cx<double>) + tot32 * sizeof(cx<float>));
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMalloc tables");
+    }
+    cx<double>* d64 = (cx<double>*)p->tables_mem;
+    cx<float>* d32 = (cx<float>*)(d64 + tot64);
+    std::vector<cx<float>> f;
+    for (int a = 0; a < 3; ++a) {
+        p->tables.tw64[a] = d64;
+        p->tables.tw32[a] = d32;
+        (void)hipMemcpy(d64, h[a].data(), h[a].size() * sizeof(cx<double>), hipMemcpyHostToDevice);
+        f.resize(h[a].size());
+        for (size_t m = 0; m < h[a].size(); ++m) {
+            f[m].x = (float)h[a][m].x;
+            f[m].y = (float)h[a][m].y;
+        }
+        (void)hipMemcpy(d32, f.data(), f.size() * sizeof(cx<float>), hipMemcpyHostToDevice);
+        d64 += h[a].size();
+        d32 += h[a].size();
+    }
+    p->tables.halfz = d64;
+    e = hipMemcpy(d64, half.data(), half.size() * sizeof(cx<double>), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        pcx_plan_destroy((pcx_plan*)p);
+        return hip_fail(e, "hipMemcpy tables");
+    }
+    *out = (pcx_plan*)p;
+    return PCX_OK;
+}
+
+extern "C" void pcx_plan_destroy(pcx_plan* pp) {
+    Plan* p = (Plan*)pp;
+    if (!p) return;
+    void* bufs[] = {p->tables_mem, p->eps_mem, p->work, p->lob_mem, p->prec, p->gram_part, p->small_mem};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+extern "C" int pcx_plan_set_eps(pcx_plan* pp, const double* eps, int layout) {
+    Plan* p = (Plan*)pp;
+    if (!p || !eps) return fail(PCX_E_ARG, "pcx_plan_set_eps: null pointer");
+    if (layout != PCX_EPS_YEE3 && layout != PCX_EPS_VOXEL) return fail(PCX_E_ARG, "pcx_plan_set_eps: bad layout");
+    const long n = p->n;
+    std::vector<double> inv(3 * n), invn(3 * n);
+    std::vector<float> inv32(3 * n), invn32(3 * n);
+    double emin = 1e300, emax = -1e300;
+    for (long q = 0; q < 3 * n; ++q) {
+        const double e = layout == PCX_EPS_YEE3 ? eps[q] : eps[q % n];
+        if (!std::isfinite(e) || !(e > 0.0))
+            return fail(PCX_E_ARG, "pcx_plan_set_eps: permittivity must be finite and positive (index %ld)", q);
+        emin = std::min(emin, e);
+        emax = std::max(emax, e);
+        inv[q] = 1.0 / e;
+        invn[q] = 1.0 / (e * (double)n);
+        inv32[q] = (float)inv[q];
+        invn32[q] = (float)invn[q];
+    }
+    const size_t bytes = 3 * n * (2 * sizeof(double) + 2 * sizeof(float));
+    int rc = p->grow(&p->eps_mem, &p->eps_cap, bytes);
+    if (rc) return rc;
+    p->inv_eps64 = p->eps_mem;
+    p->inv_epsn64 = (double*)p->inv_eps64 + 3 * n;
+    p->inv_eps32 = (double*)p->inv_epsn64 + 3 * n;
+    p->inv_epsn32 = (float*)p->inv_eps32 + 3 * n;
+    hipError_t e;
+    if ((e = hipMemcpy(p->inv_eps64, inv.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->inv_epsn64, invn.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->inv_eps32, inv32.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->inv_epsn32, invn32.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "pcx_plan_set_eps: copy");
+    p->eps_min = emin;
+    p->eps_max = emax;
+    p->eps_set = true;
+    return PCX_OK;
+}
+
+namespace pcx {
+
+int Plan::check_fits(int precision) const {
+    const int fp64 = precision == PCX_FP64;
+    const size_t limit = 160 * 1024;
+    if (plane_kernel_lds(geom.n[1], geom.n[2], fp64) > limit || xline_kernel_lds(geom.n[0], fp64) > limit)
+        return fail(PCX_E_SIZE, "grid plane %dx%d does not fit in LDS at %s", geom.n[1], geom.n[2],
+                    fp64 ? "FP64" : "FP32");
+    return PCX_OK;
+}
+
+int Plan::ensure_work(int nvec) {
+    const size_t need = (size_t)nvec * 3 * n * sizeof(cx<double>);
+    return grow(&work, &work_cap, need);
+}
+
+int Plan::apply(int op, const double kappa[3], int precision, const void* in, void* out, int nvec) {
+    if (!in || !out || !kappa) return fail(PCX_E_ARG, "apply: null pointer");
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "apply: bad precision");
+    if (nvec < 1 || nvec > max_vectors) return fail(PCX_E_ARG, "apply: nvec %d outside [1, %d]", nvec, max_vectors);
+    for (int l = 0; l < 3; ++l)
+        if (!std::isfinite(kappa[l])) return fail(PCX_E_ARG, "apply: non-finite kappa");
+    if ((op == OP_AR || op == OP_EIGVEC) && !eps_set) return fail(PCX_E_ARG, "apply: permittivity not set");
+    int rc = check_fits(precision);
+    if (rc) return rc;
+    rc = ensure_work(nvec);
+    if (rc) return rc;
+    const Grid g = grid(kappa);
+    hipError_t e = hipSuccess;
+    if (precision == PCX_FP64) {
+        auto* w = (cx<double>*)work;
+        switch (op) {
+            case OP_AR: e = launch_apply_Ar<double>(g, tables, (const double*)inv_epsn64, (const cx<double>*)in,
+                                                    (cx<double>*)out, w, nvec, stream); break;
+            case OP_QS: e = launch_QS<double>(g, tables, nullptr, (const cx<double>*)in, (cx<double>*)out, w, nvec,
+                                              stream); break;
+            case OP_EIGVEC: e = launch_QS<double>(g, tables, (const double*)inv_eps64, (const cx<double>*)in,
+                                                  (cx<double>*)out, w, nvec, stream); break;
+            case OP_QSADJ: e = launch_QS_adjoint<double>(g, tables, (const cx<double>*)in, (cx<double>*)out, w, nvec,
+                                                         stream); break;
+        }
+    } else {
+        auto* w = (cx<float>*)work;
+        switch (op) {
+            case OP_AR: e = launch_apply_Ar<float>(g, tables, (const float*)inv_epsn32, (const cx<float>*)in,
+                                                   (cx<float>*)out, w, nvec, stream); break;
+            case OP_QS: e = launch_QS<float>(g, tables, nullptr, (const cx<float>*)in, (cx<float>*)out, w, nvec,
+                                             stream); break;
+            case OP_EIGVEC: e = launch_QS<float>(g, tables, (const float*)inv_eps32, (const cx<float>*)in,
+                                                 (cx<float>*)out, w, nvec, stream); break;
+            case OP_QSADJ: e = launch_QS_adjoint<float>(g, tables, (const cx<float>*)in, (cx<float>*)out, w, nvec,
+                                                        stream); break;
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "apply: kernel launch");
+    return PCX_OK;
+}
+
+}  // namespace pcx
+
+extern "C" int pcx_apply_Ar(pcx_plan* p, const double kappa[3], int precision, const void* y, void* z, int nvec) {
+    if (!p) return fail(PCX_E_ARG, "pcx_apply_Ar: null plan");
+    return ((Plan*)p)->apply(Plan::OP_AR, kappa, precision, y, z, nvec);
+}
+extern "C" int pcx_apply_QS(pcx_plan* p, const double kappa[3], int precision, const void* y, void* u, int nvec) {
+    if (!p) return fail(PCX_E_ARG, "pcx_apply_QS: null plan");
+    return ((Plan*)p)->apply(Plan::OP_QS, kappa, precision, y, u, nvec);
+}
+extern "C" int pcx_apply_QS_adjoint(pcx_plan* p, const double kappa[3], int precision, const void* u, void* z,
+                                    int nvec) {
+    if (!p) return fail(PCX_E_ARG, "pcx_apply_QS_adjoint: null plan");
+    return ((Plan*)p)->apply(Plan::OP_QSADJ, kappa, precision, u, z, nvec);
+}
+extern "C" int pcx_eigvec(pcx_plan* p, const double kappa[3], int precision, const void* y, void* x, int nvec) {
+    if (!p) return fail(PCX_E_ARG, "pcx_eigvec: null plan");
+    return ((Plan*)p)->apply(Plan::OP_EIGVEC, kappa, precision, y, x, nvec);
+}
+
+extern "C" int pcx_grad_eps(pcx_plan* pp, int nvec, const void* x, const double* weight, void* grad, int layout) {
+    Plan* p = (Plan*)pp;
+    if (!p || !x || !weight || !grad) return fail(PCX_E_ARG, "pcx_grad_eps: null pointer");
+    if (nvec < 1 || nvec > PCX_MAX_BLOCK) return fail(PCX_E_ARG, "pcx_grad_eps: nvec out of range");
+    if (layout != PCX_EPS_YEE3 && layout != PCX_EPS_VOXEL) return fail(PCX_E_ARG, "pcx_grad_eps: bad layout");
+    int rc = p->grow(&p->small_mem, &p->small_cap, 1 << 16);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(p->small_mem, weight, nvec * sizeof(double), hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_grad_eps: copy");
+    e = launch_grad((const cx<double>*)x, (const double*)p->small_mem, nvec, p->n, (double*)grad,
+                    layout == PCX_EPS_VOXEL, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_grad_eps: launch");
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_grad_eps: sync");
+    return PCX_OK;
+}

@@ -1,0 +1,58 @@
+// Host-side plan object shared by the ABI entry points and the eigensolver.
+#pragma once
+
+#include <vector>
+
+#include "pcx_internal.h"
+
+namespace pcx {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+bool make_fft_plan(int n, FftPlan* fp);
+
+struct Plan {
+    enum { OP_AR = 0, OP_QS = 1, OP_QSADJ = 2, OP_EIGVEC = 3 };
+
+    pcx_geom geom;
+    FftPlan fx, fy, fz;
+    long n = 0;
+    int max_vectors = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    void* tables_mem = nullptr;
+    DeviceTables tables;
+
+    // 1/eps (FP64), 1/(n eps) (FP64), 1/eps (FP32), 1/(n eps) (FP32): 3n each, one allocation
+    void* eps_mem = nullptr;
+    size_t eps_cap = 0;
+    void* inv_eps64 = nullptr;
+    void* inv_epsn64 = nullptr;
+    void* inv_eps32 = nullptr;
+    void* inv_epsn32 = nullptr;
+    bool eps_set = false;
+    double eps_min = 0, eps_max = 0;
+
+    // matvec workspace (3n complex per vector)
+    void* work = nullptr;
+    size_t work_cap = 0;
+
+    // eigensolver storage
+    void* lob_mem = nullptr;
+    size_t lob_cap = 0;
+    void* prec = nullptr;
+    size_t prec_cap = 0;
+    void* gram_part = nullptr;
+    size_t gram_part_cap = 0;
+    void* small_mem = nullptr;
+    size_t small_cap = 0;
+
+    int grow(void** buf, size_t* have, size_t need);
+    Grid grid(const double kappa[3]) const;
+    int check_fits(int precision) const;
+    int ensure_work(int nvec);
+    int apply(int op, const double kappa[3], int precision, const void* in, void* out, int nvec);
+};
+
+}  // namespace pcx

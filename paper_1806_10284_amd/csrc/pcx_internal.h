@@ -1,0 +1,113 @@
+// Internal declarations shared by the HIP kernels and the host-side plan/solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pcx.h"
+
+namespace pcx {
+
+constexpr int kThreads = 256;      // work-group size of every FFT kernel
+constexpr int kMaxPasses = 8;
+constexpr double kMixTau = 1e-3;   // switch to the fallback range basis below Lambda_p^2 / Lambda_q
+
+// Mixed-radix Stockham factorisation of one axis (radices 8, 4, 2, 3, 5).
+struct FftPlan {
+    int n;
+    int npass;
+    int rad[kMaxPasses];
+};
+
+// Everything a matvec kernel needs about the grid and the Bloch phases.
+struct Grid {
+    int n1, n2, n3;
+    int s1, s2, s3;          // signed shifts of the lattice rows in grid units
+    double kap[3];           // kappa_l = k . a_l
+    double dlt[3];           // mesh sizes
+    FftPlan fx, fy, fz;
+};
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+    R x, y;
+};
+
+// device-side tables owned by a plan: twiddle LUTs exp(+2 pi i m / N) for the three axes,
+// in both precisions, and the half-turn table exp(i pi k / n3) in FP64.
+struct DeviceTables {
+    cx<double>* tw64[3];
+    cx<float>* tw32[3];
+    cx<double>* halfz;
+};
+
+// ---- launchers (pcx_fft.hip) ----
+// z = A_r y for nvec vectors; t is a 3n-per-vector workspace.
+template <typename R>
+hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y,
+                           cx<R>* z, cx<R>* t, int nvec, hipStream_t st);
+// u = (I3 (x) T)(W y) (scale_eps == nullptr) or x = B^{-1}(I3 (x) T)(W y) (scale_eps = 1/eps)
+template <typename R>
+hipError_t launch_QS(const Grid& g, const DeviceTables& tb, const R* inv_eps, const cx<R>* y, cx<R>* u,
+                     cx<R>* t, int nvec, hipStream_t st);
+// z = W^H (I3 (x) T*) u
+template <typename R>
+hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>* u, cx<R>* z, cx<R>* t,
+                             int nvec, hipStream_t st);
+// 1/Lambda_q per mode (0 at the masked mode), FP64, n values
+hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st);
+// set per-kernel LDS limits once per process
+hipError_t configure_kernels();
+
+// ---- block operations (pcx_block.hip) ----
+// A set of vectors of length N given as up to 4 segments of contiguous columns (column stride N).
+struct ColSet {
+    void* ptr[4];
+    int ncols[4];
+    int nseg;
+    __host__ __device__ int total() const { return ncols[0] + ncols[1] + ncols[2] + ncols[3]; }
+};
+inline ColSet colset(void* p0, int c0, void* p1 = nullptr, int c1 = 0, void* p2 = nullptr, int c2 = 0) {
+    ColSet s;
+    s.ptr[0] = p0; s.ncols[0] = c0;
+    s.ptr[1] = p1; s.ncols[1] = c1;
+    s.ptr[2] = p2; s.ncols[2] = c2;
+    s.ptr[3] = nullptr; s.ncols[3] = 0;
+    s.nseg = c2 ? 3 : (c1 ? 2 : 1);
+    return s;
+}
+
+// out (ka x kb, row-major) = A^H B with FP64 accumulation; part: workspace of nchunk * ka * kb complex.
+template <typename R>
+hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* part, int nchunk, cx<double>* out,
+                       hipStream_t st);
+// Y[:, m] = sum_k S[:, k] C[k, m]  (C: ks x m row-major FP64 complex, device).  Y may alias S
+// column-for-column (every thread reads its whole row before writing it).
+template <typename R>
+hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st);
+// R_j = AX_j - theta_j X_j ; W_j = prec .* R_j (prec: n doubles, applied to both y-blocks; nullptr = identity);
+// out[j] = ||R_j||^2 (FP64).
+template <typename R>
+hipError_t launch_residual(const ColSet& X, const ColSet& AX, const double* theta, const double* prec, long n,
+                           const ColSet& W, double* part, int nchunk, double* out, hipStream_t st);
+// precision conversion of a contiguous complex array
+hipError_t launch_convert(const cx<float>* in, cx<double>* out, long count, hipStream_t st);
+hipError_t launch_convert(const cx<double>* in, cx<float>* out, long count, hipStream_t st);
+// zero the masked mode: y *= (prec != 0) on both y-blocks of nvec vectors
+template <typename R>
+hipError_t launch_mask(cx<R>* y, const double* prec, long n, int nvec, hipStream_t st);
+// grad[p] = -sum_t w_t |x_t(p)|^2 ; voxel: summed over the 3 components.  w: device, nvec doubles.
+hipError_t launch_grad(const cx<double>* x, const double* w, int nvec, long n, double* grad, int voxel,
+                       hipStream_t st);
+
+// seeded complex normal deviates (counter-based: element e of stream `seed`)
+template <typename R>
+hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, hipStream_t st);
+hipError_t configure_block_kernels();
+
+// sizes used by the plan to reserve LDS and workspaces
+size_t plane_kernel_lds(int n2, int n3, int fp64);
+size_t xline_kernel_lds(int n1, int fp64);
+int xline_kernel_tile(int n1);
+
+}  // namespace pcx

@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark: nullspace-free matvecs/s, HBM GB/s against the MI355X peak, and seconds per k-point.
+
+Workload: FCC lattice with the diamond structure (dielectric spheres r = 0.12a at the two basis
+sites joined by rods r = 0.11a, eps 13 in air), grid 64^3 (n = 262144, A_r of dimension 2n),
+one wave vector at the X point, the 10 smallest positive eigenvalues, FP32 matvecs with FP64
+refinement (the default mode; --mode fp64 runs the plain FP64 path).  Synthetic, seeded input;
+everything is resident on the device before the timed region.
+
+One step = one complete k-point solve (pcx_solve): preconditioner, LOBPCG iterations (A_r block
+matvecs, FP64 Gram products, host Rayleigh-Ritz), refinement and the eigenvalues on the host.
+
+Printed (one JSON line): value = A_r applications per second over the timed solves; the
+roofline of the dominant matvec kernel measured with HIP events on a 32-vector block (working
+set ~ 450 MB, larger than the 256 MB last-level cache); and the FP64 CPU oracle's matvec rate
+on this host as a reference.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--mode fp32_refine|fp64|fp32]
+                    [--no-cpu-baseline] [--profile-kernels]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_GRID = (64, 64, 64)
+NEV = 10
+ROOF_VECTORS = 32
+
+
+def kernel_bytes_per_vector(n: int, fp64: bool) -> dict:
+    """Algorithmic HBM bytes per vector for each of the three A_r kernels (complex c, real r):
+    plane forward reads y (2c) writes t (3c); x-line reads t (3c) and 1/eps (3r) and writes t (3c);
+    plane adjoint reads t (3c) writes z (2c).  Total 16c + 3r per point."""
+    c = 16 if fp64 else 8
+    r = 8 if fp64 else 4
+    return {"plane_fwd": 5 * c * n, "xline": 6 * c * n + 3 * r * n, "plane_adj": 5 * c * n}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1806_10284_amd", "csrc", "pcx_fft.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(dominant: str, fp64: bool):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_fcc64.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    key = f"{dominant}_{'fp64' if fp64 else 'fp32'}"
+    ent = d.get("kernels", {}).get(key)
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def setup(torch, max_vectors: int):
+    import pcx_synth as S
+    from paper_1806_10284_amd import Plan, pcx_geometry, pcx_kappa_from_bloch
+    g = pcx_geometry(S.FCC, *N_GRID)
+    eps = S.sample_yee(S.FCC, N_GRID, tuple(g.shift), S.diamond_shapes(), 13.0, 1.0)
+    kappa = pcx_kappa_from_bloch(S.FCC, S.FCC_POINTS["X"])
+    plan = Plan(g, max_vectors=max_vectors)
+    plan.pcx_plan_set_eps(eps)
+    return plan, kappa, eps, g
+
+
+def roofline_block(torch, plan, kappa, fp64: bool, reps: int):
+    import pcx_synth as S
+    n = plan.n
+    dt = torch.complex128 if fp64 else torch.complex64
+    y = torch.from_numpy(np.ascontiguousarray(S.random_block(3, 2 * n, ROOF_VECTORS).T)).to(dtype=dt, device="cuda")
+    z = torch.empty_like(y)
+    plan.pcx_time_Ar_kernels(kappa, y, z, reps=2)          # warm-up
+    ms = plan.pcx_time_Ar_kernels(kappa, y, z, reps=reps)
+    names = ["plane_fwd", "xline", "plane_adj"]
+    per = kernel_bytes_per_vector(n, fp64)
+    out = {}
+    for nm, t in zip(names, ms):
+        b = per[nm] * ROOF_VECTORS
+        out[nm] = {"ms": t, "bytes": b, "gbs": b / (t * 1e-3) / 1e9}
+    tot_ms = sum(ms)
+    tot_b = sum(per.values()) * ROOF_VECTORS
+    return out, {"ms": tot_ms, "bytes": tot_b, "gbs": tot_b / (tot_ms * 1e-3) / 1e9,
+                 "matvecs_per_s": ROOF_VECTORS / (tot_ms * 1e-3)}
+
+
+def cpu_baseline(eps, kappa, budget_s: float = 12.0):
+    """The FP64 oracle's A_r application (numpy FFT route) on this host, same workload."""
+    import pcx_synth as S
+    from oracle.geometry import lattice_geometry
+    from oracle.nfsep import Ar_apply
+    from oracle.spectral import spectrum
+    g = lattice_geometry(S.FCC, *N_GRID)
+    spec = spectrum(g, kappa)
+    y = S.random_block(4, 2 * g.npts, 1)[:, 0]
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        Ar_apply(spec, eps, y)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": done / el, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} FP64 A_r applications (numpy FFT, single-threaded) on FCC diamond 64^3 at X, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="fp32_refine", choices=["fp32_refine", "fp64", "fp32"])
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run the 32-vector A_r block (and a calibration copy) for rocprofv3 counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this solver is single-device (k-points shard across GPUs "
+              "without communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_10284_amd import PCX_MODE_FP32, PCX_MODE_FP32_REFINE, PCX_MODE_FP64
+    torch.cuda.set_device(0)
+    mode = {"fp32_refine": PCX_MODE_FP32_REFINE, "fp64": PCX_MODE_FP64, "fp32": PCX_MODE_FP32}[args.mode]
+    plan, kappa, eps, g = setup(torch, max_vectors=ROOF_VECTORS)
+    print(f"[bench] setup done: FCC diamond {N_GRID}, kappa {kappa.tolist()}", file=sys.stderr, flush=True)
+
+    if args.profile_kernels:
+        for fp64 in (False, True):
+            roofline_block(torch, plan, kappa, fp64, reps=5)
+            print(f"[bench] profiled block matvec fp64={fp64}", file=sys.stderr, flush=True)
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 5 x 512 MiB", file=sys.stderr, flush=True)
+        return
+
+    solve_kw = dict(mode=mode, tol=1e-9, want_y=False)
+    for w in range(args.warmup):
+        lam, _, _, st = plan.pcx_solve(kappa, NEV, **solve_kw)
+        print(f"[bench] warmup {w}: {st.iterations} it, {st.matvecs} matvecs, {st.seconds:.3f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    matvecs = matvecs32 = 0
+    tm = 0.0
+    iters = []
+    for s in range(args.steps):
+        lam, _, _, st = plan.pcx_solve(kappa, NEV, **solve_kw)
+        matvecs += st.matvecs
+        matvecs32 += st.matvecs_fp32
+        tm += st.seconds_matvec
+        iters.append(st.iterations)
+        print(f"[bench] step {s}: {st.iterations} it ({st.iterations_fp32} fp32), {st.matvecs} matvecs, "
+              f"{st.seconds:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    el = t1 - t0
+    value = matvecs / el
+    n = plan.n
+    per32 = sum(kernel_bytes_per_vector(n, False).values())
+    per64 = sum(kernel_bytes_per_vector(n, True).values())
+    solve_gbs = (matvecs32 * per32 + (matvecs - matvecs32) * per64) / el / 1e9
+
+    fp64_roof = args.mode == "fp64"
+    kern, tot = roofline_block(torch, plan, kappa, fp64_roof, args.reps)
+    dominant = max(kern, key=lambda k: kern[k]["ms"])
+    dk = kern[dominant]
+    traffic = load_traffic(dominant, fp64_roof)
+    print(f"[bench] roofline block: {json.dumps(kern)}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(eps, kappa)
+        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "nullspace-free matvecs/s + HBM GB/s vs peak; s per k-point, 10 bands at 64^3",
+        "value": value,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32_refine": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.mode],
+        "data": "synthetic",
+        "config": {"workload": "FCC diamond 64^3 (spheres r=0.12a, rods r=0.11a, eps 13/1), X point, "
+                               "10 smallest positive eigenvalues",
+                   "grid": list(N_GRID), "nev": NEV, "mode": args.mode, "kappa": kappa.tolist()},
+        "s_per_kpoint": el / args.steps,
+        "solve": {"iterations": iters, "matvecs_per_solve": matvecs / args.steps,
+                  "fp32_matvec_fraction": matvecs32 / max(matvecs, 1),
+                  "matvec_time_fraction": tm / el, "matvec_gbs_in_solve": solve_gbs,
+                  "lambda": [float(x) for x in lam],
+                  "omega_over_2pi": [math.sqrt(max(x, 0)) / (2 * math.pi) for x in lam]},
+        "block_matvec": {"vectors": ROOF_VECTORS, "precision": "fp64" if fp64_roof else "fp32",
+                         "matvecs_per_s": tot["matvecs_per_s"], "gbs": tot["gbs"],
+                         "frac_of_peak": tot["gbs"] / HBM_PEAK_GBS,
+                         "kernels": {k: {"ms": v["ms"], "gbs": v["gbs"]} for k, v in kern.items()}},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": dk["bytes"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -111,7 +111,7 @@ int pcx_eigvec(pcx_plan *p, const double kappa[3], int precision, const void *y,
 
 typedef struct pcx_opts {
     int mode;            /* PCX_MODE_FP64 | PCX_MODE_FP32_REFINE | PCX_MODE_FP32 */
-    int block;           /* LOBPCG block size >= nev (0: nev + max(2, nev/4)) */
+    int block;           /* LOBPCG block size >= nev (0: nev + max(4, (nev+1)/2)) */
     int max_iter;        /* total iterations over both phases */
     double tol;          /* converged when ||A_r y - lambda y|| <= tol * lambda (||y|| = 1) */
     double tol_fp32;     /* FP32_REFINE: leave the FP32 phase at this residual */
@@ -149,6 +149,13 @@ int pcx_solve(pcx_plan *p, const double kappa[3], int nev, const pcx_opts *opts,
  * doubles, grad: device doubles, 3n (PCX_EPS_YEE3) or n summed over the three
  * components (PCX_EPS_VOXEL).  Overwrites grad. */
 int pcx_grad_eps(pcx_plan *p, int nvec, const void *x, const double *weight, void *grad, int layout);
+
+/* Measurement hook: runs the three kernels of pcx_apply_Ar (plane forward, x-line, plane
+ * adjoint) `reps` times on the plan's stream with HIP events around each launch and returns
+ * their mean durations in milliseconds in ms_out[0..2].  Same arguments and effect on z as
+ * pcx_apply_Ar.  Synchronises the stream. */
+int pcx_time_Ar_kernels(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z,
+                        int nvec, int reps, double ms_out[3]);
 
 const char *pcx_last_error(void);
 

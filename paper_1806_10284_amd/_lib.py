@@ -70,6 +70,8 @@ _SIGS = [
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PcxStats)]),
     ("pcx_grad_eps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int]),
+    ("pcx_time_Ar_kernels", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int, ctypes.c_int, c_double3]),
     ("pcx_last_error", ctypes.c_char_p, []),
 ]
 

@@ -141,6 +141,16 @@ class Plan:
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_eigvec, kappa, precision, y, x, 2 * self.n, 3 * self.n)
 
+    def pcx_time_Ar_kernels(self, kappa, y, z, reps: int = 10):
+        """Mean milliseconds per launch of the three A_r kernels (HIP events on the plan's stream)."""
+        precision = self._prec_of(y)
+        nv = self._check_block(y, 2 * self.n, precision, "y")
+        self._check_block(z, 2 * self.n, precision, "z")
+        ms = L.c_double3()
+        L.check(self._lib.pcx_time_Ar_kernels(self._ptr, _kappa3(kappa), int(precision), ctypes.c_void_p(y.data_ptr()),
+                                              ctypes.c_void_p(z.data_ptr()), nv, int(reps), ms))
+        return list(ms)
+
     @staticmethod
     def _prec_of(t):
         torch = _torch()

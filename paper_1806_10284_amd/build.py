@@ -42,9 +42,25 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
+def _headers():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    inc = os.path.join(ROOT, "include")
+    hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    return hs
+
+
+def _stale(src: str, obj: str, force: bool) -> bool:
+    if force or not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(x) > t for x in [src] + _headers() + [os.path.abspath(__file__)])
+
+
+def _compile(src: str, force: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not _stale(src, obj, force):
+        return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     cmd = [hipcc()] + COMMON + lang + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,11 +71,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
+def build(jobs: int | None = None, force: bool = False) -> str:
+    """Compiles every source whose object is older than it (or than any header) and links."""
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4) // 2))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -73,4 +90,4 @@ if __name__ == "__main__":
     j = None
     if "--jobs" in sys.argv:
         j = int(sys.argv[sys.argv.index("--jobs") + 1])
-    print(build(j))
+    print(build(j, force="--force" in sys.argv))

@@ -7,7 +7,7 @@ namespace pcx {
 
 #define DEV __device__ __forceinline__
 
-constexpr int kMaxCols = 4 * PCX_MAX_BLOCK;
+constexpr int kMaxCols = 6 * PCX_MAX_BLOCK;
 constexpr int kGramRows = 32;      // rows staged per sub-tile
 constexpr int kBlk = 4;            // 4 x 4 register tile of Gram entries per thread
 
@@ -23,7 +23,7 @@ DEV cx<double> to64(cx<R> a) {
 template <typename R>
 DEV R* col_ptr(const ColSet& S, int c, long N) {
     int off = 0;
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < kMaxSeg; ++s) {
         if (c < off + S.ncols[s]) return (R*)S.ptr[s] + (long)(c - off) * N;
         off += S.ncols[s];
     }
@@ -350,12 +350,12 @@ DEV unsigned long long splitmix64(unsigned long long x) {
 }
 
 template <typename R>
-__global__ void k_random(cx<R>* __restrict__ y, long count, unsigned long long seed) {
+__global__ void k_random(cx<R>* __restrict__ y, long count, unsigned long long seed, double scale) {
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
         const unsigned long long h = splitmix64(seed ^ splitmix64((unsigned long long)e));
         const double u1 = ((double)(h >> 11) + 0.5) * (1.0 / 9007199254740992.0);
         const double u2 = ((double)(splitmix64(h) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-        const double rad = sqrt(-2.0 * log(u1));
+        const double rad = scale * sqrt(-2.0 * log(u1));
         double s, c;
         sincospi(2.0 * u2, &s, &c);
         cx<R> o;
@@ -366,8 +366,8 @@ __global__ void k_random(cx<R>* __restrict__ y, long count, unsigned long long s
 }
 
 template <typename R>
-hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, hipStream_t st) {
-    hipLaunchKernelGGL((k_random<R>), dim3(grid_for(count)), dim3(256), 0, st, y, count, seed);
+hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double scale, hipStream_t st) {
+    hipLaunchKernelGGL((k_random<R>), dim3(grid_for(count)), dim3(256), 0, st, y, count, seed, scale);
     return hipGetLastError();
 }
 
@@ -378,8 +378,8 @@ hipError_t configure_block_kernels() {
     return hipFuncSetAttribute((const void*)k_gram<double>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
 }
 
-template hipError_t launch_random<float>(cx<float>*, long, unsigned long long, hipStream_t);
-template hipError_t launch_random<double>(cx<double>*, long, unsigned long long, hipStream_t);
+template hipError_t launch_random<float>(cx<float>*, long, unsigned long long, double, hipStream_t);
+template hipError_t launch_random<double>(cx<double>*, long, unsigned long long, double, hipStream_t);
 template hipError_t launch_gram<float>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t);
 template hipError_t launch_gram<double>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t);
 template hipError_t launch_combine<float>(const ColSet&, const cx<double>*, const ColSet&, long, hipStream_t);

@@ -695,6 +695,34 @@ hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>*
     return plane_adj<R>(g, tb, t, z, nvec, st);
 }
 
+template <typename R>
+hipError_t time_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y, cx<R>* z,
+                         cx<R>* t, int nvec, int reps, hipStream_t st, double ms[3]) {
+    hipEvent_t ev[4];
+    for (int q = 0; q < 4; ++q)
+        if (hipEventCreate(&ev[q]) != hipSuccess) return hipErrorOutOfMemory;
+    double acc[3] = {0, 0, 0};
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        (void)hipEventRecord(ev[0], st);
+        e = plane_fwd<R>(g, tb, y, t, nvec, st);
+        (void)hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
+        (void)hipEventRecord(ev[2], st);
+        if (e == hipSuccess) e = plane_adj<R>(g, tb, t, z, nvec, st);
+        (void)hipEventRecord(ev[3], st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+            float f = 0.0f;
+            e = hipEventElapsedTime(&f, ev[q], ev[q + 1]);
+            acc[q] += f;
+        }
+    }
+    for (int q = 0; q < 4; ++q) (void)hipEventDestroy(ev[q]);
+    for (int q = 0; q < 3; ++q) ms[q] = reps > 0 ? acc[q] / reps : 0.0;
+    return e;
+}
+
 hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st) {
     const long n = (long)g.n1 * g.n2 * g.n3;
     int blocks = (int)((n + 255) / 256);
@@ -754,6 +782,10 @@ template hipError_t launch_apply_Ar<float>(const Grid&, const DeviceTables&, con
                                            cx<float>*, cx<float>*, int, hipStream_t);
 template hipError_t launch_apply_Ar<double>(const Grid&, const DeviceTables&, const double*, const cx<double>*,
                                             cx<double>*, cx<double>*, int, hipStream_t);
+template hipError_t time_apply_Ar<float>(const Grid&, const DeviceTables&, const float*, const cx<float>*,
+                                         cx<float>*, cx<float>*, int, int, hipStream_t, double*);
+template hipError_t time_apply_Ar<double>(const Grid&, const DeviceTables&, const double*, const cx<double>*,
+                                          cx<double>*, cx<double>*, int, int, hipStream_t, double*);
 template hipError_t launch_QS<float>(const Grid&, const DeviceTables&, const float*, const cx<float>*, cx<float>*,
                                      cx<float>*, int, hipStream_t);
 template hipError_t launch_QS<double>(const Grid&, const DeviceTables&, const double*, const cx<double>*,

@@ -296,6 +296,7 @@ extern "C" void pcx_plan_destroy(pcx_plan* pp) {
     void* bufs[] = {p->tables_mem, p->eps_mem, p->work, p->lob_mem, p->prec, p->gram_part, p->small_mem};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
 }
 
@@ -413,6 +414,28 @@ extern "C" int pcx_apply_QS_adjoint(pcx_plan* p, const double kappa[3], int prec
 extern "C" int pcx_eigvec(pcx_plan* p, const double kappa[3], int precision, const void* y, void* x, int nvec) {
     if (!p) return fail(PCX_E_ARG, "pcx_eigvec: null plan");
     return ((Plan*)p)->apply(Plan::OP_EIGVEC, kappa, precision, y, x, nvec);
+}
+
+extern "C" int pcx_time_Ar_kernels(pcx_plan* pp, const double kappa[3], int precision, const void* y, void* z,
+                                   int nvec, int reps, double ms_out[3]) {
+    Plan* p = (Plan*)pp;
+    if (!p || !kappa || !y || !z || !ms_out) return fail(PCX_E_ARG, "pcx_time_Ar_kernels: null pointer");
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "pcx_time_Ar_kernels: bad precision");
+    if (nvec < 1 || nvec > p->max_vectors || reps < 1) return fail(PCX_E_ARG, "pcx_time_Ar_kernels: bad nvec/reps");
+    if (!p->eps_set) return fail(PCX_E_ARG, "pcx_time_Ar_kernels: permittivity not set");
+    int rc = p->check_fits(precision);
+    if (rc) return rc;
+    if ((rc = p->ensure_work(nvec))) return rc;
+    const Grid g = p->grid(kappa);
+    hipError_t e;
+    if (precision == PCX_FP64)
+        e = time_apply_Ar<double>(g, p->tables, (const double*)p->inv_epsn64, (const cx<double>*)y, (cx<double>*)z,
+                                  (cx<double>*)p->work, nvec, reps, p->stream, ms_out);
+    else
+        e = time_apply_Ar<float>(g, p->tables, (const float*)p->inv_epsn32, (const cx<float>*)y, (cx<float>*)z,
+                                 (cx<float>*)p->work, nvec, reps, p->stream, ms_out);
+    if (e != hipSuccess) return hip_fail(e, "pcx_time_Ar_kernels");
+    return PCX_OK;
 }
 
 extern "C" int pcx_grad_eps(pcx_plan* pp, int nvec, const void* x, const double* weight, void* grad, int layout) {

@@ -47,6 +47,8 @@ struct Plan {
     size_t gram_part_cap = 0;
     void* small_mem = nullptr;
     size_t small_cap = 0;
+    void* pinned = nullptr;          // pinned host staging for coefficient uploads
+    size_t pinned_cap = 0;
 
     int grow(void** buf, size_t* have, size_t need);
     Grid grid(const double kappa[3]) const;

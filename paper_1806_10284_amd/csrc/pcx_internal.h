@@ -46,6 +46,11 @@ struct DeviceTables {
 template <typename R>
 hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y,
                            cx<R>* z, cx<R>* t, int nvec, hipStream_t st);
+// the three launches of launch_apply_Ar, `reps` times, with HIP events around each launch on `st`;
+// ms[0..2] = mean milliseconds of the plane-forward, x-line and plane-adjoint kernels
+template <typename R>
+hipError_t time_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y, cx<R>* z,
+                         cx<R>* t, int nvec, int reps, hipStream_t st, double ms[3]);
 // u = (I3 (x) T)(W y) (scale_eps == nullptr) or x = B^{-1}(I3 (x) T)(W y) (scale_eps = 1/eps)
 template <typename R>
 hipError_t launch_QS(const Grid& g, const DeviceTables& tb, const R* inv_eps, const cx<R>* y, cx<R>* u,
@@ -60,20 +65,39 @@ hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* ou
 hipError_t configure_kernels();
 
 // ---- block operations (pcx_block.hip) ----
-// A set of vectors of length N given as up to 4 segments of contiguous columns (column stride N).
+// A set of vectors of length N given as up to kMaxSeg runs of contiguous columns (column stride N).
+constexpr int kMaxSeg = 6;
 struct ColSet {
-    void* ptr[4];
-    int ncols[4];
-    int nseg;
-    __host__ __device__ int total() const { return ncols[0] + ncols[1] + ncols[2] + ncols[3]; }
+    void* ptr[kMaxSeg];
+    int ncols[kMaxSeg];
+    __host__ __device__ int total() const {
+        int t = 0;
+        for (int s = 0; s < kMaxSeg; ++s) t += ncols[s];
+        return t;
+    }
 };
 inline ColSet colset(void* p0, int c0, void* p1 = nullptr, int c1 = 0, void* p2 = nullptr, int c2 = 0) {
     ColSet s;
+    for (int q = 0; q < kMaxSeg; ++q) {
+        s.ptr[q] = nullptr;
+        s.ncols[q] = 0;
+    }
     s.ptr[0] = p0; s.ncols[0] = c0;
     s.ptr[1] = p1; s.ncols[1] = c1;
     s.ptr[2] = p2; s.ncols[2] = c2;
-    s.ptr[3] = nullptr; s.ncols[3] = 0;
-    s.nseg = c2 ? 3 : (c1 ? 2 : 1);
+    return s;
+}
+// [A | B]: the runs of A followed by the runs of B (at most kMaxSeg non-empty runs in total)
+inline ColSet concat(const ColSet& A, const ColSet& B) {
+    ColSet s = colset(nullptr, 0);
+    int q = 0;
+    for (const ColSet* x : {&A, &B})
+        for (int r = 0; r < kMaxSeg; ++r)
+            if (x->ncols[r] > 0 && q < kMaxSeg) {
+                s.ptr[q] = x->ptr[r];
+                s.ncols[q] = x->ncols[r];
+                ++q;
+            }
     return s;
 }
 
@@ -81,8 +105,8 @@ inline ColSet colset(void* p0, int c0, void* p1 = nullptr, int c1 = 0, void* p2 
 template <typename R>
 hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* part, int nchunk, cx<double>* out,
                        hipStream_t st);
-// Y[:, m] = sum_k S[:, k] C[k, m]  (C: ks x m row-major FP64 complex, device).  Y may alias S
-// column-for-column (every thread reads its whole row before writing it).
+// Y[:, m] = sum_k S[:, k] C[k, m]  (C: ks x m row-major FP64 complex, device).  Y must not
+// overlap S.
 template <typename R>
 hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st);
 // R_j = AX_j - theta_j X_j ; W_j = prec .* R_j (prec: n doubles, applied to both y-blocks; nullptr = identity);
@@ -100,9 +124,9 @@ hipError_t launch_mask(cx<R>* y, const double* prec, long n, int nvec, hipStream
 hipError_t launch_grad(const cx<double>* x, const double* w, int nvec, long n, double* grad, int voxel,
                        hipStream_t st);
 
-// seeded complex normal deviates (counter-based: element e of stream `seed`)
+// seeded complex normal deviates times `scale` (counter-based: element e of stream `seed`)
 template <typename R>
-hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, hipStream_t st);
+hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double scale, hipStream_t st);
 hipError_t configure_block_kernels();
 
 // sizes used by the plan to reserve LDS and workspaces

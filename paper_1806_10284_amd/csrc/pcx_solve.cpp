@@ -14,155 +14,14 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <type_traits>
 #include <vector>
 
+#include "pcx_dense.h"
 #include "pcx_host.h"
 
 namespace pcx {
-
-using zc = std::complex<double>;
-
-// ---------------------------------------------------------------- small dense linear algebra (row-major)
-
-// Hermitian eigen-decomposition by cyclic Jacobi: A = V diag(w) V^H, w ascending.
-static void jacobi_eigh(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>& V) {
-    V.assign((size_t)k * k, zc(0, 0));
-    for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
-    for (int i = 0; i < k; ++i) A[(size_t)i * k + i] = zc(A[(size_t)i * k + i].real(), 0.0);
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int p = 0; p < k; ++p) {
-            dia += std::norm(A[(size_t)p * k + p]);
-            for (int q = p + 1; q < k; ++q) off += std::norm(A[(size_t)p * k + q]);
-        }
-        if (off <= 1e-32 * dia || off == 0.0) break;
-        for (int p = 0; p < k; ++p) {
-            for (int q = p + 1; q < k; ++q) {
-                const zc apq = A[(size_t)p * k + q];
-                const double mag = std::abs(apq);
-                if (mag == 0.0) continue;
-                const double app = A[(size_t)p * k + p].real(), aqq = A[(size_t)q * k + q].real();
-                const zc e = apq / mag;
-                const double th = 0.5 * std::atan2(2.0 * mag, aqq - app);
-                const double c = std::cos(th), s = std::sin(th);
-                const zc eb = std::conj(e);
-                // A <- A G with G = [[c, s], [-s conj(e), c conj(e)]] on columns p, q
-                for (int r = 0; r < k; ++r) {
-                    const zc x = A[(size_t)r * k + p], y = A[(size_t)r * k + q];
-                    A[(size_t)r * k + p] = c * x - s * eb * y;
-                    A[(size_t)r * k + q] = s * x + c * eb * y;
-                }
-                // A <- G^H A on rows p, q
-                for (int r = 0; r < k; ++r) {
-                    const zc x = A[(size_t)p * k + r], y = A[(size_t)q * k + r];
-                    A[(size_t)p * k + r] = c * x - s * e * y;
-                    A[(size_t)q * k + r] = s * x + c * e * y;
-                }
-                A[(size_t)p * k + q] = 0.0;
-                A[(size_t)q * k + p] = 0.0;
-                A[(size_t)p * k + p] = zc(A[(size_t)p * k + p].real(), 0.0);
-                A[(size_t)q * k + q] = zc(A[(size_t)q * k + q].real(), 0.0);
-                for (int r = 0; r < k; ++r) {
-                    const zc x = V[(size_t)r * k + p], y = V[(size_t)r * k + q];
-                    V[(size_t)r * k + p] = c * x - s * eb * y;
-                    V[(size_t)r * k + q] = s * x + c * eb * y;
-                }
-            }
-        }
-    }
-    std::vector<int> idx(k);
-    for (int i = 0; i < k; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(),
-              [&](int a, int b) { return A[(size_t)a * k + a].real() < A[(size_t)b * k + b].real(); });
-    w.resize(k);
-    std::vector<zc> Vs((size_t)k * k);
-    for (int c = 0; c < k; ++c) {
-        w[c] = A[(size_t)idx[c] * k + idx[c]].real();
-        for (int r = 0; r < k; ++r) Vs[(size_t)r * k + c] = V[(size_t)r * k + idx[c]];
-    }
-    V.swap(Vs);
-}
-
-// G = L L^H, L lower triangular; false if a pivot is not safely positive.
-static bool cholesky(int k, const std::vector<zc>& G, std::vector<zc>& L, double rel_tol) {
-    L.assign((size_t)k * k, zc(0, 0));
-    double dmax = 0.0;
-    for (int i = 0; i < k; ++i) dmax = std::max(dmax, G[(size_t)i * k + i].real());
-    if (!(dmax > 0.0)) return false;
-    for (int j = 0; j < k; ++j) {
-        double d = G[(size_t)j * k + j].real();
-        for (int m = 0; m < j; ++m) d -= std::norm(L[(size_t)j * k + m]);
-        if (!(d > rel_tol * dmax)) return false;
-        const double ljj = std::sqrt(d);
-        L[(size_t)j * k + j] = ljj;
-        for (int i = j + 1; i < k; ++i) {
-            zc s = G[(size_t)i * k + j];
-            for (int m = 0; m < j; ++m) s -= L[(size_t)i * k + m] * std::conj(L[(size_t)j * k + m]);
-            L[(size_t)i * k + j] = s / ljj;
-        }
-    }
-    return true;
-}
-
-// X = L^{-H} B  (B: k x m), back substitution with the upper triangular L^H
-static void solve_LH(int k, const std::vector<zc>& L, const std::vector<zc>& B, int m, std::vector<zc>& X) {
-    X = B;
-    for (int c = 0; c < m; ++c) {
-        for (int i = k - 1; i >= 0; --i) {
-            zc s = X[(size_t)i * m + c];
-            for (int j = i + 1; j < k; ++j) s -= std::conj(L[(size_t)j * k + i]) * X[(size_t)j * m + c];
-            X[(size_t)i * m + c] = s / L[(size_t)i * k + i].real();
-        }
-    }
-}
-
-// X = L^{-1} B (B: k x m), forward substitution
-static void solve_L(int k, const std::vector<zc>& L, const std::vector<zc>& B, int m, std::vector<zc>& X) {
-    X = B;
-    for (int c = 0; c < m; ++c) {
-        for (int i = 0; i < k; ++i) {
-            zc s = X[(size_t)i * m + c];
-            for (int j = 0; j < i; ++j) s -= L[(size_t)i * k + j] * X[(size_t)j * m + c];
-            X[(size_t)i * m + c] = s / L[(size_t)i * k + i].real();
-        }
-    }
-}
-
-static void hermitize(int k, std::vector<zc>& A) {
-    for (int i = 0; i < k; ++i) {
-        A[(size_t)i * k + i] = zc(A[(size_t)i * k + i].real(), 0.0);
-        for (int j = i + 1; j < k; ++j) {
-            const zc a = 0.5 * (A[(size_t)i * k + j] + std::conj(A[(size_t)j * k + i]));
-            A[(size_t)i * k + j] = a;
-            A[(size_t)j * k + i] = std::conj(a);
-        }
-    }
-}
-
-// Rayleigh-Ritz for the pencil (GA, GB): lowest `want` pairs; C is k x want with C^H GB C = I.
-static bool rayleigh_ritz(int k, std::vector<zc> GA, std::vector<zc> GB, int want, double chol_tol,
-                          std::vector<double>& theta, std::vector<zc>& C) {
-    hermitize(k, GA);
-    hermitize(k, GB);
-    std::vector<zc> L;
-    if (!cholesky(k, GB, L, chol_tol)) return false;
-    std::vector<zc> Y, H, Ht;
-    solve_L(k, L, GA, k, Y);                 // Y = L^{-1} GA
-    std::vector<zc> Yh((size_t)k * k);
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) Yh[(size_t)i * k + j] = std::conj(Y[(size_t)j * k + i]);
-    solve_L(k, L, Yh, k, Ht);                // Ht = L^{-1} Y^H = (Y L^{-H})^H = H^H = H
-    hermitize(k, Ht);
-    std::vector<double> w;
-    std::vector<zc> V;
-    jacobi_eigh(k, Ht, w, V);
-    std::vector<zc> Vw((size_t)k * want);
-    for (int i = 0; i < k; ++i)
-        for (int c = 0; c < want; ++c) Vw[(size_t)i * want + c] = V[(size_t)i * k + c];
-    solve_LH(k, L, Vw, want, C);
-    theta.assign(w.begin(), w.begin() + want);
-    return true;
-}
 
 // ---------------------------------------------------------------- the solver
 
@@ -188,6 +47,11 @@ struct Solver {
     double* dev_theta = nullptr;         // device, b
     double* res_part = nullptr;          // device
     double* res_out = nullptr;           // device, b
+    static constexpr int kSlots = 8;
+    zc* pinned = nullptr;                // host, kSlots * slot_elems
+    cx<double>* dev_slots = nullptr;     // device, kSlots * slot_elems
+    size_t slot_elems = 0;
+    int slot_next = 0;
     std::vector<double> theta;           // host
     std::vector<double> resid;           // host, relative residuals of the current block
 
@@ -225,40 +89,32 @@ struct Solver {
         return sync();
     }
 
-    // Y = S C with C (ks x m) from the host
+    // Y = S C with C (ks x m) from the host.  The coefficients go through a ring of pinned host
+    // slots into matching device slots; stream order keeps each device slot alive until its
+    // combine has run, and a slot is reused only after several stream synchronisations.
     template <typename R>
     int combine(const ColSet& S, const std::vector<zc>& C, const ColSet& Y) {
-        hipError_t e = hipMemcpyAsync(dev_small, C.data(), sizeof(zc) * C.size(), hipMemcpyHostToDevice, p->stream);
+        if (C.size() > slot_elems) return fail(PCX_E_ARG, "pcx_solve: coefficient block too large");
+        const int q = slot_next;
+        slot_next = (slot_next + 1) % kSlots;
+        std::copy(C.begin(), C.end(), pinned + (size_t)q * slot_elems);
+        cx<double>* dst = dev_slots + (size_t)q * slot_elems;
+        hipError_t e = hipMemcpyAsync(dst, pinned + (size_t)q * slot_elems, sizeof(zc) * C.size(),
+                                      hipMemcpyHostToDevice, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: coefficient copy");
-        e = launch_combine<R>(S, (const cx<double>*)dev_small, Y, N, p->stream);
+        e = launch_combine<R>(S, dst, Y, N, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: combine");
-        // the coefficient buffer is reused by the next call: keep the host ahead by at most one launch
-        return sync();
+        return PCX_OK;
     }
 
     // Cholesky-QR (SVQB fallback) of the b columns of `Y`, result into `T`; then swap.
     template <typename R>
-    int orthonormalize(cx<R>*& Y, cx<R>*& T) {
-        std::vector<zc> G;
-        int rc = gram<R>(colset(Y, b), colset(Y, b), G);
+    int orthonormalize(cx<R>*& Y, cx<R>*& T, int m) {
+        std::vector<zc> G, C;
+        int rc = gram<R>(colset(Y, m), colset(Y, m), G);
         if (rc) return rc;
-        std::vector<zc> L, C, I((size_t)b * b, zc(0, 0));
-        for (int i = 0; i < b; ++i) I[(size_t)i * b + i] = 1.0;
-        hermitize(b, G);
-        if (cholesky(b, G, L, 1e-14)) {
-            solve_LH(b, L, I, b, C);
-        } else {
-            std::vector<double> w;
-            std::vector<zc> V;
-            jacobi_eigh(b, G, w, V);
-            const double wmax = std::max(w.back(), 1e-300);
-            C.assign((size_t)b * b, zc(0, 0));
-            for (int c = 0; c < b; ++c) {
-                const double d = 1.0 / std::sqrt(std::max(w[c], 1e-14 * wmax));
-                for (int r = 0; r < b; ++r) C[(size_t)r * b + c] = V[(size_t)r * b + c] * d;
-            }
-        }
-        rc = combine<R>(colset(Y, b), C, colset(T, b));
+        orthonormalizer(m, G, C);
+        rc = combine<R>(colset(Y, m), C, colset(T, m));
         if (rc) return rc;
         std::swap(Y, T);
         return PCX_OK;
@@ -305,15 +161,15 @@ struct Solver {
         hipError_t e = launch_mask<R>(B.X, prec, n, b, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: mask");
         for (int pass = 0; pass < 2; ++pass)
-            if ((rc = orthonormalize<R>(B.X, B.T1))) return rc;
+            if ((rc = orthonormalize<R>(B.X, B.T1, b))) return rc;
         if ((rc = matvec<R>(B.X, B.AX, b))) return rc;
         if ((rc = rr_block<R>(B))) return rc;
-        bool hasP = false;
+        int np = 0;                       // columns of P (the previous active set)
         const double chol_tol = sizeof(R) == 8 ? 1e-13 : 1e-9;
         double best = 1e300;
         int stall = 0;
         for (;;) {
-            if ((rc = residuals<R>(B))) return rc;
+            if ((rc = residuals<R>(B))) return rc;   // W <- prec (AX - X theta) for all b columns
             bool all = true;
             double worst = 0;
             for (int j = 0; j < nev; ++j) {
@@ -328,75 +184,70 @@ struct Solver {
             if (worst < 0.9 * best) {
                 best = worst;
                 stall = 0;
-            } else if (sizeof(R) == 4 && ++stall >= 8) {
+            } else if (sizeof(R) == 4 && worst < 1e-2 && ++stall >= 12) {
                 return PCX_OK;
             }
             ++iters;
             ++st.iterations;
             if (sizeof(R) == 4) ++st.iterations_fp32;
-            // W <- W - X (X^H W), twice, then orthonormalise W
+            // soft locking: only columns whose residual is above tol expand the basis
+            std::vector<int> act;
+            for (int j = 0; j < b; ++j)
+                if (resid[j] > tol) act.push_back(j);
+            const int na = (int)act.size();
+            // W_act <- W_act - X (X^H W_act), selecting the active columns in the same pass; twice
             for (int pass = 0; pass < 2; ++pass) {
-                std::vector<zc> G, C((size_t)2 * b * b, zc(0, 0));
-                if ((rc = gram<R>(colset(B.X, b), colset(B.W, b), G))) return rc;
-                for (int r = 0; r < b; ++r)
-                    for (int c = 0; c < b; ++c) C[(size_t)r * b + c] = -G[(size_t)r * b + c];
-                for (int r = 0; r < b; ++r) C[(size_t)(b + r) * b + r] = 1.0;
-                if ((rc = combine<R>(colset(B.X, b, B.W, b), C, colset(B.T1, b)))) return rc;
+                const int wc = pass == 0 ? b : na;
+                std::vector<zc> G, C((size_t)(b + wc) * na, zc(0, 0));
+                if ((rc = gram<R>(colset(B.X, b), colset(B.W, wc), G))) return rc;
+                for (int c = 0; c < na; ++c) {
+                    const int src = pass == 0 ? act[c] : c;
+                    for (int r = 0; r < b; ++r) C[(size_t)r * na + c] = -G[(size_t)r * wc + src];
+                    C[(size_t)(b + src) * na + c] = 1.0;
+                }
+                if ((rc = combine<R>(colset(B.X, b, B.W, wc), C, colset(B.T1, na)))) return rc;
                 std::swap(B.W, B.T1);
             }
-            if ((rc = orthonormalize<R>(B.W, B.T1))) return rc;
-            if ((rc = matvec<R>(B.W, B.AW, b))) return rc;
-            // Rayleigh-Ritz on S = [X W P]
+            if ((rc = orthonormalize<R>(B.W, B.T1, na))) return rc;
+            if ((rc = matvec<R>(B.W, B.AW, na))) return rc;
+            // Rayleigh-Ritz on S = [X W P]; without P if the basis is too ill-conditioned
             std::vector<double> th;
             std::vector<zc> C;
             int k = 0;
-            for (int tryP = hasP ? 1 : 0; tryP >= 0; --tryP) {
-                k = tryP ? 3 * b : 2 * b;
-                ColSet S = tryP ? colset(B.X, b, B.W, b, B.P, b) : colset(B.X, b, B.W, b);
-                // B-set = [S | AS]: build with up to 4 runs; AS runs follow
-                ColSet BS;
-                if (tryP) {
-                    // [X W P AX] and [AW AP] as two gram calls to stay within 4 runs
-                    std::vector<zc> G1, G2;
-                    if ((rc = gram<R>(S, colset(B.X, b, B.W, b, B.P, b), G1))) return rc;
-                    if ((rc = gram<R>(S, colset(B.AX, b, B.AW, b, B.AP, b), G2))) return rc;
-                    std::vector<zc> GB((size_t)k * k), GA((size_t)k * k);
-                    for (size_t q = 0; q < GB.size(); ++q) { GB[q] = G1[q]; GA[q] = G2[q]; }
-                    if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C)) break;
-                } else {
-                    std::vector<zc> G;
-                    BS = colset(B.X, b, B.W, b, B.AX, b);
-                    BS.ptr[3] = B.AW;
-                    BS.ncols[3] = b;
-                    BS.nseg = 4;
-                    if ((rc = gram<R>(S, BS, G))) return rc;
-                    std::vector<zc> GB((size_t)k * k), GA((size_t)k * k);
-                    for (int r = 0; r < k; ++r)
-                        for (int c = 0; c < k; ++c) {
-                            GB[(size_t)r * k + c] = G[(size_t)r * 2 * k + c];
-                            GA[(size_t)r * k + c] = G[(size_t)r * 2 * k + k + c];
-                        }
-                    if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C)) break;
-                    return fail(PCX_E_NOCONV, "pcx_solve: Rayleigh-Ritz basis became singular");
-                }
+            bool withP = np > 0;
+            for (;;) {
+                k = b + na + (withP ? np : 0);
+                ColSet S = withP ? colset(B.X, b, B.W, na, B.P, np) : colset(B.X, b, B.W, na);
+                ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
+                std::vector<zc> G, GB((size_t)k * k), GA((size_t)k * k);
+                if ((rc = gram<R>(S, concat(S, AS), G))) return rc;     // S^H [S | AS]
+                for (int r = 0; r < k; ++r)
+                    for (int c = 0; c < k; ++c) {
+                        GB[(size_t)r * k + c] = G[(size_t)r * 2 * k + c];
+                        GA[(size_t)r * k + c] = G[(size_t)r * 2 * k + k + c];
+                    }
+                if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C)) break;
+                if (!withP) return fail(PCX_E_NOCONV, "pcx_solve: Rayleigh-Ritz basis became singular");
+                withP = false;
             }
-            // [X' | P'] = S [C | C_P], C_P = C with the X rows zeroed
-            std::vector<zc> C2((size_t)k * 2 * b, zc(0, 0));
-            for (int r = 0; r < k; ++r)
-                for (int c = 0; c < b; ++c) {
-                    C2[(size_t)r * 2 * b + c] = C[(size_t)r * b + c];
-                    if (r >= b) C2[(size_t)r * 2 * b + b + c] = C[(size_t)r * b + c];
-                }
-            ColSet S = k == 3 * b ? colset(B.X, b, B.W, b, B.P, b) : colset(B.X, b, B.W, b);
-            ColSet AS = k == 3 * b ? colset(B.AX, b, B.AW, b, B.AP, b) : colset(B.AX, b, B.AW, b);
-            if ((rc = combine<R>(S, C2, colset(B.T1, b, B.T3, b)))) return rc;
-            if ((rc = combine<R>(AS, C2, colset(B.T2, b, B.T4, b)))) return rc;
+            // [X' | P'] = S [C | C_P]; C_P = the active columns of C with the X rows zeroed
+            const int m = b + na;
+            std::vector<zc> C2((size_t)k * m, zc(0, 0));
+            for (int r = 0; r < k; ++r) {
+                for (int c = 0; c < b; ++c) C2[(size_t)r * m + c] = C[(size_t)r * b + c];
+                if (r >= b)
+                    for (int c = 0; c < na; ++c) C2[(size_t)r * m + b + c] = C[(size_t)r * b + act[c]];
+            }
+            ColSet S = withP ? colset(B.X, b, B.W, na, B.P, np) : colset(B.X, b, B.W, na);
+            ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
+            if ((rc = combine<R>(S, C2, colset(B.T1, b, B.T3, na)))) return rc;
+            if ((rc = combine<R>(AS, C2, colset(B.T2, b, B.T4, na)))) return rc;
             std::swap(B.X, B.T1);
             std::swap(B.P, B.T3);
             std::swap(B.AX, B.T2);
             std::swap(B.AP, B.T4);
             theta = th;
-            hasP = true;
+            np = na;
         }
     }
 };
@@ -446,7 +297,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     S.n = n;
     S.N = N;
     if (nev < 1) return fail(PCX_E_ARG, "pcx_solve: nev must be >= 1");
-    int b = S.o.block > 0 ? S.o.block : nev + std::max(2, nev / 4);
+    int b = S.o.block > 0 ? S.o.block : nev + std::max(4, (nev + 1) / 2);
     if (b < nev) return fail(PCX_E_ARG, "pcx_solve: block (%d) smaller than nev (%d)", b, nev);
     if (b > PCX_MAX_BLOCK || 3L * b > N - 2) return fail(PCX_E_ARG, "pcx_solve: block %d too large for this grid", b);
     if (S.o.mode < PCX_MODE_FP64 || S.o.mode > PCX_MODE_FP32) return fail(PCX_E_ARG, "pcx_solve: bad mode");
@@ -461,21 +312,35 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (use32 && (rc = p->check_fits(PCX_FP32))) return rc;
 
     // storage: FP64 blocks, then FP32 blocks
+    hipError_t e0;
     const size_t bytes64 = use64 ? 10 * (size_t)b * N * sizeof(cx<double>) : 0;
     const size_t bytes32 = use32 ? 10 * (size_t)b * N * sizeof(cx<float>) : 0;
     if ((rc = p->grow(&p->lob_mem, &p->lob_cap, bytes64 + bytes32))) return rc;
     if ((rc = p->grow(&p->prec, &p->prec_cap, n * sizeof(double)))) return rc;
     S.gram_chunks = (int)std::min<long>(1024, std::max<long>(1, N / 1024));
-    const size_t gp = (size_t)S.gram_chunks * (3 * b) * (3 * b) * sizeof(cx<double>);
+    const size_t gp = (size_t)S.gram_chunks * (3 * b) * (6 * b) * sizeof(cx<double>);
     const size_t rp = (size_t)S.gram_chunks * b * sizeof(double);
     if ((rc = p->grow(&p->gram_part, &p->gram_part_cap, gp + rp))) return rc;
-    const size_t small = (size_t)(3 * b) * (4 * b) * sizeof(cx<double>) + 2 * b * sizeof(double) + 1024;
+    const size_t gram_out = (size_t)(3 * b) * (6 * b) * sizeof(cx<double>);
+    S.slot_elems = (size_t)(3 * b) * (2 * b);
+    const size_t slots = Solver::kSlots * S.slot_elems * sizeof(cx<double>);
+    const size_t small = gram_out + slots + 2 * b * sizeof(double) + 1024;
     if ((rc = p->grow(&p->small_mem, &p->small_cap, std::max<size_t>(small, 1 << 16)))) return rc;
+    if (p->pinned_cap < slots) {
+        if (p->pinned) (void)hipHostFree(p->pinned);
+        p->pinned = nullptr;
+        p->pinned_cap = 0;
+        e0 = hipHostMalloc(&p->pinned, slots, hipHostMallocDefault);
+        if (e0 != hipSuccess) return hip_fail(e0, "pcx_solve: pinned staging");
+        p->pinned_cap = slots;
+    }
+    S.pinned = (zc*)p->pinned;
     S.prec = (double*)p->prec;
     S.gram_part = (cx<double>*)p->gram_part;
     S.res_part = (double*)((char*)p->gram_part + gp);
     S.dev_small = (cx<double>*)p->small_mem;
-    S.dev_theta = (double*)((char*)p->small_mem + (size_t)(3 * b) * (4 * b) * sizeof(cx<double>));
+    S.dev_slots = (cx<double>*)((char*)p->small_mem + gram_out);
+    S.dev_theta = (double*)((char*)p->small_mem + gram_out + slots);
     S.res_out = S.dev_theta + b;
     (void)hipEventCreate(&S.ev0);
     (void)hipEventCreate(&S.ev1);
@@ -488,11 +353,34 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     Blocks<float> B32{};
     if (use64) B64 = carve<double>(p->lob_mem, b, N);
     if (use32) B32 = carve<float>((char*)p->lob_mem + bytes64, b, N);
+    // start block: the plane waves of the smallest Lambda_q (the homogeneous-medium eigenvectors,
+    // both polarisations) plus a small seeded random perturbation
+    std::vector<double> hp(n);
+    e = hipMemcpyAsync(hp.data(), S.prec, n * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner copy");
+    if ((rc = S.sync())) return rc;
+    std::vector<long> modes(n);
+    for (long q = 0; q < n; ++q) modes[q] = q;
+    const long nm = std::min<long>(n, (b + 1) / 2);
+    std::partial_sort(modes.begin(), modes.begin() + nm, modes.end(), [&](long a, long c) { return hp[a] > hp[c]; });
+    auto seed_block = [&](auto* X) -> int {
+        using C = typename std::remove_pointer<decltype(X)>::type;
+        hipError_t e2 = launch_random(X, (long)b * N, S.o.seed, 1e-3, p->stream);
+        if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: random start");
+        for (int c = 0; c < b; ++c) {
+            const long mode = modes[(c / 2) % nm];
+            C one;
+            one.x = 1;
+            one.y = 0;
+            e2 = hipMemcpyAsync(X + (size_t)c * N + (c % 2) * n + mode, &one, sizeof(C), hipMemcpyHostToDevice, p->stream);
+            if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: start block");
+        }
+        return S.sync();
+    };
     int iters = 0;
     rc = PCX_OK;
     if (use32) {
-        e = launch_random<float>(B32.X, (long)b * N, S.o.seed, p->stream);
-        if (e != hipSuccess) rc = hip_fail(e, "pcx_solve: random start");
+        rc = seed_block(B32.X);
         const double tol32 = S.o.mode == PCX_MODE_FP32 ? S.o.tol : std::max(S.o.tol, S.o.tol_fp32);
         if (!rc) rc = S.phase<float>(B32, tol32, S.o.max_iter, iters);
         if (!rc && use64) {
@@ -500,8 +388,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
             if (e != hipSuccess) rc = hip_fail(e, "pcx_solve: convert");
         }
     } else {
-        e = launch_random<double>(B64.X, (long)b * N, S.o.seed, p->stream);
-        if (e != hipSuccess) rc = hip_fail(e, "pcx_solve: random start");
+        rc = seed_block(B64.X);
     }
     if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters);
     if (!rc) {

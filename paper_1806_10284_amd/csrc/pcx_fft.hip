@@ -145,68 +145,93 @@ struct Bfly<R, 8> {
 };
 
 // ------------------------------------------------------------------ Stockham pass in LDS
-// nlines transforms of length N, element stride es and line stride ls (in elements), in place.
-// Butterfly b -> (line = b % nlines, j = b / nlines) so neighbouring lanes touch neighbouring
-// lines (unit stride for the strided axis).  Pass with radix RAD after the radices whose
-// product is Ns (Stockham autosort): inputs j + r N/RAD, twiddle w^{r (j mod Ns)},
-// w = exp(sign 2 pi i / (Ns RAD)); outputs (j / Ns) Ns RAD + j mod Ns + r Ns.
-template <typename R, int RAD, int MAXB>
+// nlines transforms of length N, element stride es and line stride ls (in elements), in place,
+// by a work-group of NT threads.  Butterfly b -> (line = b % nlines, j = b / nlines) so
+// neighbouring lanes touch neighbouring lines (unit stride for the strided axis).  Pass with
+// radix RAD after the radices whose product is Ns (Stockham autosort): inputs j + r N/RAD,
+// twiddle w^{r (j mod Ns)}, w = exp(sign 2 pi i / (Ns RAD)); outputs (j / Ns) Ns RAD + j mod Ns + r Ns.
+template <typename R, int RAD, int MAXB, int NT>
 DEV void stockham_pass(cx<R>* buf, int N, int Ns, int nlines, int es, int ls, const cx<R>* tw, int sign) {
     const int NR = N / RAD;
     const int total = NR * nlines;
     const int twstep = N / (Ns * RAD);
+    // butterfly b = tid + t NT -> (line, j) = (b % nlines, b / nlines), advanced incrementally
+    const int dj = NT / nlines, dl = NT % nlines;
+    const int line0 = threadIdx.x % nlines, j0 = threadIdx.x / nlines;
     cx<R> v[MAXB][RAD];
+    {
+        int line = line0, j = j0;
 #pragma unroll
-    for (int t = 0; t < MAXB; ++t) {
-        const int b = threadIdx.x + t * kThreads;
-        if (b < total) {
-            const int line = b % nlines;
-            const int j = b / nlines;
-            const cx<R>* src = buf + line * ls + j * es;
+        for (int t = 0; t < MAXB; ++t) {
+            if (threadIdx.x + t * NT < total) {
+                const cx<R>* src = buf + line * ls + j * es;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) v[t][r] = src[r * NR * es];
-            const int k = j % Ns;
-            if (k) {
+                for (int r = 0; r < RAD; ++r) v[t][r] = src[r * NR * es];
+                const int k = j % Ns;
+                if (k) {
 #pragma unroll
-                for (int r = 1; r < RAD; ++r) {
-                    cx<R> w = tw[r * k * twstep];
-                    if (sign < 0) w.y = -w.y;
-                    v[t][r] = cmul(v[t][r], w);
+                    for (int r = 1; r < RAD; ++r) {
+                        cx<R> w = tw[r * k * twstep];
+                        if (sign < 0) w.y = -w.y;
+                        v[t][r] = cmul(v[t][r], w);
+                    }
                 }
+            }
+            line += dl;
+            j += dj;
+            if (line >= nlines) {
+                line -= nlines;
+                ++j;
             }
         }
     }
     __syncthreads();
+    {
+        int line = line0, j = j0;
 #pragma unroll
-    for (int t = 0; t < MAXB; ++t) {
-        const int b = threadIdx.x + t * kThreads;
-        if (b < total) {
-            const int line = b % nlines;
-            const int j = b / nlines;
-            const int k = j % Ns;
-            Bfly<R, RAD>::run(v[t], sign);
-            cx<R>* dst = buf + line * ls + ((j / Ns) * Ns * RAD + k) * es;
+        for (int t = 0; t < MAXB; ++t) {
+            if (threadIdx.x + t * NT < total) {
+                const int k = j % Ns;
+                Bfly<R, RAD>::run(v[t], sign);
+                cx<R>* dst = buf + line * ls + ((j / Ns) * Ns * RAD + k) * es;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) dst[r * Ns * es] = v[t][r];
+                for (int r = 0; r < RAD; ++r) dst[r * Ns * es] = v[t][r];
+            }
+            line += dl;
+            j += dj;
+            if (line >= nlines) {
+                line -= nlines;
+                ++j;
+            }
         }
     }
     __syncthreads();
 }
 
-// EPT >= ceil(N * nlines / kThreads)
-template <typename R, int EPT>
+// All nlines transforms, in chunks of lines so that each thread holds at most kEpc elements per
+// pass (lines are independent, so a chunk runs all its passes before the next chunk starts).
+constexpr int kEpc = 4;
+
+template <typename R, int EPT, int NT>
 DEV void fft_lines(cx<R>* buf, const FftPlan& fp, int nlines, int es, int ls, const cx<R>* tw, int sign) {
-    int Ns = 1;
-    for (int p = 0; p < fp.npass; ++p) {
-        const int rad = fp.rad[p];
-        switch (rad) {
-            case 8: stockham_pass<R, 8, (EPT + 7) / 8>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
-            case 4: stockham_pass<R, 4, (EPT + 3) / 4>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
-            case 2: stockham_pass<R, 2, (EPT + 1) / 2>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
-            case 3: stockham_pass<R, 3, (EPT + 2) / 3>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
-            default: stockham_pass<R, 5, (EPT + 4) / 5>(buf, fp.n, Ns, nlines, es, ls, tw, sign); break;
+    const int lpc = (kEpc * NT) / fp.n > 0 ? (kEpc * NT) / fp.n : 1;
+#pragma unroll 1
+    for (int l0 = 0; l0 < nlines; l0 += lpc) {
+        const int nl = nlines - l0 < lpc ? nlines - l0 : lpc;
+        cx<R>* b0 = buf + l0 * ls;
+        int Ns = 1;
+#pragma unroll 1
+        for (int p = 0; p < fp.npass; ++p) {
+            const int rad = fp.rad[p];
+            switch (rad) {
+                case 8: stockham_pass<R, 8, 1, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 4: stockham_pass<R, 4, 1, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 2: stockham_pass<R, 2, 2, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 3: stockham_pass<R, 3, 2, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                default: stockham_pass<R, 5, 1, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+            }
+            Ns *= rad;
         }
-        Ns *= rad;
     }
 }
 
@@ -224,38 +249,65 @@ DEV cx<double> lam_of_turn(double t, double inv_delta) {
 
 DEV double abs2(cx<double> a) { return a.x * a.x + a.y * a.y; }
 
-// Row l of W (Section 5.1): W[:,0] = (Lq 1 - Lambda conj(Ls)) / Lp, W[:,1] = sqrt(Lq) (1 x conj Lambda) / Lp,
-// Lp^2 = sum_{a<b} |Lambda_a - Lambda_b|^2; for Lp^2 < tau Lq the reference vector 1 is replaced by
-// e_m, m = first index with |Lambda_m|^2 <= (1 + 1e-8) min |Lambda|^2.
-DEV void w_row(cx<double> L0, cx<double> L1, cx<double> L2, int l, cx<double>* w1, cx<double>* w2) {
+// Basis choice per mode (Section 5.1 reading): 0 = the paper's basis (reference vector 1),
+// 1..3 = fallback reference vector e_{code-1}, kMasked = no range space (Gamma mode).
+constexpr unsigned char kMasked = 255;
+
+DEV unsigned char mix_code(cx<double> L0, cx<double> L1, cx<double> L2) {
     const double a0 = abs2(L0), a1 = abs2(L1), a2 = abs2(L2);
     const double Lq = a0 + a1 + a2;
     const double Lp2 = abs2(L0 - L1) + abs2(L0 - L2) + abs2(L1 - L2);
-    const double sq = sqrt(Lq);
-    const cx<double> Ll = (l == 0) ? L0 : (l == 1 ? L1 : L2);
-    // components of conj(Lambda)
-    const cx<double> v0 = conjc(L0), v1 = conjc(L1), v2 = conjc(L2);
-    if (Lp2 >= kMixTau * Lq) {
-        const double inv = 1.0 / sqrt(Lp2);
-        const cx<double> Ls = L0 + L1 + L2;
-        cx<double> c1 = mk<double>(Lq, 0.0) - cmulc(Ll, Ls);
-        cx<double> cr = (l == 0) ? (v2 - v1) : (l == 1 ? (v0 - v2) : (v1 - v0));
+    if (Lp2 >= kMixTau * Lq) return 0;
+    const double mn = fmin(a0, fmin(a1, a2)) * (1.0 + 1e-8);
+    return (unsigned char)(1 + ((a0 <= mn) ? 0 : ((a1 <= mn) ? 1 : 2)));
+}
+
+DEV double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+DEV float rsqrt_r(float x) { return rsqrtf(x); }
+DEV double sqrt_r(double x) { return sqrt(x); }
+DEV float sqrt_r(float x) { return sqrtf(x); }
+
+// Row l of W in precision R for the basis `code` (not kMasked), from FP64 symbols:
+//   code 0: W[:,0] = (Lq 1 - Lambda conj(Ls)) / Lp, W[:,1] = sqrt(Lq) (1 x conj Lambda) / Lp,
+//           evaluated without cancellation as W[l,0] = sum_{m != l} conj(L_m)(L_m - L_l) / Lp and
+//           W[:,1] = sqrt(Lq) conj(L2 - L1, L0 - L2, L1 - L0) / Lp, Lp^2 = sum |L_a - L_b|^2,
+//           the differences taken in FP64;
+//   code 1+m: the same with 1 replaced by e_m: W[l,0] = (delta_lm Lq - L_l conj(L_m)) / d,
+//           W[:,1] = sqrt(Lq) (e_m x conj Lambda) / d, d^2 = Lq - |L_m|^2 = sum_{l != m} |L_l|^2.
+template <typename R>
+DEV void w_row_code(cx<double> L0, cx<double> L1, cx<double> L2, int code, int l, cx<R>* w1, cx<R>* w2) {
+    const double a0 = abs2(L0), a1 = abs2(L1), a2 = abs2(L2);
+    const R sq = sqrt_r((R)(a0 + a1 + a2));
+    const cx<R> zero = mk<R>((R)0, (R)0);
+    if (code == 0) {
+        const cx<double> D10 = L1 - L0, D20 = L2 - L0, D21 = L2 - L1;
+        const R inv = rsqrt_r((R)(abs2(D10) + abs2(D20) + abs2(D21)));
+        const cx<R> d10 = cvt<R>(D10), d20 = cvt<R>(D20), d21 = cvt<R>(D21);
+        cx<R> c1, c2;
+        if (l == 0) {
+            c1 = cmul(conjc(cvt<R>(L1)), d10) + cmul(conjc(cvt<R>(L2)), d20);
+            c2 = conjc(d21);
+        } else if (l == 1) {
+            c1 = cmul(conjc(cvt<R>(L2)), d21) - cmul(conjc(cvt<R>(L0)), d10);
+            c2 = zero - conjc(d20);
+        } else {
+            c1 = zero - cmul(conjc(cvt<R>(L0)), d20) - cmul(conjc(cvt<R>(L1)), d21);
+            c2 = conjc(d10);
+        }
         *w1 = cscale(c1, inv);
-        *w2 = cscale(cr, sq * inv);
+        *w2 = cscale(c2, sq * inv);
     } else {
-        const double mn = fmin(a0, fmin(a1, a2)) * (1.0 + 1e-8);
-        const int m = (a0 <= mn) ? 0 : ((a1 <= mn) ? 1 : 2);
-        const double am = (m == 0) ? a0 : (m == 1 ? a1 : a2);
-        const cx<double> Lm = (m == 0) ? L0 : (m == 1 ? L1 : L2);
-        const double inv = 1.0 / sqrt(Lq - am);
-        cx<double> c1 = mk<double>(l == m ? Lq : 0.0, 0.0) - cmulc(Ll, Lm);
-        // e_m x v: e0 -> (0, -v2, v1); e1 -> (v2, 0, -v0); e2 -> (-v1, v0, 0)
-        cx<double> zero = mk<double>(0.0, 0.0);
-        cx<double> cr;
+        const int m = code - 1;
+        const double d2 = (m == 0) ? a1 + a2 : (m == 1 ? a0 + a2 : a0 + a1);
+        const R inv = rsqrt_r((R)d2);
+        const cx<R> Ll = cvt<R>((l == 0) ? L0 : (l == 1 ? L1 : L2));
+        const cx<R> Lm = cvt<R>((m == 0) ? L0 : (m == 1 ? L1 : L2));
+        const cx<R> v0 = conjc(cvt<R>(L0)), v1 = conjc(cvt<R>(L1)), v2 = conjc(cvt<R>(L2));
+        cx<R> cr;
         if (m == 0) cr = (l == 0) ? zero : (l == 1 ? zero - v2 : v1);
         else if (m == 1) cr = (l == 0) ? v2 : (l == 1 ? zero : zero - v0);
         else cr = (l == 0) ? zero - v1 : (l == 1 ? v0 : zero);
-        *w1 = cscale(c1, inv);
+        *w1 = cscale(l == m ? mk<R>((R)d2, (R)0) : zero - cmulc(Ll, Lm), inv);
         *w2 = cscale(cr, sq * inv);
     }
 }
@@ -266,29 +318,31 @@ DEV void w_row(cx<double> L0, cx<double> L1, cx<double> L2, int l, cx<double>* w
 //   twz    cx<R>[n3]  LUT exp(+2 pi i m / n3)
 //   twy    cx<R>[n2]  LUT exp(+2 pi i m / n2)
 //   twb    cx<R>[n2]  exp(2 pi i b phi2(i))
+//   twc    cx<R>[n3]  exp(2 pi i c A(i)), the j-independent part of exp(2 pi i c phi3(i, j))
+//   lamy   cx<double>[n2]  Lambda_2(i, j)
 //   halfz  cx<double>[n3]  exp(i pi k / n3)
 //   rowz   cx<double>[n2]  exp(i pi phi3(i, j))
-//   lamy   cx<double>[n2]  Lambda_2(i, j)
-//   phi3   double[n2]
-//   kstar  int[n2]   masked k of row j (or -1)
+// With t_y = (kappa2 + j - s1 t_x)/n2, phi3(i, j) = A(i) - s3 j / (n2 n3) where
+// A(i) = (kappa3 - s2 t_x - s3 (kappa2 - s1 t_x) / n2) / n3, so
+//   exp(2 pi i c phi3) = twc[c] * exp(-2 pi i ((c j s3) mod n2 n3) / (n2 n3))
+// and the second factor is read from the plan's table of (n2 n3)-th roots of unity.
 template <typename R>
 struct PlaneLds {
     cx<R>* plane;
     cx<R>* twz;
     cx<R>* twy;
     cx<R>* twb;
+    cx<R>* twc;
+    cx<double>* lamy;
     cx<double>* halfz;
     cx<double>* rowz;
-    cx<double>* lamy;
-    double* phi3;
-    int* kstar;
 };
 
 template <typename R>
 __host__ DEV size_t plane_lds_bytes(int n2, int n3) {
-    size_t b = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + n3 + 2 * n2);
+    size_t b = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + 2 * n3 + 2 * n2);
     b = (b + 15) & ~(size_t)15;
-    b += sizeof(cx<double>) * (n3 + 2 * n2) + sizeof(double) * n2 + sizeof(int) * n2;
+    b += sizeof(cx<double>) * (n3 + 2 * n2);
     return b;
 }
 
@@ -299,63 +353,63 @@ DEV PlaneLds<R> plane_lds(char* base, int n2, int n3) {
     L.twz = L.plane + (size_t)n2 * (n3 + 1);
     L.twy = L.twz + n3;
     L.twb = L.twy + n2;
-    size_t off = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + n3 + 2 * n2);
+    L.twc = L.twb + n2;
+    size_t off = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + 2 * n3 + 2 * n2);
     off = (off + 15) & ~(size_t)15;
     L.halfz = (cx<double>*)(base + off);
     L.rowz = L.halfz + n3;
     L.lamy = L.rowz + n2;
-    L.phi3 = (double*)(L.lamy + n2);
-    L.kstar = (int*)(L.phi3 + n2);
     return L;
 }
 
-// Fills the tables for plane i; returns Lambda_1(i) and whether t_x(i) is whole.
-template <typename R>
-DEV void plane_setup(const Grid& g, const DeviceTables& tb, int i, PlaneLds<R>& L, cx<double>* lamx_out) {
+// Fills the tables for plane i; returns Lambda_1(i).
+template <typename R, int NT>
+DEV cx<double> plane_setup(const Grid& g, const DeviceTables& tb, int i, PlaneLds<R>& L) {
     const int n2 = g.n2, n3 = g.n3;
     const double tx = (g.kap[0] + (double)i) / (double)g.n1;
-    const bool tx_whole = (tx == rint(tx));
     const cx<R>* twz_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[2] : (const cx<R>*)tb.tw32[2];
     const cx<R>* twy_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[1] : (const cx<R>*)tb.tw32[1];
     const double phi2 = (g.kap[1] - (double)g.s1 * tx) / (double)n2;
-    for (int q = threadIdx.x; q < n3; q += kThreads) {
+    const double Ai = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((g.kap[1] - (double)g.s1 * tx) / (double)n2)) /
+                      (double)n3;
+    for (int q = threadIdx.x; q < n3; q += NT) {
         L.twz[q] = twz_g[q];
         L.halfz[q] = tb.halfz[q];
+        L.twc[q] = cis_turns<R>((double)q * Ai);
     }
-    for (int j = threadIdx.x; j < n2; j += kThreads) {
+    for (int j = threadIdx.x; j < n2; j += NT) {
         L.twy[j] = twy_g[j];
         L.twb[j] = cis_turns<R>((double)j * phi2);
         const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)n2;
         L.lamy[j] = lam_of_turn(ty, 1.0 / g.dlt[1]);
         const double p3 = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)n3;
-        L.phi3[j] = p3;
         double s, c;
         sincospi(p3, &s, &c);
         L.rowz[j] = mk<double>(c, s);
-        int ks = -1;
-        const double Rz = (g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty;   // t_z = (k + Rz) / n3
-        if (tx_whole && ty == rint(ty) && Rz == rint(Rz)) {
-            long kk = (-(long)rint(Rz)) % n3;
-            if (kk < 0) kk += n3;
-            ks = (int)kk;
-        }
-        L.kstar[j] = ks;
     }
-    *lamx_out = lam_of_turn(tx, 1.0 / g.dlt[0]);
+    return lam_of_turn(tx, 1.0 / g.dlt[0]);
 }
 
-// Lambda_3 at (j, k) from the tables: exp(i pi t_z) = exp(i pi k / n3) exp(i pi phi3(i, j))
+// Lambda_3 at mode (j, k) from exp(i pi t_z) = exp(i pi k / n3) exp(i pi phi3(i, j)) (FP64)
 template <typename R>
 DEV cx<double> lam_z(const PlaneLds<R>& L, int j, int k, double inv_dz) {
-    cx<double> h = cmul(L.halfz[k], L.rowz[j]);
+    const cx<double> h = cmul(L.halfz[k], L.rowz[j]);
     return lam_from_halfturn(h.y, h.x, inv_dz);
 }
 
+// exp(2 pi i c phi3(i, j))
+template <typename R>
+DEV cx<R> z_twiddle(const PlaneLds<R>& L, const cx<R>* __restrict__ rot, int c, int j, int s3, int M) {
+    int m = (c * j * s3) % M;
+    if (m < 0) m += M;
+    return cmul(L.twc[c], rot[m]);
+}
+
 // ------------------------------------------------------------------ kernel 1: W y, then z and y inverse DFTs
-// y: [v][2][n1][n2][n3]   ->   t: [v][3][n1][n3][n2]
-template <typename R, int EPT>
-__global__ void __launch_bounds__(kThreads) k_plane_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
-                                                         cx<R>* __restrict__ t) {
+// y: [v][2][n1][n2][n3]   ->   t: [v][3][n1][n3][n2];   grid (n1, nvec), NT threads.
+template <typename R, int NT, int EPT>
+__global__ void __launch_bounds__(NT) k_plane_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
+                                                   cx<R>* __restrict__ t) {
     extern __shared__ __align__(16) char lds[];
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const int i = blockIdx.x;
@@ -364,61 +418,42 @@ __global__ void __launch_bounds__(kThreads) k_plane_fwd(Grid g, DeviceTables tb,
     const int np = n2 * n3;
     const int ld = n3 + 1;
     PlaneLds<R> L = plane_lds<R>(lds, n2, n3);
-    cx<double> lamx;
-    plane_setup<R>(g, tb, i, L, &lamx);
+    const cx<double> lamx = plane_setup<R, NT>(g, tb, i, L);
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    const unsigned char* codes = g.codes + (long)i * np;
     __syncthreads();
-
-    // this thread's elements e = tid + s * kThreads of the plane: (j, k) = (e / n3, e % n3)
-    cx<R> y1[EPT], y2[EPT], twc[EPT];
-    const cx<R>* yb = y + (long)v * 2 * n + (long)i * np;
-#pragma unroll
-    for (int s = 0; s < EPT; ++s) {
-        const int e = threadIdx.x + s * kThreads;
-        if (e < np) {
-            y1[s] = yb[e];
-            y2[s] = yb[n + e];
-            const int j = e / n3, c = e % n3;
-            twc[s] = cis_turns<R>((double)c * L.phi3[j]);
-        }
-    }
     const double idz = 1.0 / g.dlt[2];
+    const cx<R>* yb = y + (long)v * 2 * n + (long)i * np;
+#pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         // u_l = W_l1 y1 + W_l2 y2 into the plane [j][k]
-#pragma unroll
-        for (int s = 0; s < EPT; ++s) {
-            const int e = threadIdx.x + s * kThreads;
-            if (e < np) {
-                const int j = e / n3, k = e % n3;
-                cx<R> u = mk<R>(0, 0);
-                if (L.kstar[j] != k) {
-                    cx<double> w1, w2;
-                    w_row(lamx, L.lamy[j], lam_z(L, j, k, idz), l, &w1, &w2);
-                    u = cmul(cvt<R>(w1), y1[s]) + cmul(cvt<R>(w2), y2[s]);
-                }
-                L.plane[j * ld + k] = u;
+#pragma unroll 1
+        for (int e = threadIdx.x; e < np; e += NT) {
+            const int j = e / n3, k = e % n3;
+            const int code = codes[e];
+            cx<R> u = mk<R>((R)0, (R)0);
+            if (code != kMasked) {
+                cx<R> w1, w2;
+                w_row_code<R>(lamx, L.lamy[j], lam_z(L, j, k, idz), code, l, &w1, &w2);
+                u = cmul(w1, yb[e]) + cmul(w2, yb[n + e]);
             }
+            L.plane[j * ld + k] = u;
         }
         __syncthreads();
-        fft_lines<R, EPT>(L.plane, g.fz, n2, 1, ld, L.twz, +1);        // k -> c along rows j
-#pragma unroll
-        for (int s = 0; s < EPT; ++s) {
-            const int e = threadIdx.x + s * kThreads;
-            if (e < np) {
-                const int j = e / n3, c = e % n3;
-                L.plane[j * ld + c] = cmul(L.plane[j * ld + c], twc[s]);
-            }
+        fft_lines<R, EPT, NT>(L.plane, g.fz, n2, 1, ld, L.twz, +1);    // k -> c along rows j
+#pragma unroll 1
+        for (int e = threadIdx.x; e < np; e += NT) {
+            const int j = e / n3, c = e % n3;
+            L.plane[j * ld + c] = cmul(L.plane[j * ld + c], z_twiddle(L, rot, c, j, g.s3, np));
         }
         __syncthreads();
-        fft_lines<R, EPT>(L.plane, g.fy, n3, ld, 1, L.twy, +1);        // j -> b along columns c
+        fft_lines<R, EPT, NT>(L.plane, g.fy, n3, ld, 1, L.twy, +1);    // j -> b along columns c
         // write t[v][l][i][c][b] = plane[b][c] * exp(2 pi i b phi2)
         cx<R>* tb_out = t + ((long)v * 3 + l) * n + (long)i * np;
-#pragma unroll
-        for (int s = 0; s < EPT; ++s) {
-            const int e = threadIdx.x + s * kThreads;
-            if (e < np) {
-                const int c = e / n2, b = e % n2;
-                tb_out[e] = cmul(L.plane[b * ld + c], L.twb[b]);
-            }
+#pragma unroll 1
+        for (int e = threadIdx.x; e < np; e += NT) {
+            const int c = e / n2, b = e % n2;
+            tb_out[e] = cmul(L.plane[b * ld + c], L.twb[b]);
         }
         __syncthreads();
     }
@@ -426,9 +461,9 @@ __global__ void __launch_bounds__(kThreads) k_plane_fwd(Grid g, DeviceTables tb,
 
 // ------------------------------------------------------------------ kernel 3: y and z forward DFTs, then W^H
 // t: [v][3][n1][n3][n2]  ->  z: [v][2][n1][n2][n3]
-template <typename R, int EPT>
-__global__ void __launch_bounds__(kThreads) k_plane_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
-                                                         cx<R>* __restrict__ z) {
+template <typename R, int NT, int EPT>
+__global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
+                                                   cx<R>* __restrict__ z) {
     extern __shared__ __align__(16) char lds[];
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const int i = blockIdx.x;
@@ -437,67 +472,84 @@ __global__ void __launch_bounds__(kThreads) k_plane_adj(Grid g, DeviceTables tb,
     const int np = n2 * n3;
     const int ld = n3 + 1;
     PlaneLds<R> L = plane_lds<R>(lds, n2, n3);
-    cx<double> lamx;
-    plane_setup<R>(g, tb, i, L, &lamx);
+    const cx<double> lamx = plane_setup<R, NT>(g, tb, i, L);
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    const unsigned char* codes = g.codes + (long)i * np;
     __syncthreads();
-
-    cx<R> acc1[EPT], acc2[EPT], twc[EPT];
-#pragma unroll
-    for (int s = 0; s < EPT; ++s) {
-        const int e = threadIdx.x + s * kThreads;
-        acc1[s] = mk<R>(0, 0);
-        acc2[s] = mk<R>(0, 0);
-        if (e < np) {
-            const int j = e / n3, c = e % n3;
-            twc[s] = cis_turns<R>((double)c * L.phi3[j]);
-        }
-    }
     const double idz = 1.0 / g.dlt[2];
+    constexpr bool kRegAcc = sizeof(R) == 4 ? EPT <= 4 : EPT <= 8;   // accumulators in registers
+    constexpr int NA = kRegAcc ? EPT : 1;
+    cx<R> acc1[NA], acc2[NA];
+#pragma unroll
+    for (int s = 0; s < NA; ++s) acc1[s] = acc2[s] = mk<R>((R)0, (R)0);
+#pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         const cx<R>* tin = t + ((long)v * 3 + l) * n + (long)i * np;
-#pragma unroll
-        for (int s = 0; s < EPT; ++s) {
-            const int e = threadIdx.x + s * kThreads;
-            if (e < np) {
-                const int c = e / n2, b = e % n2;
-                L.plane[b * ld + c] = cmulc(tin[e], L.twb[b]);
-            }
+#pragma unroll 1
+        for (int e = threadIdx.x; e < np; e += NT) {
+            const int c = e / n2, b = e % n2;
+            L.plane[b * ld + c] = cmulc(tin[e], L.twb[b]);
         }
         __syncthreads();
-        fft_lines<R, EPT>(L.plane, g.fy, n3, ld, 1, L.twy, -1);        // b -> j along columns c
-#pragma unroll
-        for (int s = 0; s < EPT; ++s) {
-            const int e = threadIdx.x + s * kThreads;
-            if (e < np) {
-                const int j = e / n3, c = e % n3;
-                L.plane[j * ld + c] = cmulc(L.plane[j * ld + c], twc[s]);
-            }
+        fft_lines<R, EPT, NT>(L.plane, g.fy, n3, ld, 1, L.twy, -1);    // b -> j along columns c
+#pragma unroll 1
+        for (int e = threadIdx.x; e < np; e += NT) {
+            const int j = e / n3, c = e % n3;
+            L.plane[j * ld + c] = cmulc(L.plane[j * ld + c], z_twiddle(L, rot, c, j, g.s3, np));
         }
         __syncthreads();
-        fft_lines<R, EPT>(L.plane, g.fz, n2, 1, ld, L.twz, -1);        // c -> k along rows j
+        fft_lines<R, EPT, NT>(L.plane, g.fz, n2, 1, ld, L.twz, -1);    // c -> k along rows j
+        if (kRegAcc) {
+            // accumulate W^H v in registers
 #pragma unroll
-        for (int s = 0; s < EPT; ++s) {
-            const int e = threadIdx.x + s * kThreads;
-            if (e < np) {
-                const int j = e / n3, k = e % n3;
-                if (L.kstar[j] != k) {
-                    cx<double> w1, w2;
-                    w_row(lamx, L.lamy[j], lam_z(L, j, k, idz), l, &w1, &w2);
-                    const cx<R> val = L.plane[j * ld + k];
-                    acc1[s] = acc1[s] + cmulc(val, cvt<R>(w1));
-                    acc2[s] = acc2[s] + cmulc(val, cvt<R>(w2));
+            for (int s = 0; s < NA; ++s) {
+                const int e = threadIdx.x + s * NT;
+                if (e < np) {
+                    const int j = e / n3, k = e % n3;
+                    const int code = codes[e];
+                    if (code != kMasked) {
+                        cx<R> w1, w2;
+                        w_row_code<R>(lamx, L.lamy[j], lam_z(L, j, k, idz), code, l, &w1, &w2);
+                        const cx<R> val = L.plane[j * ld + k];
+                        acc1[s] = acc1[s] + cmulc(val, w1);
+                        acc2[s] = acc2[s] + cmulc(val, w2);
+                    }
                 }
+            }
+        } else {
+            // many modes per thread: accumulate in the (thread-private) output entries
+            cx<R>* zb = z + (long)v * 2 * n + (long)i * np;
+#pragma unroll 1
+            for (int e = threadIdx.x; e < np; e += NT) {
+                const int j = e / n3, k = e % n3;
+                const int code = codes[e];
+                cx<R> a1 = mk<R>((R)0, (R)0), a2 = a1;
+                if (l > 0) {
+                    a1 = zb[e];
+                    a2 = zb[n + e];
+                }
+                if (code != kMasked) {
+                    cx<R> w1, w2;
+                    w_row_code<R>(lamx, L.lamy[j], lam_z(L, j, k, idz), code, l, &w1, &w2);
+                    const cx<R> val = L.plane[j * ld + k];
+                    a1 = a1 + cmulc(val, w1);
+                    a2 = a2 + cmulc(val, w2);
+                }
+                zb[e] = a1;
+                zb[n + e] = a2;
             }
         }
         __syncthreads();
     }
-    cx<R>* zb = z + (long)v * 2 * n + (long)i * np;
+    if (kRegAcc) {
+        cx<R>* zb = z + (long)v * 2 * n + (long)i * np;
 #pragma unroll
-    for (int s = 0; s < EPT; ++s) {
-        const int e = threadIdx.x + s * kThreads;
-        if (e < np) {
-            zb[e] = acc1[s];
-            zb[n + e] = acc2[s];
+        for (int s = 0; s < NA; ++s) {
+            const int e = threadIdx.x + s * NT;
+            if (e < np) {
+                zb[e] = acc1[s];
+                zb[n + e] = acc2[s];
+            }
         }
     }
 }
@@ -508,7 +560,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_adj(Grid g, DeviceTables tb,
 // MODE 1: t -> IDFT_x -> * exp(2 pi i a phi1) n^{-1/2} (* inv_eps if given) -> u (e-layout)
 // MODE 2: u (e-layout) -> * exp(-2 pi i a phi1) n^{-1/2} -> DFT_x -> t
 template <typename R, int EPT, int MODE>
-__global__ void __launch_bounds__(kThreads) k_xline(Grid g, DeviceTables tb, const R* __restrict__ scale,
+__global__ void __launch_bounds__(256) k_xline(Grid g, DeviceTables tb, const R* __restrict__ scale,
                                                      cx<R>* __restrict__ t, cx<R>* __restrict__ u, int TB) {
     extern __shared__ __align__(16) char lds[];
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
@@ -523,27 +575,28 @@ __global__ void __launch_bounds__(kThreads) k_xline(Grid g, DeviceTables tb, con
     cx<R>* twa = twx + n1;
     const cx<R>* twx_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[0] : (const cx<R>*)tb.tw32[0];
     const double phi1 = g.kap[0] / (double)n1;
-    for (int a = threadIdx.x; a < n1; a += kThreads) {
+    for (int a = threadIdx.x; a < n1; a += 256) {
         twx[a] = twx_g[a];
         if (MODE != 0) twa[a] = cis_turns<R>((double)a * phi1);
     }
     const R rsq = (R)(1.0 / sqrt((double)n));
     const int tot = n1 * qn;
+#pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         cx<R>* tl = t + ((long)v * 3 + l) * n;
         cx<R>* ul = u + ((long)v * 3 + l) * n;
         __syncthreads();
         if (MODE != 2) {
             // load t[i][q0 + ql] -> buf[ql][i]
-            for (int e = threadIdx.x; e < tot; e += kThreads) {
+            for (int e = threadIdx.x; e < tot; e += 256) {
                 const int ii = e / qn, ql = e % qn;
                 buf[ql * ld + ii] = tl[(long)ii * np + q0 + ql];
             }
             __syncthreads();
-            fft_lines<R, EPT>(buf, g.fx, qn, 1, ld, twx, +1);            // i -> a
+            fft_lines<R, EPT, 256>(buf, g.fx, qn, 1, ld, twx, +1);            // i -> a
         } else {
             // load u[(q0 + ql) * n1 + a] -> buf[ql][a] with the conjugate x twiddle
-            for (int e = threadIdx.x; e < tot; e += kThreads) {
+            for (int e = threadIdx.x; e < tot; e += 256) {
                 const int ql = e / n1, a = e % n1;
                 cx<R> val = ul[(q0 + ql) * n1 + a];
                 buf[ql * ld + a] = cscale(cmulc(val, twa[a]), rsq);
@@ -552,7 +605,7 @@ __global__ void __launch_bounds__(kThreads) k_xline(Grid g, DeviceTables tb, con
         }
         if (MODE == 0) {
             const R* sl = scale + (long)l * n;
-            for (int e = threadIdx.x; e < tot; e += kThreads) {
+            for (int e = threadIdx.x; e < tot; e += 256) {
                 const int ql = e / n1, a = e % n1;
                 buf[ql * ld + a] = cscale(buf[ql * ld + a], sl[(q0 + ql) * n1 + a]);
             }
@@ -560,7 +613,7 @@ __global__ void __launch_bounds__(kThreads) k_xline(Grid g, DeviceTables tb, con
         }
         if (MODE == 1) {
             const R* sl = scale ? scale + (long)l * n : nullptr;
-            for (int e = threadIdx.x; e < tot; e += kThreads) {
+            for (int e = threadIdx.x; e < tot; e += 256) {
                 const int ql = e / n1, a = e % n1;
                 R f = rsq;
                 if (sl) f *= sl[(q0 + ql) * n1 + a];
@@ -568,12 +621,45 @@ __global__ void __launch_bounds__(kThreads) k_xline(Grid g, DeviceTables tb, con
             }
             continue;
         }
-        fft_lines<R, EPT>(buf, g.fx, qn, 1, ld, twx, -1);                // a -> i
-        for (int e = threadIdx.x; e < tot; e += kThreads) {
+        fft_lines<R, EPT, 256>(buf, g.fx, qn, 1, ld, twx, -1);                // a -> i
+        for (int e = threadIdx.x; e < tot; e += 256) {
             const int ii = e / qn, ql = e % qn;
             tl[(long)ii * np + q0 + ql] = buf[ql * ld + ii];
         }
     }
+}
+
+// ------------------------------------------------------------------ mixing basis per mode
+// FP64 decision, shared by the FP32 and FP64 kernels: kMasked where Lambda_q = 0 (t_x, t_y, t_z all
+// whole), else mix_code of the FP64 symbols.
+__global__ void k_modecode(Grid g, unsigned char* __restrict__ out) {
+    const long n = (long)g.n1 * g.n2 * g.n3;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int k = (int)(e % g.n3);
+        const int j = (int)((e / g.n3) % g.n2);
+        const int i = (int)(e / ((long)g.n2 * g.n3));
+        const double tx = (g.kap[0] + (double)i) / (double)g.n1;
+        const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)g.n2;
+        const double Rz = (g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty;
+        const double tz = ((g.kap[2] + (double)k) - (double)g.s2 * tx - (double)g.s3 * ty) / (double)g.n3;
+        bool masked = false;
+        if (tx == rint(tx) && ty == rint(ty) && Rz == rint(Rz)) {
+            long kk = (-(long)rint(Rz)) % g.n3;
+            if (kk < 0) kk += g.n3;
+            masked = (kk == k);
+        }
+        out[e] = masked ? kMasked
+                        : mix_code(lam_of_turn(tx, 1.0 / g.dlt[0]), lam_of_turn(ty, 1.0 / g.dlt[1]),
+                                   lam_of_turn(tz, 1.0 / g.dlt[2]));
+    }
+}
+
+hipError_t launch_modecode(const Grid& g, unsigned char* out, hipStream_t st) {
+    const long n = (long)g.n1 * g.n2 * g.n3;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_modecode, dim3(blocks), dim3(256), 0, st, g, out);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ preconditioner diagonal
@@ -600,11 +686,22 @@ __global__ void k_precond(Grid g, DeviceTables tb, double* __restrict__ out) {
 }
 
 // ------------------------------------------------------------------ launchers
-static int ept_for(long elems) {
-    long e = (elems + kThreads - 1) / kThreads;
+constexpr int kXThreads = 256;     // x-line kernel work-group
+
+static int pow2_at_least(long e) {
     int p = 1;
     while (p < e) p <<= 1;
     return p;
+}
+
+// plane kernels: enough threads that each owns at most 4 modes (up to 1024 threads; FP64 up to
+// 512 so that the 128 registers a 1024-thread group allows per lane are not exceeded)
+static void plane_shape(long np, int fp64, int* nt, int* ept) {
+    int t = 256;
+    const int tmax = fp64 ? 512 : 1024;
+    while (t < tmax && (np + t - 1) / t > 4) t <<= 1;
+    *nt = t;
+    *ept = pow2_at_least((np + t - 1) / t);
 }
 
 static int xline_tile(int n1) {
@@ -618,6 +715,36 @@ template <typename R>
 static size_t xline_lds_bytes(int n1, int TB) {
     return sizeof(cx<R>) * ((size_t)TB * (n1 + 1) + 2 * n1);
 }
+
+#define PCX_PLANE_DISPATCH(NTV, EPTV, CALL)                     \
+    if (NTV == 1024) {                                          \
+        switch (EPTV) {                                         \
+            case 1: CALL(1024, 1); break;                       \
+            case 2: CALL(1024, 2); break;                       \
+            case 4: CALL(1024, 4); break;                       \
+            case 8: CALL(1024, 8); break;                       \
+            case 16: CALL(1024, 16); break;                     \
+            case 32: CALL(1024, 32); break;                     \
+            case 64: CALL(1024, 64); break;                     \
+            default: return hipErrorInvalidValue;               \
+        }                                                       \
+    } else if (NTV == 512) {                                    \
+        switch (EPTV) {                                         \
+            case 4: CALL(512, 4); break;                        \
+            case 8: CALL(512, 8); break;                        \
+            case 16: CALL(512, 16); break;                      \
+            case 32: CALL(512, 32); break;                      \
+            case 64: CALL(512, 64); break;                      \
+            default: return hipErrorInvalidValue;               \
+        }                                                       \
+    } else {                                                    \
+        switch (EPTV) {                                         \
+            case 1: CALL(256, 1); break;                        \
+            case 2: CALL(256, 2); break;                        \
+            case 4: CALL(256, 4); break;                        \
+            default: return hipErrorInvalidValue;               \
+        }                                                       \
+    }
 
 #define PCX_EPT_DISPATCH(EPTV, CALL) \
     switch (EPTV) {                  \
@@ -636,9 +763,10 @@ static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* 
                             hipStream_t st) {
     dim3 grid(g.n1, nvec);
     const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
-    const int ept = ept_for((long)g.n2 * g.n3);
-#define CALLF(E) hipLaunchKernelGGL((k_plane_fwd<R, E>), grid, dim3(kThreads), lds, st, g, tb, y, t)
-    PCX_EPT_DISPATCH(ept, CALLF)
+    int nt, ept;
+    plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, &nt, &ept);
+#define CALLF(NT, E) hipLaunchKernelGGL((k_plane_fwd<R, NT, E>), grid, dim3(NT), lds, st, g, tb, y, t)
+    PCX_PLANE_DISPATCH(nt, ept, CALLF)
 #undef CALLF
     return hipGetLastError();
 }
@@ -648,9 +776,10 @@ static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* 
                             hipStream_t st) {
     dim3 grid(g.n1, nvec);
     const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
-    const int ept = ept_for((long)g.n2 * g.n3);
-#define CALLA(E) hipLaunchKernelGGL((k_plane_adj<R, E>), grid, dim3(kThreads), lds, st, g, tb, t, z)
-    PCX_EPT_DISPATCH(ept, CALLA)
+    int nt, ept;
+    plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, &nt, &ept);
+#define CALLA(NT, E) hipLaunchKernelGGL((k_plane_adj<R, NT, E>), grid, dim3(NT), lds, st, g, tb, t, z)
+    PCX_PLANE_DISPATCH(nt, ept, CALLA)
 #undef CALLA
     return hipGetLastError();
 }
@@ -662,8 +791,8 @@ static hipError_t xline(const Grid& g, const DeviceTables& tb, const R* scale, c
     const long np = (long)g.n2 * g.n3;
     dim3 grid((unsigned)((np + TB - 1) / TB), nvec);
     const size_t lds = xline_lds_bytes<R>(g.n1, TB);
-    const int ept = ept_for((long)g.n1 * TB);
-#define CALLX(E) hipLaunchKernelGGL((k_xline<R, E, MODE>), grid, dim3(kThreads), lds, st, g, tb, scale, t, u, TB)
+    const int ept = pow2_at_least(((long)g.n1 * TB + kXThreads - 1) / kXThreads);
+#define CALLX(E) hipLaunchKernelGGL((k_xline<R, E, MODE>), grid, dim3(kXThreads), lds, st, g, tb, scale, t, u, TB)
     PCX_EPT_DISPATCH(ept, CALLX)
 #undef CALLX
     return hipGetLastError();
@@ -675,22 +804,6 @@ hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_e
     hipError_t e = plane_fwd<R>(g, tb, y, t, nvec, st);
     if (e != hipSuccess) return e;
     e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
-    if (e != hipSuccess) return e;
-    return plane_adj<R>(g, tb, t, z, nvec, st);
-}
-
-template <typename R>
-hipError_t launch_QS(const Grid& g, const DeviceTables& tb, const R* inv_eps, const cx<R>* y, cx<R>* u, cx<R>* t,
-                     int nvec, hipStream_t st) {
-    hipError_t e = plane_fwd<R>(g, tb, y, t, nvec, st);
-    if (e != hipSuccess) return e;
-    return xline<R, 1>(g, tb, inv_eps, t, u, nvec, st);
-}
-
-template <typename R>
-hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>* u, cx<R>* z, cx<R>* t, int nvec,
-                             hipStream_t st) {
-    hipError_t e = xline<R, 2>(g, tb, nullptr, t, const_cast<cx<R>*>(u), nvec, st);
     if (e != hipSuccess) return e;
     return plane_adj<R>(g, tb, t, z, nvec, st);
 }
@@ -723,6 +836,22 @@ hipError_t time_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps
     return e;
 }
 
+template <typename R>
+hipError_t launch_QS(const Grid& g, const DeviceTables& tb, const R* inv_eps, const cx<R>* y, cx<R>* u, cx<R>* t,
+                     int nvec, hipStream_t st) {
+    hipError_t e = plane_fwd<R>(g, tb, y, t, nvec, st);
+    if (e != hipSuccess) return e;
+    return xline<R, 1>(g, tb, inv_eps, t, u, nvec, st);
+}
+
+template <typename R>
+hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>* u, cx<R>* z, cx<R>* t, int nvec,
+                             hipStream_t st) {
+    hipError_t e = xline<R, 2>(g, tb, nullptr, t, const_cast<cx<R>*>(u), nvec, st);
+    if (e != hipSuccess) return e;
+    return plane_adj<R>(g, tb, t, z, nvec, st);
+}
+
 hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st) {
     const long n = (long)g.n1 * g.n2 * g.n3;
     int blocks = (int)((n + 255) / 256);
@@ -731,36 +860,55 @@ hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* ou
     return hipGetLastError();
 }
 
+template <typename F>
+static hipError_t set_max_lds(F f) {
+    return hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <typename R, int NT, int E>
+static hipError_t set_plane() {
+    hipError_t e = set_max_lds(k_plane_fwd<R, NT, E>);
+    if (e == hipSuccess) e = set_max_lds(k_plane_adj<R, NT, E>);
+    return e;
+}
+
+template <typename R, int E>
+static hipError_t set_xline() {
+    hipError_t e = set_max_lds(k_xline<R, E, 0>);
+    if (e == hipSuccess) e = set_max_lds(k_xline<R, E, 1>);
+    if (e == hipSuccess) e = set_max_lds(k_xline<R, E, 2>);
+    return e;
+}
+
 template <typename R>
 static hipError_t set_lds_limits() {
-    const int maxb = 160 * 1024;
-#define SETP(E)                                                                                            \
-    do {                                                                                                   \
-        hipError_t e1 = hipFuncSetAttribute((const void*)k_plane_fwd<R, E>,                                \
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, maxb);             \
-        if (e1 != hipSuccess) return e1;                                                                   \
-        e1 = hipFuncSetAttribute((const void*)k_plane_adj<R, E>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                 maxb);                                                                    \
-        if (e1 != hipSuccess) return e1;                                                                   \
-        e1 = hipFuncSetAttribute((const void*)k_xline<R, E, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                 maxb);                                                                    \
-        if (e1 != hipSuccess) return e1;                                                                   \
-        e1 = hipFuncSetAttribute((const void*)k_xline<R, E, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                 maxb);                                                                    \
-        if (e1 != hipSuccess) return e1;                                                                   \
-        e1 = hipFuncSetAttribute((const void*)k_xline<R, E, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                 maxb);                                                                    \
-        if (e1 != hipSuccess) return e1;                                                                   \
-    } while (0)
-    SETP(1);
-    SETP(2);
-    SETP(4);
-    SETP(8);
-    SETP(16);
-    SETP(32);
-    SETP(64);
-#undef SETP
-    return hipSuccess;
+    hipError_t e = hipSuccess;
+#define CHK(x) \
+    if (e == hipSuccess) e = (x)
+    CHK((set_plane<R, 1024, 1>()));
+    CHK((set_plane<R, 1024, 2>()));
+    CHK((set_plane<R, 1024, 4>()));
+    CHK((set_plane<R, 1024, 8>()));
+    CHK((set_plane<R, 1024, 16>()));
+    CHK((set_plane<R, 1024, 32>()));
+    CHK((set_plane<R, 1024, 64>()));
+    CHK((set_plane<R, 512, 4>()));
+    CHK((set_plane<R, 512, 8>()));
+    CHK((set_plane<R, 512, 16>()));
+    CHK((set_plane<R, 512, 32>()));
+    CHK((set_plane<R, 512, 64>()));
+    CHK((set_plane<R, 256, 1>()));
+    CHK((set_plane<R, 256, 2>()));
+    CHK((set_plane<R, 256, 4>()));
+    CHK((set_xline<R, 1>()));
+    CHK((set_xline<R, 2>()));
+    CHK((set_xline<R, 4>()));
+    CHK((set_xline<R, 8>()));
+    CHK((set_xline<R, 16>()));
+    CHK((set_xline<R, 32>()));
+    CHK((set_xline<R, 64>()));
+#undef CHK
+    return e;
 }
 
 hipError_t configure_kernels() {

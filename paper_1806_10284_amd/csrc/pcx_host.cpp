@@ -212,7 +212,23 @@ Grid Plan::grid(const double kappa[3]) const {
     g.fx = fx;
     g.fy = fy;
     g.fz = fz;
+    g.codes = (const unsigned char*)codes;
     return g;
+}
+
+int Plan::grid_for(const double kappa[3], Grid* g) {
+    int rc = grow(&codes, &codes_cap, (size_t)n);
+    if (rc) return rc;
+    if (!codes_valid || kappa[0] != codes_kappa[0] || kappa[1] != codes_kappa[1] || kappa[2] != codes_kappa[2]) {
+        codes_valid = false;
+        Grid g0 = grid(kappa);
+        hipError_t e = launch_modecode(g0, (unsigned char*)codes, stream);
+        if (e != hipSuccess) return hip_fail(e, "mode codes");
+        for (int l = 0; l < 3; ++l) codes_kappa[l] = kappa[l];
+        codes_valid = true;
+    }
+    *g = grid(kappa);
+    return PCX_OK;
 }
 
 }  // namespace pcx
@@ -253,38 +269,53 @@ extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_str
         half[k].x = std::cos(ang);
         half[k].y = std::sin(ang);
     }
-    size_t tot64 = 0, tot32 = 0;
-    for (int a = 0; a < 3; ++a) {
-        tot64 += h[a].size();
-        tot32 += h[a].size();
+    // exp(-2 pi i m / M), M = n2 n3
+    const long M = (long)g->n[1] * g->n[2];
+    std::vector<cx<double>> rot(M);
+    for (long m = 0; m < M; ++m) {
+        long mm = m;
+        if (2 * mm > M) mm -= M;
+        const double ang = -2.0 * M_PI * (double)mm / (double)M;
+        rot[m].x = std::cos(ang);
+        rot[m].y = std::sin(ang);
     }
-    tot64 += half.size();
-    e = hipMalloc(&p->tables_mem, tot64 * sizeof(cx<double>) + tot32 * sizeof(cx<float>));
+    size_t tot = 0;
+    for (int a = 0; a < 3; ++a) tot += h[a].size();
+    const size_t bytes = (tot + half.size() + rot.size()) * sizeof(cx<double>) + (tot + rot.size()) * sizeof(cx<float>);
+    e = hipMalloc(&p->tables_mem, bytes);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "hipMalloc tables");
     }
     cx<double>* d64 = (cx<double>*)p->tables_mem;
-    cx<float>* d32 = (cx<float>*)(d64 + tot64);
-    std::vector<cx<float>> f;
-    for (int a = 0; a < 3; ++a) {
+    cx<float>* d32 = (cx<float>*)(d64 + tot + half.size() + rot.size());
+    auto put = [&](cx<double>* dst64, cx<float>* dst32, const std::vector<cx<double>>& src) -> hipError_t {
+        hipError_t r = hipMemcpy(dst64, src.data(), src.size() * sizeof(cx<double>), hipMemcpyHostToDevice);
+        if (r != hipSuccess || !dst32) return r;
+        std::vector<cx<float>> f(src.size());
+        for (size_t m = 0; m < src.size(); ++m) {
+            f[m].x = (float)src[m].x;
+            f[m].y = (float)src[m].y;
+        }
+        return hipMemcpy(dst32, f.data(), f.size() * sizeof(cx<float>), hipMemcpyHostToDevice);
+    };
+    hipError_t ec = hipSuccess;
+    for (int a = 0; a < 3 && ec == hipSuccess; ++a) {
         p->tables.tw64[a] = d64;
         p->tables.tw32[a] = d32;
-        (void)hipMemcpy(d64, h[a].data(), h[a].size() * sizeof(cx<double>), hipMemcpyHostToDevice);
-        f.resize(h[a].size());
-        for (size_t m = 0; m < h[a].size(); ++m) {
-            f[m].x = (float)h[a][m].x;
-            f[m].y = (float)h[a][m].y;
-        }
-        (void)hipMemcpy(d32, f.data(), f.size() * sizeof(cx<float>), hipMemcpyHostToDevice);
+        ec = put(d64, d32, h[a]);
         d64 += h[a].size();
         d32 += h[a].size();
     }
     p->tables.halfz = d64;
-    e = hipMemcpy(d64, half.data(), half.size() * sizeof(cx<double>), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
+    if (ec == hipSuccess) ec = put(d64, nullptr, half);
+    d64 += half.size();
+    p->tables.rot64 = d64;
+    p->tables.rot32 = d32;
+    if (ec == hipSuccess) ec = put(d64, d32, rot);
+    if (ec != hipSuccess) {
         pcx_plan_destroy((pcx_plan*)p);
-        return hip_fail(e, "hipMemcpy tables");
+        return hip_fail(ec, "hipMemcpy tables");
     }
     *out = (pcx_plan*)p;
     return PCX_OK;
@@ -293,7 +324,7 @@ extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_str
 extern "C" void pcx_plan_destroy(pcx_plan* pp) {
     Plan* p = (Plan*)pp;
     if (!p) return;
-    void* bufs[] = {p->tables_mem, p->eps_mem, p->work, p->lob_mem, p->prec, p->gram_part, p->small_mem};
+    void* bufs[] = {p->tables_mem, p->eps_mem, p->work, p->lob_mem, p->prec, p->gram_part, p->small_mem, p->codes};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->pinned) (void)hipHostFree(p->pinned);
@@ -365,7 +396,8 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
     if (rc) return rc;
     rc = ensure_work(nvec);
     if (rc) return rc;
-    const Grid g = grid(kappa);
+    Grid g;
+    if ((rc = grid_for(kappa, &g))) return rc;
     hipError_t e = hipSuccess;
     if (precision == PCX_FP64) {
         auto* w = (cx<double>*)work;
@@ -426,7 +458,8 @@ extern "C" int pcx_time_Ar_kernels(pcx_plan* pp, const double kappa[3], int prec
     int rc = p->check_fits(precision);
     if (rc) return rc;
     if ((rc = p->ensure_work(nvec))) return rc;
-    const Grid g = p->grid(kappa);
+    Grid g;
+    if ((rc = p->grid_for(kappa, &g))) return rc;
     hipError_t e;
     if (precision == PCX_FP64)
         e = time_apply_Ar<double>(g, p->tables, (const double*)p->inv_epsn64, (const cx<double>*)y, (cx<double>*)z,

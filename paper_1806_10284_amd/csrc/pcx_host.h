@@ -50,7 +50,15 @@ struct Plan {
     void* pinned = nullptr;          // pinned host staging for coefficient uploads
     size_t pinned_cap = 0;
 
+    // mixing-basis codes for the last kappa (n bytes), recomputed when kappa changes
+    void* codes = nullptr;
+    size_t codes_cap = 0;
+    double codes_kappa[3] = {0, 0, 0};
+    bool codes_valid = false;
+
     int grow(void** buf, size_t* have, size_t need);
+    // grid description for kappa (computes the mode codes on the plan stream when kappa is new)
+    int grid_for(const double kappa[3], Grid* g);
     Grid grid(const double kappa[3]) const;
     int check_fits(int precision) const;
     int ensure_work(int nvec);

@@ -8,7 +8,6 @@
 
 namespace pcx {
 
-constexpr int kThreads = 256;      // work-group size of every FFT kernel
 constexpr int kMaxPasses = 8;
 constexpr double kMixTau = 1e-3;   // switch to the fallback range basis below Lambda_p^2 / Lambda_q
 
@@ -26,6 +25,7 @@ struct Grid {
     double kap[3];           // kappa_l = k . a_l
     double dlt[3];           // mesh sizes
     FftPlan fx, fy, fz;
+    const unsigned char* codes;  // mixing basis per mode (launch_modecode), n bytes
 };
 
 template <typename R>
@@ -34,11 +34,14 @@ struct alignas(2 * sizeof(R)) cx {
 };
 
 // device-side tables owned by a plan: twiddle LUTs exp(+2 pi i m / N) for the three axes,
-// in both precisions, and the half-turn table exp(i pi k / n3) in FP64.
+// in both precisions, the half-turn table exp(i pi k / n3) in FP64, and the (n2 n3)-th roots
+// of unity exp(-2 pi i m / (n2 n3)) in both precisions.
 struct DeviceTables {
     cx<double>* tw64[3];
     cx<float>* tw32[3];
     cx<double>* halfz;
+    cx<double>* rot64;
+    cx<float>* rot32;
 };
 
 // ---- launchers (pcx_fft.hip) ----
@@ -59,6 +62,8 @@ hipError_t launch_QS(const Grid& g, const DeviceTables& tb, const R* inv_eps, co
 template <typename R>
 hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>* u, cx<R>* z, cx<R>* t,
                              int nvec, hipStream_t st);
+// mixing-basis code per mode for the grid's kappa (n bytes): decided once in FP64
+hipError_t launch_modecode(const Grid& g, unsigned char* out, hipStream_t st);
 // 1/Lambda_q per mode (0 at the masked mode), FP64, n values
 hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st);
 // set per-kernel LDS limits once per process

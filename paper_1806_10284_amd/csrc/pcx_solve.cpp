@@ -345,7 +345,8 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     (void)hipEventCreate(&S.ev0);
     (void)hipEventCreate(&S.ev1);
 
-    const Grid g = p->grid(kappa);
+    Grid g;
+    if ((rc = p->grid_for(kappa, &g))) return rc;
     hipError_t e = launch_precond_diag(g, p->tables, S.prec, p->stream);
     if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner");
 

@@ -8,8 +8,6 @@ namespace pcx {
 #define DEV __device__ __forceinline__
 
 constexpr int kMaxCols = 6 * PCX_MAX_BLOCK;
-constexpr int kGramRows = 32;      // rows staged per sub-tile
-constexpr int kBlk = 4;            // 4 x 4 register tile of Gram entries per thread
 
 template <typename R>
 DEV cx<double> to64(cx<R> a) {
@@ -31,68 +29,107 @@ DEV R* col_ptr(const ColSet& S, int c, long N) {
 }
 
 // ------------------------------------------------------------------ Gram: part[chunk] = A^H B over the chunk rows
-template <typename R>
+// Each work-group stages kGramRows rows of all A and B columns in LDS (row-major, padded), and
+// each thread accumulates BLK x BLK tiles of Gram entries for its pair-blocks in FP64.
+// HERM: B = [A] or [A | A'] (kb = nh ka, nh = 1 or 2; the first ka columns of B are the columns of
+// A) with every ka x ka half of A^H B Hermitian, so A is staged once, as B's first half, and only
+// the block upper triangle of each half is computed (the caller mirrors the rest).
+constexpr int kGramRows = 16;
+constexpr int kMaxPB = 2;      // pair-blocks per thread
+
+template <int BLK, bool HERM>
+DEV void pair_block(int pb, int nbA, int nbB, int* ba, int* bb) {
+    if (!HERM) {
+        *ba = pb / nbB;
+        *bb = pb % nbB;
+        return;
+    }
+    const int tri = nbA * (nbA + 1) / 2;
+    const int h = pb / tri;
+    int rem = pb - h * tri, row = 0;
+    while (rem >= nbA - row) {
+        rem -= nbA - row;
+        ++row;
+    }
+    *ba = row;
+    *bb = h * nbA + row + rem;          // block column within the (ka-aligned) B layout
+}
+
+template <typename R, int BLK, bool HERM>
 __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long rows_per_chunk,
-                                               cx<double>* __restrict__ part, int round) {
+                                               cx<double>* __restrict__ part) {
     extern __shared__ __align__(16) char lds[];
     const int ka = A.total(), kb = B.total();
-    const int ka4 = (ka + kBlk - 1) / kBlk * kBlk, kb4 = (kb + kBlk - 1) / kBlk * kBlk;
-    cx<double>* As = (cx<double>*)lds;                  // [ka4][kGramRows]
-    cx<double>* Bs = As + (size_t)ka4 * kGramRows;       // [kb4][kGramRows]
-    const cx<R>** acol = (const cx<R>**)(Bs + (size_t)kb4 * kGramRows);
+    const int kaP = (ka + BLK - 1) / BLK * BLK;
+    // B columns in LDS: plain, or (HERM) each half padded to kaP so blocks never straddle halves
+    const int kbP = HERM ? (kb / ka) * kaP : (kb + BLK - 1) / BLK * BLK;
+    const int bofs = HERM ? 0 : kaP;                    // first B column in the tile
+    const int ncol = bofs + kbP;
+    const int ldr = ncol + 1;                           // row stride (complex), padded
+    cx<double>* T = (cx<double>*)lds;                   // [kGramRows][ldr]: A columns then B columns
+    const cx<R>** acol = (const cx<R>**)(T + (size_t)kGramRows * ldr);
     const cx<R>** bcol = acol + kMaxCols;
     for (int c = threadIdx.x; c < ka; c += blockDim.x) acol[c] = col_ptr<const cx<R>>(A, c, N);
     for (int c = threadIdx.x; c < kb; c += blockDim.x) bcol[c] = col_ptr<const cx<R>>(B, c, N);
 
     const long r0 = (long)blockIdx.x * rows_per_chunk;
     const long r1 = min(N, r0 + rows_per_chunk);
-    const int nbA = ka4 / kBlk, nbB = kb4 / kBlk;
-    const int PB = nbA * nbB;
-    constexpr int kMaxPB = 2;   // pair-blocks per thread and round
-    const int pb0 = round * kMaxPB * 256;
-    cx<double> acc[kMaxPB][kBlk][kBlk];
+    const int nbA = kaP / BLK, nbB = kbP / BLK;
+    const int PB = HERM ? (kb / ka) * nbA * (nbA + 1) / 2 : nbA * nbB;
+    int pba[kMaxPB], pbb[kMaxPB];
+#pragma unroll
+    for (int p = 0; p < kMaxPB; ++p) {
+        const int pb = threadIdx.x + p * blockDim.x;
+        pba[p] = pbb[p] = -1;
+        if (pb < PB) pair_block<BLK, HERM>(pb, nbA, nbB, &pba[p], &pbb[p]);
+    }
+    cx<double> acc[kMaxPB][BLK][BLK];
 #pragma unroll
     for (int p = 0; p < kMaxPB; ++p)
 #pragma unroll
-        for (int u = 0; u < kBlk; ++u)
+        for (int u = 0; u < BLK; ++u)
 #pragma unroll
-            for (int w = 0; w < kBlk; ++w) acc[p][u][w].x = acc[p][u][w].y = 0.0;
+            for (int w = 0; w < BLK; ++w) acc[p][u][w].x = acc[p][u][w].y = 0.0;
     __syncthreads();
 
     for (long rt = r0; rt < r1; rt += kGramRows) {
         const int rows = (int)min((long)kGramRows, r1 - rt);
-        for (int e = threadIdx.x; e < ka4 * kGramRows; e += blockDim.x) {
+        // column c of the tile: A columns [0, kaP) unless HERM, then B columns (HERM: half h at h kaP)
+        for (int e = threadIdx.x; e < ncol * kGramRows; e += blockDim.x) {
             const int c = e / kGramRows, r = e % kGramRows;
             cx<double> val;
             val.x = val.y = 0.0;
-            if (c < ka && r < rows) val = to64(acol[c][rt + r]);
-            As[e] = val;
-        }
-        for (int e = threadIdx.x; e < kb4 * kGramRows; e += blockDim.x) {
-            const int c = e / kGramRows, r = e % kGramRows;
-            cx<double> val;
-            val.x = val.y = 0.0;
-            if (c < kb && r < rows) val = to64(bcol[c][rt + r]);
-            Bs[e] = val;
+            if (r < rows) {
+                if (c < bofs) {
+                    if (c < ka) val = to64(acol[c][rt + r]);
+                } else {
+                    int cb = c - bofs;
+                    if (HERM) {
+                        const int h = cb / kaP, q = cb % kaP;
+                        cb = q < ka ? h * ka + q : -1;
+                    }
+                    if (cb >= 0 && cb < kb) val = to64(bcol[cb][rt + r]);
+                }
+            }
+            T[(size_t)r * ldr + c] = val;
         }
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < kMaxPB; ++p) {
-            const int pb = pb0 + threadIdx.x + p * blockDim.x;
-            if (pb < PB) {
-                const int ba = pb / nbB, bb = pb % nbB;
-                const cx<double>* ap = As + (size_t)ba * kBlk * kGramRows;
-                const cx<double>* bp = Bs + (size_t)bb * kBlk * kGramRows;
+            if (pba[p] >= 0) {
+                const cx<double>* ap = T + pba[p] * BLK;
+                const cx<double>* bp = T + bofs + pbb[p] * BLK;
+#pragma unroll 4
                 for (int r = 0; r < kGramRows; ++r) {
-                    cx<double> av[kBlk], bv[kBlk];
+                    cx<double> av[BLK], bv[BLK];
 #pragma unroll
-                    for (int u = 0; u < kBlk; ++u) av[u] = ap[u * kGramRows + r];
+                    for (int u = 0; u < BLK; ++u) av[u] = ap[(size_t)r * ldr + u];
 #pragma unroll
-                    for (int w = 0; w < kBlk; ++w) bv[w] = bp[w * kGramRows + r];
+                    for (int w = 0; w < BLK; ++w) bv[w] = bp[(size_t)r * ldr + w];
 #pragma unroll
-                    for (int u = 0; u < kBlk; ++u)
+                    for (int u = 0; u < BLK; ++u)
 #pragma unroll
-                        for (int w = 0; w < kBlk; ++w) {
+                        for (int w = 0; w < BLK; ++w) {
                             // conj(a) * b
                             acc[p][u][w].x += av[u].x * bv[w].x + av[u].y * bv[w].y;
                             acc[p][u][w].y += av[u].x * bv[w].y - av[u].y * bv[w].x;
@@ -105,52 +142,105 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
     cx<double>* out = part + (size_t)blockIdx.x * ka * kb;
 #pragma unroll
     for (int p = 0; p < kMaxPB; ++p) {
-        const int pb = pb0 + threadIdx.x + p * blockDim.x;
-        if (pb < PB) {
-            const int ba = pb / nbB, bb = pb % nbB;
+        if (pba[p] >= 0) {
 #pragma unroll
-            for (int u = 0; u < kBlk; ++u)
+            for (int u = 0; u < BLK; ++u)
 #pragma unroll
-                for (int w = 0; w < kBlk; ++w) {
-                    const int ia = ba * kBlk + u, ib = bb * kBlk + w;
+                for (int w = 0; w < BLK; ++w) {
+                    const int ia = pba[p] * BLK + u;
+                    int ib = pbb[p] * BLK + w;
+                    if (HERM) {
+                        const int h = ib / kaP, q = ib % kaP;
+                        ib = q < ka ? h * ka + q : kb;
+                    }
                     if (ia < ka && ib < kb) out[(size_t)ia * kb + ib] = acc[p][u][w];
                 }
         }
     }
 }
 
-__global__ void k_reduce_parts(const cx<double>* __restrict__ part, int nchunk, int count, cx<double>* __restrict__ out) {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
-        double sx = 0.0, sy = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
-            cx<double> v = part[(size_t)c * count + e];
-            sx += v.x;
-            sy += v.y;
-        }
-        out[e].x = sx;
-        out[e].y = sy;
+// out[e] = sum over chunks of part[c][e]: stage 1 sums chunk groups in parallel, stage 2 the groups
+constexpr int kRedGroups = 32;
+
+__global__ void k_reduce_stage1(const cx<double>* __restrict__ part, int nchunk, int count,
+                                cx<double>* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (e >= count) return;
+    double sx = 0.0, sy = 0.0;
+    for (int c = g; c < nchunk; c += kRedGroups) {
+        const cx<double> v = part[(size_t)c * count + e];
+        sx += v.x;
+        sy += v.y;
     }
+    out[(size_t)g * count + e].x = sx;
+    out[(size_t)g * count + e].y = sy;
+}
+
+__global__ void k_reduce_stage2(const cx<double>* __restrict__ mid, int count, cx<double>* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double sx = 0.0, sy = 0.0;
+    for (int g = 0; g < kRedGroups; ++g) {
+        const cx<double> v = mid[(size_t)g * count + e];
+        sx += v.x;
+        sy += v.y;
+    }
+    out[e].x = sx;
+    out[e].y = sy;
+}
+
+template <typename R, int BLK, bool HERM>
+static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>* part, int chunks, long rpc,
+                            hipStream_t st) {
+    const int ka = A.total(), kb = B.total();
+    const int kaP = (ka + BLK - 1) / BLK * BLK;
+    const int kbP = HERM ? (kb / ka) * kaP : (kb + BLK - 1) / BLK * BLK;
+    const int nbA = kaP / BLK, nbB = kbP / BLK;
+    const int PB = HERM ? (kb / ka) * nbA * (nbA + 1) / 2 : nbA * nbB;
+    if (PB > kMaxPB * 256) return hipErrorInvalidValue;
+    const size_t lds = sizeof(cx<double>) * (size_t)kGramRows * ((HERM ? 0 : kaP) + kbP + 1) +
+                       2 * sizeof(void*) * kMaxCols;
+    hipLaunchKernelGGL((k_gram<R, BLK, HERM>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
+    return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* part, int nchunk, cx<double>* out,
-                       hipStream_t st) {
+                       hipStream_t st, bool herm) {
     const int ka = A.total(), kb = B.total();
     if (ka < 1 || kb < 1 || ka > kMaxCols || kb > kMaxCols) return hipErrorInvalidValue;
-    const int ka4 = (ka + kBlk - 1) / kBlk * kBlk, kb4 = (kb + kBlk - 1) / kBlk * kBlk;
+    if (herm && kb != ka && kb != 2 * ka) return hipErrorInvalidValue;
     long rpc = (N + nchunk - 1) / nchunk;
     rpc = (rpc + kGramRows - 1) / kGramRows * kGramRows;
     const int chunks = (int)((N + rpc - 1) / rpc);
-    const size_t lds = sizeof(cx<double>) * (size_t)(ka4 + kb4) * kGramRows + 2 * sizeof(void*) * kMaxCols;
-    const int PB = (ka4 / kBlk) * (kb4 / kBlk);
-    const int rounds = (PB + 2 * 256 - 1) / (2 * 256);
-    for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL((k_gram<R>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part, r);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    // smallest register tile that still gives >= ~128 pair-blocks, within 2 per thread
+    hipError_t e;
+    auto pbs = [&](int blk) {
+        const int a = (ka + blk - 1) / blk;
+        return herm ? (kb / ka) * a * (a + 1) / 2 : a * ((kb + blk - 1) / blk);
+    };
+    int blk = 4;
+    if (pbs(1) <= 128) blk = 1;
+    else if (pbs(2) <= 256) blk = 2;
+    if (pbs(blk) > kMaxPB * 256) blk = 4;
+    if (herm) {
+        e = blk == 1 ? gram_impl<R, 1, true>(A, B, N, part, chunks, rpc, st)
+            : blk == 2 ? gram_impl<R, 2, true>(A, B, N, part, chunks, rpc, st)
+                       : gram_impl<R, 4, true>(A, B, N, part, chunks, rpc, st);
+    } else {
+        e = blk == 1 ? gram_impl<R, 1, false>(A, B, N, part, chunks, rpc, st)
+            : blk == 2 ? gram_impl<R, 2, false>(A, B, N, part, chunks, rpc, st)
+                       : gram_impl<R, 4, false>(A, B, N, part, chunks, rpc, st);
     }
+    if (e != hipSuccess) return e;
     const int count = ka * kb;
-    hipLaunchKernelGGL(k_reduce_parts, dim3((count + 255) / 256), dim3(256), 0, st, part, chunks, count, out);
+    cx<double>* mid = part + (size_t)chunks * count;
+    hipLaunchKernelGGL(k_reduce_stage1, dim3((count + 255) / 256, kRedGroups), dim3(256), 0, st, part, chunks, count,
+                       mid);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_stage2, dim3((count + 255) / 256), dim3(256), 0, st, mid, count, out);
     return hipGetLastError();
 }
 
@@ -371,17 +461,30 @@ hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double s
     return hipGetLastError();
 }
 
+template <typename R, int BLK, bool HERM>
+static hipError_t set_gram_lds() {
+    return hipFuncSetAttribute((const void*)k_gram<R, BLK, HERM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024);
+}
+
 hipError_t configure_block_kernels() {
-    const int maxb = 160 * 1024;
-    hipError_t e = hipFuncSetAttribute((const void*)k_gram<float>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_gram<double>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
+    hipError_t e = hipSuccess;
+#define G(R, B, H) \
+    if (e == hipSuccess) e = set_gram_lds<R, B, H>()
+    G(float, 1, false); G(float, 2, false); G(float, 4, false);
+    G(float, 1, true); G(float, 2, true); G(float, 4, true);
+    G(double, 1, false); G(double, 2, false); G(double, 4, false);
+    G(double, 1, true); G(double, 2, true); G(double, 4, true);
+#undef G
+    return e;
 }
 
 template hipError_t launch_random<float>(cx<float>*, long, unsigned long long, double, hipStream_t);
 template hipError_t launch_random<double>(cx<double>*, long, unsigned long long, double, hipStream_t);
-template hipError_t launch_gram<float>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t);
-template hipError_t launch_gram<double>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t);
+template hipError_t launch_gram<float>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t,
+                                       bool);
+template hipError_t launch_gram<double>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t,
+                                        bool);
 template hipError_t launch_combine<float>(const ColSet&, const cx<double>*, const ColSet&, long, hipStream_t);
 template hipError_t launch_combine<double>(const ColSet&, const cx<double>*, const ColSet&, long, hipStream_t);
 template hipError_t launch_residual<float>(const ColSet&, const ColSet&, const double*, const double*, long,

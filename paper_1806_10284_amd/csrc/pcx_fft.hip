@@ -212,9 +212,9 @@ DEV void stockham_pass(cx<R>* buf, int N, int Ns, int nlines, int es, int ls, co
 // pass (lines are independent, so a chunk runs all its passes before the next chunk starts).
 constexpr int kEpc = 4;
 
-template <typename R, int EPT, int NT>
+template <typename R, int EPC, int NT>
 DEV void fft_lines(cx<R>* buf, const FftPlan& fp, int nlines, int es, int ls, const cx<R>* tw, int sign) {
-    const int lpc = (kEpc * NT) / fp.n > 0 ? (kEpc * NT) / fp.n : 1;
+    const int lpc = (EPC * NT) / fp.n > 0 ? (EPC * NT) / fp.n : 1;
 #pragma unroll 1
     for (int l0 = 0; l0 < nlines; l0 += lpc) {
         const int nl = nlines - l0 < lpc ? nlines - l0 : lpc;
@@ -224,11 +224,11 @@ DEV void fft_lines(cx<R>* buf, const FftPlan& fp, int nlines, int es, int ls, co
         for (int p = 0; p < fp.npass; ++p) {
             const int rad = fp.rad[p];
             switch (rad) {
-                case 8: stockham_pass<R, 8, 1, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
-                case 4: stockham_pass<R, 4, 1, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
-                case 2: stockham_pass<R, 2, 2, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
-                case 3: stockham_pass<R, 3, 2, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
-                default: stockham_pass<R, 5, 1, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 8: stockham_pass<R, 8, (EPC + 7) / 8, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 4: stockham_pass<R, 4, (EPC + 3) / 4, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 2: stockham_pass<R, 2, (EPC + 1) / 2, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                case 3: stockham_pass<R, 3, (EPC + 2) / 3, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
+                default: stockham_pass<R, 5, (EPC + 4) / 5, NT>(b0, fp.n, Ns, nl, es, ls, tw, sign); break;
             }
             Ns *= rad;
         }
@@ -336,13 +336,14 @@ struct PlaneLds {
     cx<double>* lamy;
     cx<double>* halfz;
     cx<double>* rowz;
+    double* phi3;
 };
 
 template <typename R>
 __host__ DEV size_t plane_lds_bytes(int n2, int n3) {
     size_t b = sizeof(cx<R>) * ((size_t)n2 * (n3 + 1) + 2 * n3 + 2 * n2);
     b = (b + 15) & ~(size_t)15;
-    b += sizeof(cx<double>) * (n3 + 2 * n2);
+    b += sizeof(cx<double>) * (n3 + 2 * n2) + sizeof(double) * n2;
     return b;
 }
 
@@ -359,6 +360,7 @@ DEV PlaneLds<R> plane_lds(char* base, int n2, int n3) {
     L.halfz = (cx<double>*)(base + off);
     L.rowz = L.halfz + n3;
     L.lamy = L.rowz + n2;
+    L.phi3 = (double*)(L.lamy + n2);
     return L;
 }
 
@@ -383,6 +385,7 @@ DEV cx<double> plane_setup(const Grid& g, const DeviceTables& tb, int i, PlaneLd
         const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)n2;
         L.lamy[j] = lam_of_turn(ty, 1.0 / g.dlt[1]);
         const double p3 = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)n3;
+        L.phi3[j] = p3;
         double s, c;
         sincospi(p3, &s, &c);
         L.rowz[j] = mk<double>(c, s);
@@ -397,16 +400,21 @@ DEV cx<double> lam_z(const PlaneLds<R>& L, int j, int k, double inv_dz) {
     return lam_from_halfturn(h.y, h.x, inv_dz);
 }
 
-// exp(2 pi i c phi3(i, j))
-template <typename R>
-DEV cx<R> z_twiddle(const PlaneLds<R>& L, const cx<R>* __restrict__ rot, int c, int j, int s3, int M) {
+// exp(2 pi i c phi3(i, j)): FP64 as the product of the per-plane factor and a root of unity from
+// the plan's table; FP32 by sincospif of the turn c phi3 reduced in FP64.
+DEV cx<double> z_twiddle(const PlaneLds<double>& L, const cx<double>* __restrict__ rot, int c, int j, int s3, int M) {
     int m = (c * j * s3) % M;
     if (m < 0) m += M;
     return cmul(L.twc[c], rot[m]);
 }
+DEV cx<float> z_twiddle(const PlaneLds<float>& L, const cx<float>* __restrict__ rot, int c, int j, int s3, int M) {
+    return cis_turns<float>((double)c * L.phi3[j]);
+}
 
 // ------------------------------------------------------------------ kernel 1: W y, then z and y inverse DFTs
 // y: [v][2][n1][n2][n3]   ->   t: [v][3][n1][n3][n2];   grid (n1, nvec), NT threads.
+// Each thread owns the modes e = tid + s NT (s < EPT): their y values and z-twiddles stay in
+// registers for the three components.
 template <typename R, int NT, int EPT>
 __global__ void __launch_bounds__(NT) k_plane_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
                                                    cx<R>* __restrict__ t) {
@@ -421,33 +429,83 @@ __global__ void __launch_bounds__(NT) k_plane_fwd(Grid g, DeviceTables tb, const
     const cx<double> lamx = plane_setup<R, NT>(g, tb, i, L);
     const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
     const unsigned char* codes = g.codes + (long)i * np;
-    __syncthreads();
     const double idz = 1.0 / g.dlt[2];
     const cx<R>* yb = y + (long)v * 2 * n + (long)i * np;
+    // modes per thread small enough: y and the z-twiddles of the owned modes stay in registers
+    constexpr bool kRegY = sizeof(R) == 4 ? EPT <= 4 : EPT <= 8;
+    constexpr int NY = kRegY ? EPT : 1;
+    cx<R> y1[NY], y2[NY], tw[NY];
+    if (kRegY) {
+#pragma unroll
+        for (int s = 0; s < NY; ++s) {
+            const int e = threadIdx.x + s * NT;
+            if (e < np) {
+                y1[s] = yb[e];
+                y2[s] = yb[n + e];
+            }
+        }
+    }
+    __syncthreads();
+    if (kRegY) {
+#pragma unroll
+        for (int s = 0; s < NY; ++s) {
+            const int e = threadIdx.x + s * NT;
+            if (e < np) tw[s] = z_twiddle(L, rot, e % n3, e / n3, g.s3, np);
+        }
+    }
 #pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         // u_l = W_l1 y1 + W_l2 y2 into the plane [j][k]
-#pragma unroll 1
-        for (int e = threadIdx.x; e < np; e += NT) {
-            const int j = e / n3, k = e % n3;
-            const int code = codes[e];
-            cx<R> u = mk<R>((R)0, (R)0);
-            if (code != kMasked) {
-                cx<R> w1, w2;
-                w_row_code<R>(lamx, L.lamy[j], lam_z(L, j, k, idz), code, l, &w1, &w2);
-                u = cmul(w1, yb[e]) + cmul(w2, yb[n + e]);
+        if (kRegY) {
+#pragma unroll
+            for (int s = 0; s < NY; ++s) {
+                const int e = threadIdx.x + s * NT;
+                if (e < np) {
+                    const int j = e / n3, k = e % n3;
+                    const int code = codes[e];
+                    cx<R> u = mk<R>((R)0, (R)0);
+                    if (code != kMasked) {
+                        cx<R> w1, w2;
+                        w_row_code<R>(lamx, L.lamy[j], lam_z(L, j, k, idz), code, l, &w1, &w2);
+                        u = cmul(w1, y1[s]) + cmul(w2, y2[s]);
+                    }
+                    L.plane[j * ld + k] = u;
+                }
             }
-            L.plane[j * ld + k] = u;
-        }
-        __syncthreads();
-        fft_lines<R, EPT, NT>(L.plane, g.fz, n2, 1, ld, L.twz, +1);    // k -> c along rows j
+        } else {
 #pragma unroll 1
-        for (int e = threadIdx.x; e < np; e += NT) {
-            const int j = e / n3, c = e % n3;
-            L.plane[j * ld + c] = cmul(L.plane[j * ld + c], z_twiddle(L, rot, c, j, g.s3, np));
+            for (int e = threadIdx.x; e < np; e += NT) {
+                const int j = e / n3, k = e % n3;
+                const int code = codes[e];
+                cx<R> u = mk<R>((R)0, (R)0);
+                if (code != kMasked) {
+                    cx<R> w1, w2;
+                    w_row_code<R>(lamx, L.lamy[j], lam_z(L, j, k, idz), code, l, &w1, &w2);
+                    u = cmul(w1, yb[e]) + cmul(w2, yb[n + e]);
+                }
+                L.plane[j * ld + k] = u;
+            }
         }
         __syncthreads();
-        fft_lines<R, EPT, NT>(L.plane, g.fy, n3, ld, 1, L.twy, +1);    // j -> b along columns c
+        fft_lines<R, kEpc, NT>(L.plane, g.fz, n2, 1, ld, L.twz, +1);    // k -> c along rows j
+        if (kRegY) {
+#pragma unroll
+            for (int s = 0; s < NY; ++s) {
+                const int e = threadIdx.x + s * NT;
+                if (e < np) {
+                    const int j = e / n3, c = e % n3;
+                    L.plane[j * ld + c] = cmul(L.plane[j * ld + c], tw[s]);
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int e = threadIdx.x; e < np; e += NT) {
+                const int j = e / n3, c = e % n3;
+                L.plane[j * ld + c] = cmul(L.plane[j * ld + c], z_twiddle(L, rot, c, j, g.s3, np));
+            }
+        }
+        __syncthreads();
+        fft_lines<R, kEpc, NT>(L.plane, g.fy, n3, ld, 1, L.twy, +1);    // j -> b along columns c
         // write t[v][l][i][c][b] = plane[b][c] * exp(2 pi i b phi2)
         cx<R>* tb_out = t + ((long)v * 3 + l) * n + (long)i * np;
 #pragma unroll 1
@@ -479,9 +537,16 @@ __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const
     const double idz = 1.0 / g.dlt[2];
     constexpr bool kRegAcc = sizeof(R) == 4 ? EPT <= 4 : EPT <= 8;   // accumulators in registers
     constexpr int NA = kRegAcc ? EPT : 1;
-    cx<R> acc1[NA], acc2[NA];
+    cx<R> acc1[NA], acc2[NA], tw[NA];
 #pragma unroll
     for (int s = 0; s < NA; ++s) acc1[s] = acc2[s] = mk<R>((R)0, (R)0);
+    if (kRegAcc) {
+#pragma unroll
+        for (int s = 0; s < NA; ++s) {
+            const int e = threadIdx.x + s * NT;
+            if (e < np) tw[s] = z_twiddle(L, rot, e % n3, e / n3, g.s3, np);
+        }
+    }
 #pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         const cx<R>* tin = t + ((long)v * 3 + l) * n + (long)i * np;
@@ -491,14 +556,25 @@ __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const
             L.plane[b * ld + c] = cmulc(tin[e], L.twb[b]);
         }
         __syncthreads();
-        fft_lines<R, EPT, NT>(L.plane, g.fy, n3, ld, 1, L.twy, -1);    // b -> j along columns c
+        fft_lines<R, kEpc, NT>(L.plane, g.fy, n3, ld, 1, L.twy, -1);    // b -> j along columns c
+        if (kRegAcc) {
+#pragma unroll
+            for (int s = 0; s < NA; ++s) {
+                const int e = threadIdx.x + s * NT;
+                if (e < np) {
+                    const int j = e / n3, c = e % n3;
+                    L.plane[j * ld + c] = cmulc(L.plane[j * ld + c], tw[s]);
+                }
+            }
+        } else {
 #pragma unroll 1
-        for (int e = threadIdx.x; e < np; e += NT) {
-            const int j = e / n3, c = e % n3;
-            L.plane[j * ld + c] = cmulc(L.plane[j * ld + c], z_twiddle(L, rot, c, j, g.s3, np));
+            for (int e = threadIdx.x; e < np; e += NT) {
+                const int j = e / n3, c = e % n3;
+                L.plane[j * ld + c] = cmulc(L.plane[j * ld + c], z_twiddle(L, rot, c, j, g.s3, np));
+            }
         }
         __syncthreads();
-        fft_lines<R, EPT, NT>(L.plane, g.fz, n2, 1, ld, L.twz, -1);    // c -> k along rows j
+        fft_lines<R, kEpc, NT>(L.plane, g.fz, n2, 1, ld, L.twz, -1);    // c -> k along rows j
         if (kRegAcc) {
             // accumulate W^H v in registers
 #pragma unroll
@@ -593,7 +669,7 @@ __global__ void __launch_bounds__(256) k_xline(Grid g, DeviceTables tb, const R*
                 buf[ql * ld + ii] = tl[(long)ii * np + q0 + ql];
             }
             __syncthreads();
-            fft_lines<R, EPT, 256>(buf, g.fx, qn, 1, ld, twx, +1);            // i -> a
+            fft_lines<R, (EPT < 16 ? EPT : 16), 256>(buf, g.fx, qn, 1, ld, twx, +1);            // i -> a
         } else {
             // load u[(q0 + ql) * n1 + a] -> buf[ql][a] with the conjugate x twiddle
             for (int e = threadIdx.x; e < tot; e += 256) {
@@ -621,7 +697,7 @@ __global__ void __launch_bounds__(256) k_xline(Grid g, DeviceTables tb, const R*
             }
             continue;
         }
-        fft_lines<R, EPT, 256>(buf, g.fx, qn, 1, ld, twx, -1);                // a -> i
+        fft_lines<R, (EPT < 16 ? EPT : 16), 256>(buf, g.fx, qn, 1, ld, twx, -1);                // a -> i
         for (int e = threadIdx.x; e < tot; e += 256) {
             const int ii = e / qn, ql = e % qn;
             tl[(long)ii * np + q0 + ql] = buf[ql * ld + ii];
@@ -696,10 +772,16 @@ static int pow2_at_least(long e) {
 
 // plane kernels: enough threads that each owns at most 4 modes (up to 1024 threads; FP64 up to
 // 512 so that the 128 registers a 1024-thread group allows per lane are not exceeded)
+static int g_plane_threads = 0;   // 0: automatic; 256 / 512 / 1024 force the work-group size
+
+void set_plane_threads(int nt) { g_plane_threads = nt; }
+int get_plane_threads() { return g_plane_threads; }
+
 static void plane_shape(long np, int fp64, int* nt, int* ept) {
     int t = 256;
     const int tmax = fp64 ? 512 : 1024;
     while (t < tmax && (np + t - 1) / t > 4) t <<= 1;
+    if (g_plane_threads == 256 || g_plane_threads == 512 || (g_plane_threads == 1024 && !fp64)) t = g_plane_threads;
     *nt = t;
     *ept = pow2_at_least((np + t - 1) / t);
 }
@@ -742,6 +824,10 @@ static size_t xline_lds_bytes(int n1, int TB) {
             case 1: CALL(256, 1); break;                        \
             case 2: CALL(256, 2); break;                        \
             case 4: CALL(256, 4); break;                        \
+            case 8: CALL(256, 8); break;                        \
+            case 16: CALL(256, 16); break;                      \
+            case 32: CALL(256, 32); break;                      \
+            case 64: CALL(256, 64); break;                      \
             default: return hipErrorInvalidValue;               \
         }                                                       \
     }
@@ -900,6 +986,10 @@ static hipError_t set_lds_limits() {
     CHK((set_plane<R, 256, 1>()));
     CHK((set_plane<R, 256, 2>()));
     CHK((set_plane<R, 256, 4>()));
+    CHK((set_plane<R, 256, 8>()));
+    CHK((set_plane<R, 256, 16>()));
+    CHK((set_plane<R, 256, 32>()));
+    CHK((set_plane<R, 256, 64>()));
     CHK((set_xline<R, 1>()));
     CHK((set_xline<R, 2>()));
     CHK((set_xline<R, 4>()));

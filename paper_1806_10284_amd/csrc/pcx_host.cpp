@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -176,6 +177,7 @@ static hipError_t g_config_status = hipErrorNotReady;
 
 static int ensure_configured() {
     if (g_config_status == hipErrorNotReady) {
+        if (const char* env = std::getenv("PCX_PLANE_THREADS")) set_plane_threads(std::atoi(env));
         g_config_status = configure_kernels();
         if (g_config_status == hipSuccess) g_config_status = configure_block_kernels();
     }

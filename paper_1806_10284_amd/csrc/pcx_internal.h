@@ -66,6 +66,9 @@ hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>*
 hipError_t launch_modecode(const Grid& g, unsigned char* out, hipStream_t st);
 // 1/Lambda_q per mode (0 at the masked mode), FP64, n values
 hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st);
+// work-group size of the plane kernels: 0 = automatic, else 256 / 512 / 1024 (FP64: at most 512)
+void set_plane_threads(int nt);
+int get_plane_threads();
 // set per-kernel LDS limits once per process
 hipError_t configure_kernels();
 
@@ -106,10 +109,13 @@ inline ColSet concat(const ColSet& A, const ColSet& B) {
     return s;
 }
 
-// out (ka x kb, row-major) = A^H B with FP64 accumulation; part: workspace of nchunk * ka * kb complex.
+// out (ka x kb, row-major) = A^H B with FP64 accumulation; part: workspace of (nchunk + 32) * ka * kb
+// complex.  herm: B = [A] or [A | A'] (kb = ka or 2 ka) with every ka x ka half Hermitian; only the
+// entries whose register blocks lie on or above the block diagonal of each half are written, the
+// rest must be mirrored by the caller (mirror_upper does it on the host).
 template <typename R>
 hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* part, int nchunk, cx<double>* out,
-                       hipStream_t st);
+                       hipStream_t st, bool herm = false);
 // Y[:, m] = sum_k S[:, k] C[k, m]  (C: ks x m row-major FP64 complex, device).  Y must not
 // overlap S.
 template <typename R>

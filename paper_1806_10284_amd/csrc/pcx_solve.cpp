@@ -77,16 +77,25 @@ struct Solver {
         return rc;
     }
 
-    // G (ka x kb) = A^H B on the host
+    // G (ka x kb) = A^H B on the host.  herm: B = [A] or [A | AA] with each ka x ka half Hermitian;
+    // the device computes the upper part and the lower part is mirrored here.
     template <typename R>
-    int gram(const ColSet& A, const ColSet& B, std::vector<zc>& G) {
+    int gram(const ColSet& A, const ColSet& B, std::vector<zc>& G, bool herm = false) {
         const int ka = A.total(), kb = B.total();
-        hipError_t e = launch_gram<R>(A, B, N, gram_part, gram_chunks, dev_small, p->stream);
+        hipError_t e = launch_gram<R>(A, B, N, gram_part, gram_chunks, dev_small, p->stream, herm);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: gram");
         G.resize((size_t)ka * kb);
         e = hipMemcpyAsync(G.data(), dev_small, sizeof(zc) * ka * kb, hipMemcpyDeviceToHost, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: gram copy");
-        return sync();
+        int rc = sync();
+        if (rc || !herm) return rc;
+        for (int h = 0; h < kb / ka; ++h)
+            for (int i = 0; i < ka; ++i) {
+                zc* row = G.data() + (size_t)i * kb + (size_t)h * ka;
+                row[i] = zc(row[i].real(), 0.0);
+                for (int j = 0; j < i; ++j) row[j] = std::conj(G[(size_t)j * kb + (size_t)h * ka + i]);
+            }
+        return PCX_OK;
     }
 
     // Y = S C with C (ks x m) from the host.  The coefficients go through a ring of pinned host
@@ -111,7 +120,7 @@ struct Solver {
     template <typename R>
     int orthonormalize(cx<R>*& Y, cx<R>*& T, int m) {
         std::vector<zc> G, C;
-        int rc = gram<R>(colset(Y, m), colset(Y, m), G);
+        int rc = gram<R>(colset(Y, m), colset(Y, m), G, true);
         if (rc) return rc;
         orthonormalizer(m, G, C);
         rc = combine<R>(colset(Y, m), C, colset(T, m));
@@ -140,11 +149,14 @@ struct Solver {
     // Rayleigh-Ritz on the b columns of X alone (start of a phase)
     template <typename R>
     int rr_block(Blocks<R>& B) {
-        std::vector<zc> GA, GB;
-        int rc = gram<R>(colset(B.X, b), colset(B.AX, b), GA);
+        std::vector<zc> G, GA((size_t)b * b), GB((size_t)b * b);
+        int rc = gram<R>(colset(B.X, b), colset(B.X, b, B.AX, b), G, true);   // X^H [X | AX]
         if (rc) return rc;
-        rc = gram<R>(colset(B.X, b), colset(B.X, b), GB);
-        if (rc) return rc;
+        for (int r = 0; r < b; ++r)
+            for (int c = 0; c < b; ++c) {
+                GB[(size_t)r * b + c] = G[(size_t)r * 2 * b + c];
+                GA[(size_t)r * b + c] = G[(size_t)r * 2 * b + b + c];
+            }
         std::vector<zc> C;
         if (!rayleigh_ritz(b, GA, GB, b, 1e-14, theta, C)) return fail(PCX_E_NOCONV, "pcx_solve: start block is singular");
         if ((rc = combine<R>(colset(B.X, b), C, colset(B.T1, b)))) return rc;
@@ -220,7 +232,7 @@ struct Solver {
                 ColSet S = withP ? colset(B.X, b, B.W, na, B.P, np) : colset(B.X, b, B.W, na);
                 ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
                 std::vector<zc> G, GB((size_t)k * k), GA((size_t)k * k);
-                if ((rc = gram<R>(S, concat(S, AS), G))) return rc;     // S^H [S | AS]
+                if ((rc = gram<R>(S, concat(S, AS), G, true))) return rc;     // S^H [S | AS]
                 for (int r = 0; r < k; ++r)
                     for (int c = 0; c < k; ++c) {
                         GB[(size_t)r * k + c] = G[(size_t)r * 2 * k + c];
@@ -318,7 +330,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if ((rc = p->grow(&p->lob_mem, &p->lob_cap, bytes64 + bytes32))) return rc;
     if ((rc = p->grow(&p->prec, &p->prec_cap, n * sizeof(double)))) return rc;
     S.gram_chunks = (int)std::min<long>(1024, std::max<long>(1, N / 1024));
-    const size_t gp = (size_t)S.gram_chunks * (3 * b) * (6 * b) * sizeof(cx<double>);
+    const size_t gp = (size_t)(S.gram_chunks + 32) * (3 * b) * (6 * b) * sizeof(cx<double>);
     const size_t rp = (size_t)S.gram_chunks * b * sizeof(double);
     if ((rc = p->grow(&p->gram_part, &p->gram_part_cap, gp + rp))) return rc;
     const size_t gram_out = (size_t)(3 * b) * (6 * b) * sizeof(cx<double>);

@@ -56,6 +56,7 @@ typedef enum pcx_status {
 enum { PCX_FP64 = 0, PCX_FP32 = 1 };                 /* arithmetic / storage precision */
 enum { PCX_EPS_YEE3 = 0, PCX_EPS_VOXEL = 1 };        /* permittivity layouts */
 enum { PCX_MODE_FP64 = 0, PCX_MODE_FP32_REFINE = 1, PCX_MODE_FP32 = 2 };
+enum { PCX_VARIANT_AUTO = 0, PCX_VARIANT_GENERIC = 1 };  /* kernel variants of the A_r path */
 
 #define PCX_MAX_N 256      /* largest supported n1, n2, n3 */
 #define PCX_MAX_BLOCK 64   /* largest LOBPCG block */
@@ -94,6 +95,15 @@ void pcx_plan_destroy(pcx_plan *p);
  * owned by each grid point (PCX_EPS_VOXEL).  Every value must be finite and > 0
  * (else PCX_E_ARG).  Copied to the device (1/eps in FP64 and FP32). */
 int pcx_plan_set_eps(pcx_plan *p, const double *eps, int layout);
+
+/* Kernel variant used by the apply calls and the eigensolver of this plan.
+ * PCX_VARIANT_AUTO (default): the fixed-size kernels compiled for common grid
+ * shapes (all transform lengths known at compile time, the three field
+ * components of a plane staged together) where the grid and precision have
+ * them, else the generic kernels.  PCX_VARIANT_GENERIC: runtime-sized kernels
+ * for every grid.  Both compute the same A_r (Section 5.1, Algorithms 5.1 and
+ * 5.2) up to rounding order.  Errors: PCX_E_ARG (null plan, unknown variant). */
+int pcx_plan_set_variant(pcx_plan *p, int variant);
 
 /* z = A_r y (eq. NFSEP) for nvec vectors.  y, z: device, 2n complex each, in
  * `precision`; y and z may not overlap.  Errors: PCX_E_ARG (nvec out of

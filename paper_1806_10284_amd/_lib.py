@@ -11,6 +11,7 @@ PCX_OK, PCX_E_ARG, PCX_E_SIZE, PCX_E_LATTICE, PCX_E_NOCONV, PCX_E_OOM, PCX_E_DEV
 PCX_FP64, PCX_FP32 = 0, 1
 PCX_EPS_YEE3, PCX_EPS_VOXEL = 0, 1
 PCX_MODE_FP64, PCX_MODE_FP32_REFINE, PCX_MODE_FP32 = 0, 1, 2
+PCX_VARIANT_AUTO, PCX_VARIANT_GENERIC = 0, 1
 PCX_MAX_N = 256
 PCX_MAX_BLOCK = 64
 
@@ -57,6 +58,7 @@ _SIGS = [
                                         ctypes.POINTER(ctypes.c_void_p)]),
     ("pcx_plan_destroy", None, [ctypes.c_void_p]),
     ("pcx_plan_set_eps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    ("pcx_plan_set_variant", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("pcx_apply_Ar", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int]),
     ("pcx_apply_QS", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -87,6 +89,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1806_10284_amd.build`")
+    try:
+        # torch first: its HIP runtime is then the one the library binds to, so device memory and
+        # streams from torch are valid in the library's calls
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, res, args in _SIGS:
         fn = getattr(lib, name)

@@ -102,6 +102,10 @@ class Plan:
             raise ValueError(f"eps has {e.size} values, expected {want}")
         L.check(self._lib.pcx_plan_set_eps(self._ptr, e.ctypes.data_as(ctypes.c_void_p), int(layout)))
 
+    def pcx_plan_set_variant(self, variant: int):
+        """PCX_VARIANT_AUTO (fixed-size kernels where available) or PCX_VARIANT_GENERIC."""
+        L.check(self._lib.pcx_plan_set_variant(self._ptr, int(variant)))
+
     # -- operators
     def _check_block(self, t, per_vec: int, precision: int, name: str) -> int:
         torch = _torch()

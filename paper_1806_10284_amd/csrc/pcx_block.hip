@@ -35,7 +35,7 @@ DEV R* col_ptr(const ColSet& S, int c, long N) {
 // A) with every ka x ka half of A^H B Hermitian, so A is staged once, as B's first half, and only
 // the block upper triangle of each half is computed (the caller mirrors the rest).
 constexpr int kGramRows = 16;
-constexpr int kMaxPB = 2;      // pair-blocks per thread
+constexpr int kMaxPB = 2;      // pair-blocks per thread (MPB = 1 or 2 per instantiation)
 
 template <int BLK, bool HERM>
 DEV void pair_block(int pb, int nbA, int nbB, int* ba, int* bb) {
@@ -55,7 +55,7 @@ DEV void pair_block(int pb, int nbA, int nbB, int* ba, int* bb) {
     *bb = h * nbA + row + rem;          // block column within the (ka-aligned) B layout
 }
 
-template <typename R, int BLK, bool HERM>
+template <typename R, int BLK, bool HERM, int MPB>
 __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long rows_per_chunk,
                                                cx<double>* __restrict__ part) {
     extern __shared__ __align__(16) char lds[];
@@ -76,16 +76,16 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
     const long r1 = min(N, r0 + rows_per_chunk);
     const int nbA = kaP / BLK, nbB = kbP / BLK;
     const int PB = HERM ? (kb / ka) * nbA * (nbA + 1) / 2 : nbA * nbB;
-    int pba[kMaxPB], pbb[kMaxPB];
+    int pba[MPB], pbb[MPB];
 #pragma unroll
-    for (int p = 0; p < kMaxPB; ++p) {
+    for (int p = 0; p < MPB; ++p) {
         const int pb = threadIdx.x + p * blockDim.x;
         pba[p] = pbb[p] = -1;
         if (pb < PB) pair_block<BLK, HERM>(pb, nbA, nbB, &pba[p], &pbb[p]);
     }
-    cx<double> acc[kMaxPB][BLK][BLK];
+    cx<double> acc[MPB][BLK][BLK];
 #pragma unroll
-    for (int p = 0; p < kMaxPB; ++p)
+    for (int p = 0; p < MPB; ++p)
 #pragma unroll
         for (int u = 0; u < BLK; ++u)
 #pragma unroll
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
         }
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < kMaxPB; ++p) {
+        for (int p = 0; p < MPB; ++p) {
             if (pba[p] >= 0) {
                 const cx<double>* ap = T + pba[p] * BLK;
                 const cx<double>* bp = T + bofs + pbb[p] * BLK;
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
     }
     cx<double>* out = part + (size_t)blockIdx.x * ka * kb;
 #pragma unroll
-    for (int p = 0; p < kMaxPB; ++p) {
+    for (int p = 0; p < MPB; ++p) {
         if (pba[p] >= 0) {
 #pragma unroll
             for (int u = 0; u < BLK; ++u)
@@ -201,7 +201,10 @@ static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>
     if (PB > kMaxPB * 256) return hipErrorInvalidValue;
     const size_t lds = sizeof(cx<double>) * (size_t)kGramRows * ((HERM ? 0 : kaP) + kbP + 1) +
                        2 * sizeof(void*) * kMaxCols;
-    hipLaunchKernelGGL((k_gram<R, BLK, HERM>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
+    if (PB <= 256)
+        hipLaunchKernelGGL((k_gram<R, BLK, HERM, 1>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
+    else
+        hipLaunchKernelGGL((k_gram<R, BLK, HERM, 2>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
     return hipGetLastError();
 }
 
@@ -245,7 +248,10 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
 }
 
 // ------------------------------------------------------------------ Y = S C
-constexpr int kOutChunk = 8;
+// One thread per row: outputs in chunks of kOutChunk FP64 accumulators, S re-read per chunk
+// (from L2 when the work-group's rows are still resident); C[k][o] is uniform across the
+// work-group and comes through the scalar cache.
+constexpr int kOutChunk = 16;
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __restrict__ C, ColSet Y, long N) {
@@ -337,12 +343,15 @@ __global__ void __launch_bounds__(256) k_residual(ColSet X, ColSet AX, const dou
     }
 }
 
-__global__ void k_reduce_real(const double* __restrict__ part, int nchunk, int count, double* __restrict__ out) {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * count + e];
-        out[e] = s;
-    }
+// out[e] = sum over chunks of part[c][e]; one work-group per entry e
+__global__ void __launch_bounds__(256) k_reduce_real(const double* __restrict__ part, int nchunk, int count,
+                                                      double* __restrict__ out) {
+    __shared__ double red[4];
+    const int e = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += blockDim.x) s += part[(size_t)c * count + e];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[e] = s;
 }
 
 template <typename R>
@@ -356,7 +365,7 @@ hipError_t launch_residual(const ColSet& X, const ColSet& AX, const double* thet
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int count = X.total();
-    hipLaunchKernelGGL(k_reduce_real, dim3((count + 255) / 256), dim3(256), 0, st, part, chunks, count, out);
+    hipLaunchKernelGGL(k_reduce_real, dim3(count), dim3(256), 0, st, part, chunks, count, out);
     return hipGetLastError();
 }
 
@@ -463,7 +472,10 @@ hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double s
 
 template <typename R, int BLK, bool HERM>
 static hipError_t set_gram_lds() {
-    return hipFuncSetAttribute((const void*)k_gram<R, BLK, HERM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram<R, BLK, HERM, 1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_gram<R, BLK, HERM, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                160 * 1024);
 }
 

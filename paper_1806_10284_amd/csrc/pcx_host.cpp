@@ -215,6 +215,7 @@ Grid Plan::grid(const double kappa[3]) const {
     g.fy = fy;
     g.fz = fz;
     g.codes = (const unsigned char*)codes;
+    g.generic = variant == PCX_VARIANT_GENERIC ? 1 : 0;
     return g;
 }
 
@@ -431,6 +432,14 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
 }
 
 }  // namespace pcx
+
+extern "C" int pcx_plan_set_variant(pcx_plan* p, int variant) {
+    if (!p) return fail(PCX_E_ARG, "pcx_plan_set_variant: null plan");
+    if (variant != PCX_VARIANT_AUTO && variant != PCX_VARIANT_GENERIC)
+        return fail(PCX_E_ARG, "pcx_plan_set_variant: unknown variant %d", variant);
+    ((Plan*)p)->variant = variant;
+    return PCX_OK;
+}
 
 extern "C" int pcx_apply_Ar(pcx_plan* p, const double kappa[3], int precision, const void* y, void* z, int nvec) {
     if (!p) return fail(PCX_E_ARG, "pcx_apply_Ar: null plan");

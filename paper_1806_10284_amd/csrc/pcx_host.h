@@ -56,6 +56,9 @@ struct Plan {
     double codes_kappa[3] = {0, 0, 0};
     bool codes_valid = false;
 
+    // kernel variant of the A_r path (PCX_VARIANT_*)
+    int variant = PCX_VARIANT_AUTO;
+
     int grow(void** buf, size_t* have, size_t need);
     // grid description for kappa (computes the mode codes on the plan stream when kappa is new)
     int grid_for(const double kappa[3], Grid* g);

@@ -26,6 +26,7 @@ struct Grid {
     double dlt[3];           // mesh sizes
     FftPlan fx, fy, fz;
     const unsigned char* codes;  // mixing basis per mode (launch_modecode), n bytes
+    int generic;             // 1: runtime-sized kernels only; 0: fixed-size kernels where they exist
 };
 
 template <typename R>
@@ -71,6 +72,22 @@ void set_plane_threads(int nt);
 int get_plane_threads();
 // set per-kernel LDS limits once per process
 hipError_t configure_kernels();
+
+// ---- fixed-size kernels (pcx_fixed.hip) ----
+// Each launcher sets *done when it has a kernel for the grid (and launched it), else leaves the
+// work to the generic kernels.
+template <typename R>
+hipError_t launch_fixed_plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, int nvec,
+                                  hipStream_t st, bool* done);
+template <typename R>
+hipError_t launch_fixed_plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, int nvec,
+                                  hipStream_t st, bool* done);
+template <typename R>
+hipError_t launch_fixed_xline(const Grid& g, const DeviceTables& tb, const R* scale, cx<R>* t, int nvec,
+                              hipStream_t st, bool* done);
+bool fixed_plane_available(int n2, int n3, int fp64);
+bool fixed_xline_available(int n1, long np, int fp64);
+hipError_t configure_fixed_kernels();
 
 // ---- block operations (pcx_block.hip) ----
 // A set of vectors of length N given as up to kMaxSeg runs of contiguous columns (column stride N).

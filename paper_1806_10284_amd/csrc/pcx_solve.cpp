@@ -21,7 +21,19 @@
 #include "pcx_dense.h"
 #include "pcx_host.h"
 
+#ifndef PCX_ORTHO_PASSES
+#define PCX_ORTHO_PASSES 2
+#endif
+#ifndef PCX_FP32_STALL
+#define PCX_FP32_STALL 12
+#endif
+
 namespace pcx {
+
+// classical Gram-Schmidt passes of W against X per iteration
+constexpr int kOrthoPasses = PCX_ORTHO_PASSES;
+// iterations without a 10% drop of the worst residual that end a reduced-precision phase
+constexpr int kFp32Stall = PCX_FP32_STALL;
 
 // ---------------------------------------------------------------- the solver
 
@@ -196,7 +208,7 @@ struct Solver {
             if (worst < 0.9 * best) {
                 best = worst;
                 stall = 0;
-            } else if (sizeof(R) == 4 && worst < 1e-2 && ++stall >= 12) {
+            } else if (sizeof(R) == 4 && worst < 1e-2 && ++stall >= kFp32Stall) {
                 return PCX_OK;
             }
             ++iters;
@@ -207,8 +219,8 @@ struct Solver {
             for (int j = 0; j < b; ++j)
                 if (resid[j] > tol) act.push_back(j);
             const int na = (int)act.size();
-            // W_act <- W_act - X (X^H W_act), selecting the active columns in the same pass; twice
-            for (int pass = 0; pass < 2; ++pass) {
+            // W_act <- W_act - X (X^H W_act), selecting the active columns in the first pass
+            for (int pass = 0; pass < kOrthoPasses; ++pass) {
                 const int wc = pass == 0 ? b : na;
                 std::vector<zc> G, C((size_t)(b + wc) * na, zc(0, 0));
                 if ((rc = gram<R>(colset(B.X, b), colset(B.W, wc), G))) return rc;
@@ -329,7 +341,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     const size_t bytes32 = use32 ? 10 * (size_t)b * N * sizeof(cx<float>) : 0;
     if ((rc = p->grow(&p->lob_mem, &p->lob_cap, bytes64 + bytes32))) return rc;
     if ((rc = p->grow(&p->prec, &p->prec_cap, n * sizeof(double)))) return rc;
-    S.gram_chunks = (int)std::min<long>(1024, std::max<long>(1, N / 1024));
+    S.gram_chunks = (int)std::min<long>(1024, std::max<long>(1, N / 512));
     const size_t gp = (size_t)(S.gram_chunks + 32) * (3 * b) * (6 * b) * sizeof(cx<double>);
     const size_t rp = (size_t)S.gram_chunks * b * sizeof(double);
     if ((rc = p->grow(&p->gram_part, &p->gram_part_cap, gp + rp))) return rc;

@@ -27,7 +27,10 @@ def say(*a):
     print("[gpu-case]", *a, file=sys.stderr, flush=True)
 
 
-def _setup(avec, n, kappa, eps, nvec=1, seed=0):
+VARIANTS = {"auto": 0, "generic": 1}
+
+
+def _setup(avec, n, kappa, eps, nvec=1, seed=0, variant="auto"):
     import torch
     from paper_1806_10284_amd import Plan, pcx_geometry
     g = pcx_geometry(avec, *n)
@@ -35,6 +38,7 @@ def _setup(avec, n, kappa, eps, nvec=1, seed=0):
     assert tuple(g.shift) == tuple(int(s) for s in og.shift)
     plan = Plan(g, max_vectors=max(nvec, 4))
     plan.pcx_plan_set_eps(eps)
+    plan.pcx_plan_set_variant(VARIANTS[variant])
     y = S.random_block(seed, 2 * og.npts, nvec)
     return plan, og, spectrum(og, kappa), y
 
@@ -64,18 +68,23 @@ CASES = [
     ("ortho_60_48_40", S.ORTHO, (60, 48, 40), (0.3, 0.1, 0.2)),
     ("gamma_sc8", S.SC, (8, 8, 8), (0.0, 0.0, 0.0)),
     ("integer_kappa", S.triclinic(4), (6, 8, 5), (1.0, -1.0, 2.0)),
+    # shapes with fixed-size kernels (planes 16x16, 32x32, 40x40; x lines 16, 32, 64)
+    ("gamma_sc16", S.SC, (16, 16, 16), (0.0, 0.0, 0.0)),
+    ("tri_32_40_40", S.triclinic(6), (32, 40, 40), (0.37, -0.21, 0.08)),
+    ("fcc_64_32_32", S.FCC, (64, 32, 32), (0.25, 0.5, -0.125)),
 ]
 
 
+@pytest.mark.parametrize("variant", ["auto", "generic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name,avec,n,kappa", CASES)
-def test_apply_Ar_parity(name, avec, n, kappa, prec):
+def test_apply_Ar_parity(name, avec, n, kappa, prec, variant):
     import torch
-    rng = np.random.default_rng(hash(name) % 2**32)
+    rng = np.random.default_rng(sum(map(ord, name)))
     npts = n[0] * n[1] * n[2]
     eps = rng.uniform(1.0, 13.0, (3, npts))
-    plan, og, spec, y = _setup(avec, n, kappa, eps, nvec=3, seed=7)
-    say("apply_Ar", name, n, prec)
+    plan, og, spec, y = _setup(avec, n, kappa, eps, nvec=3, seed=7, variant=variant)
+    say("apply_Ar", name, n, prec, variant)
     z = torch.empty_like(_to_dev(y, prec))
     plan.pcx_apply_Ar(kappa, _to_dev(y, prec), z)
     torch.cuda.synchronize()
@@ -110,16 +119,17 @@ def test_QS_and_adjoint_and_eigvec(name, avec, n, kappa, prec):
         _cmp(z[:, v], QS_adjoint(spec, ur[:, v]), prec, "QS_adjoint")
 
 
+@pytest.mark.parametrize("variant", ["auto", "generic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_apply_Ar_fcc64_full_size(prec):
+def test_apply_Ar_fcc64_full_size(prec, variant):
     """The 64^3 diamond workload: every output entry against the oracle (numpy FFT route)."""
     import torch
     n = (64, 64, 64)
     og = lattice_geometry(S.FCC, *n)
     eps = S.sample_yee(S.FCC, n, og.shift, S.diamond_shapes(), 13.0, 1.0)
     kappa = (0.5, 0.0, 0.5)
-    plan, og, spec, y = _setup(S.FCC, n, kappa, eps, nvec=1, seed=11)
-    say("apply_Ar fcc64", prec)
+    plan, og, spec, y = _setup(S.FCC, n, kappa, eps, nvec=1, seed=11, variant=variant)
+    say("apply_Ar fcc64", prec, variant)
     z = torch.empty_like(_to_dev(y, prec))
     plan.pcx_apply_Ar(kappa, _to_dev(y, prec), z)
     torch.cuda.synchronize()

@@ -128,6 +128,10 @@ typedef struct pcx_opts {
     unsigned long long seed;  /* start block */
     int precondition;    /* 1: precondition with Lambda_q^{-1} (the Sigma_r^{-2} scaling) */
     int verbose;         /* 1: print one line per iteration to stderr */
+    const void *y0;      /* warm start: device, n_y0 vectors of 2n complex128 (e.g. the y of a
+                            nearby solve), copied into the first n_y0 columns of the start
+                            block; NULL: plane-wave start only */
+    int n_y0;            /* 0 <= n_y0 <= block */
 } pcx_opts;
 
 void pcx_opts_default(pcx_opts *o);

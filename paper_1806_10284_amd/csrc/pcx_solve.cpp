@@ -22,7 +22,7 @@
 #include "pcx_host.h"
 
 #ifndef PCX_ORTHO_PASSES
-#define PCX_ORTHO_PASSES 2
+#define PCX_ORTHO_PASSES 1
 #endif
 #ifndef PCX_FP32_STALL
 #define PCX_FP32_STALL 12
@@ -301,6 +301,8 @@ extern "C" void pcx_opts_default(pcx_opts* o) {
     o->seed = 12345;
     o->precondition = 1;
     o->verbose = 0;
+    o->y0 = nullptr;
+    o->n_y0 = 0;
 }
 
 extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx_opts* opts, double* lambda,
@@ -327,6 +329,8 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (S.o.mode < PCX_MODE_FP64 || S.o.mode > PCX_MODE_FP32) return fail(PCX_E_ARG, "pcx_solve: bad mode");
     if (!(S.o.tol > 0) || S.o.max_iter < 1) return fail(PCX_E_ARG, "pcx_solve: bad tolerance or max_iter");
     if (b > p->max_vectors) return fail(PCX_E_ARG, "pcx_solve: block %d exceeds the plan's max_vectors", b);
+    if (S.o.n_y0 < 0 || S.o.n_y0 > b || (S.o.n_y0 > 0 && !S.o.y0))
+        return fail(PCX_E_ARG, "pcx_solve: warm start needs 0 <= n_y0 <= block (%d) and y0", b);
     S.nev = nev;
     S.b = b;
     const bool use32 = S.o.mode != PCX_MODE_FP64;
@@ -399,6 +403,14 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
             one.y = 0;
             e2 = hipMemcpyAsync(X + (size_t)c * N + (c % 2) * n + mode, &one, sizeof(C), hipMemcpyHostToDevice, p->stream);
             if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: start block");
+        }
+        if (S.o.n_y0 > 0) {
+            const long cnt = (long)S.o.n_y0 * N;
+            if (std::is_same<C, cx<double>>::value)
+                e2 = hipMemcpyAsync((void*)X, S.o.y0, cnt * sizeof(cx<double>), hipMemcpyDeviceToDevice, p->stream);
+            else
+                e2 = launch_convert((const cx<double>*)S.o.y0, (cx<float>*)(void*)X, cnt, p->stream);
+            if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: warm start");
         }
         return S.sync();
     };

@@ -49,11 +49,70 @@ def kernel_bytes_per_vector(n: int, fp64: bool) -> dict:
     return {"plane_fwd": 5 * c * n, "xline": 6 * c * n + 3 * r * n, "plane_adj": 5 * c * n}
 
 
+KERNEL_SOURCES = ("pcx_fft.hip", "pcx_fixed.hip", "pcx_dev.h", "pcx_internal.h")
+
+
 def kernel_source_hash() -> str:
+    """Digest of the matvec kernel sources; counter summaries taken on other sources are not used."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1806_10284_amd", "csrc", "pcx_fft.hip"), "rb") as f:
-        h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1806_10284_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
+
+
+# kernel-name prefix in a rocprofv3 trace -> (A_r kernel, precision)
+KERNEL_KEYS = [
+    ("pcx::k_p3_fwd<float", "plane_fwd_fp32"), ("pcx::k_p3_fwd<double", "plane_fwd_fp64"),
+    ("pcx::k_plane_fwd<float", "plane_fwd_fp32"), ("pcx::k_plane_fwd<double", "plane_fwd_fp64"),
+    ("pcx::k_p3_adj<float", "plane_adj_fp32"), ("pcx::k_p3_adj<double", "plane_adj_fp64"),
+    ("pcx::k_plane_adj<float", "plane_adj_fp32"), ("pcx::k_plane_adj<double", "plane_adj_fp64"),
+    ("pcx::k_xl_fixed<float", "xline_fp32"), ("pcx::k_xl_fixed<double", "xline_fp64"),
+    ("pcx::k_xline<float", "xline_fp32"), ("pcx::k_xline<double", "xline_fp64"),
+]
+
+
+def summarize_traffic(fetch_csv: str, write_csv: str, out_json: str):
+    """Per-dispatch HBM bytes of the A_r kernels from two rocprofv3 --pmc runs of
+    `bench.py --profile-kernels` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
+    what the same counter reads for the 512 MiB calibration copy of that run."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        acc = defaultdict(list)
+        copy = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            name = r["Kernel_Name"]
+            key = next((k for p, k in KERNEL_KEYS if name.startswith("void " + p) or name.startswith(p)), None)
+            if key:
+                acc[key].append(v)
+            elif "copy" in name.lower() or "elementwise" in name.lower():
+                copy.append(v)
+        return {k: sum(v) / len(v) for k, v in acc.items()}, (max(copy) if copy else None)
+
+    fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = 512 * 1024
+    cal_f = copy_kib / fcopy if fcopy else 1.0
+    cal_w = copy_kib / wcopy if wcopy else 1.0
+    per_f32 = kernel_bytes_per_vector(N_GRID[0] * N_GRID[1] * N_GRID[2], False)
+    per_f64 = kernel_bytes_per_vector(N_GRID[0] * N_GRID[1] * N_GRID[2], True)
+    kernels = {}
+    for key in sorted(set(fetch) & set(write)):
+        base, prec = key.rsplit("_", 1)
+        alg = (per_f64 if prec == "fp64" else per_f32)[base] * ROOF_VECTORS
+        hbm = (fetch[key] * cal_f + write[key] * cal_w) * 1024.0
+        kernels[key] = {"hbm_bytes_per_launch": hbm, "fetch_kib": fetch[key], "write_kib": write[key],
+                        "algorithmic_bytes_per_launch": alg, "vectors": ROOF_VECTORS}
+    out = {"kernel_source_hash": kernel_source_hash(), "calibration": {"fetch": cal_f, "write": cal_w},
+           "kernels": kernels, "note": "FCC diamond 64^3, 32-vector block; commands in traffic_fcc64.md"}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
 
 
 def load_traffic(dominant: str, fp64: bool):
@@ -138,7 +197,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the 32-vector A_r block (and a calibration copy) for rocprofv3 counters")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_fcc64.json from two rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        out = summarize_traffic(*args.summarize_traffic, os.path.join(ROOT, "profiles", "traffic_fcc64.json"))
+        print(json.dumps(out, indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this solver is single-device (k-points shard across GPUs "
               "without communication; see DESIGN.md)", file=sys.stderr)
@@ -163,7 +228,7 @@ def main():
         print("[bench] calibration copy: 5 x 512 MiB", file=sys.stderr, flush=True)
         return
 
-    solve_kw = dict(mode=mode, tol=1e-9, want_y=False)
+    solve_kw = dict(mode=mode, tol=1e-10, want_y=False)
     for w in range(args.warmup):
         lam, _, _, st = plan.pcx_solve(kappa, NEV, **solve_kw)
         print(f"[bench] warmup {w}: {st.iterations} it, {st.matvecs} matvecs, {st.seconds:.3f} s",
@@ -189,6 +254,13 @@ def main():
     per32 = sum(kernel_bytes_per_vector(n, False).values())
     per64 = sum(kernel_bytes_per_vector(n, True).values())
     solve_gbs = (matvecs32 * per32 + (matvecs - matvecs32) * per64) / el / 1e9
+
+    # per-band agreement of the timed mode with the plain FP64 path (same tolerance)
+    per_band = None
+    if args.mode != "fp64":
+        lam64, _, _, _ = plan.pcx_solve(kappa, NEV, mode=PCX_MODE_FP64, tol=1e-10, want_y=False)
+        per_band = [float(abs(a - b) / b) for a, b in zip(lam, lam64)]
+        print(f"[bench] per-band |lambda - lambda_fp64| / lambda_fp64: {per_band}", file=sys.stderr, flush=True)
 
     fp64_roof = args.mode == "fp64"
     kern, tot = roofline_block(torch, plan, kappa, fp64_roof, args.reps)
@@ -222,7 +294,8 @@ def main():
         "solve": {"iterations": iters, "matvecs_per_solve": matvecs / args.steps,
                   "fp32_matvec_fraction": matvecs32 / max(matvecs, 1),
                   "matvec_time_fraction": tm / el, "matvec_gbs_in_solve": solve_gbs,
-                  "lambda": [float(x) for x in lam],
+                  "tol": solve_kw["tol"], "lambda": [float(x) for x in lam],
+                  "rel_diff_vs_fp64_per_band": per_band,
                   "omega_over_2pi": [math.sqrt(max(x, 0)) / (2 * math.pi) for x in lam]},
         "block_matvec": {"vectors": ROOF_VECTORS, "precision": "fp64" if fp64_roof else "fp32",
                          "matvecs_per_s": tot["matvecs_per_s"], "gbs": tot["gbs"],

@@ -29,8 +29,10 @@ DEV R* col_ptr(const ColSet& S, int c, long N) {
 }
 
 // ------------------------------------------------------------------ Gram: part[chunk] = A^H B over the chunk rows
-// Each work-group stages kGramRows rows of all A and B columns in LDS (row-major, padded), and
-// each thread accumulates BLK x BLK tiles of Gram entries for its pair-blocks in FP64.
+// Each work-group stages kGramRows rows of all A and B columns in LDS, and each thread accumulates
+// a BLK x BLK tile of Gram entries (a pair of column blocks) in FP64.  Within a staged row the
+// columns are interleaved by block: column u of block q sits at u * nblocks + q, so the lanes of a
+// wave, which hold consecutive blocks, read consecutive 16-byte words (no bank conflicts).
 // HERM: B = [A] or [A | A'] (kb = nh ka, nh = 1 or 2; the first ka columns of B are the columns of
 // A) with every ka x ka half of A^H B Hermitian, so A is staged once, as B's first half, and only
 // the block upper triangle of each half is computed (the caller mirrors the rest).
@@ -94,38 +96,42 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
 
     for (long rt = r0; rt < r1; rt += kGramRows) {
         const int rows = (int)min((long)kGramRows, r1 - rt);
-        // column c of the tile: A columns [0, kaP) unless HERM, then B columns (HERM: half h at h kaP)
+        // padded column c of the tile: A columns [0, kaP) unless HERM, then B columns (HERM: half
+        // h at h kaP); stored at its interleaved position
         for (int e = threadIdx.x; e < ncol * kGramRows; e += blockDim.x) {
             const int c = e / kGramRows, r = e % kGramRows;
             cx<double> val;
             val.x = val.y = 0.0;
-            if (r < rows) {
-                if (c < bofs) {
-                    if (c < ka) val = to64(acol[c][rt + r]);
-                } else {
-                    int cb = c - bofs;
-                    if (HERM) {
-                        const int h = cb / kaP, q = cb % kaP;
-                        cb = q < ka ? h * ka + q : -1;
-                    }
-                    if (cb >= 0 && cb < kb) val = to64(bcol[cb][rt + r]);
+            int pos;
+            if (c < bofs) {
+                pos = (c % BLK) * nbA + c / BLK;
+                if (r < rows && c < ka) val = to64(acol[c][rt + r]);
+            } else {
+                int cb = c - bofs;
+                pos = bofs + (cb % BLK) * nbB + cb / BLK;
+                if (HERM) {
+                    const int h = cb / kaP, q = cb % kaP;
+                    cb = q < ka ? h * ka + q : -1;
                 }
+                if (r < rows && cb >= 0 && cb < kb) val = to64(bcol[cb][rt + r]);
             }
-            T[(size_t)r * ldr + c] = val;
+            T[(size_t)r * ldr + pos] = val;
         }
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < MPB; ++p) {
             if (pba[p] >= 0) {
-                const cx<double>* ap = T + pba[p] * BLK;
-                const cx<double>* bp = T + bofs + pbb[p] * BLK;
+                // HERM: A is B's first half, interleaved with B's block count
+                const int sa = HERM ? nbB : nbA;
+                const cx<double>* ap = T + pba[p];
+                const cx<double>* bp = T + bofs + pbb[p];
 #pragma unroll 4
                 for (int r = 0; r < kGramRows; ++r) {
                     cx<double> av[BLK], bv[BLK];
 #pragma unroll
-                    for (int u = 0; u < BLK; ++u) av[u] = ap[(size_t)r * ldr + u];
+                    for (int u = 0; u < BLK; ++u) av[u] = ap[(size_t)r * ldr + u * sa];
 #pragma unroll
-                    for (int w = 0; w < BLK; ++w) bv[w] = bp[(size_t)r * ldr + w];
+                    for (int w = 0; w < BLK; ++w) bv[w] = bp[(size_t)r * ldr + w * nbB];
 #pragma unroll
                     for (int u = 0; u < BLK; ++u)
 #pragma unroll
@@ -217,24 +223,34 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     long rpc = (N + nchunk - 1) / nchunk;
     rpc = (rpc + kGramRows - 1) / kGramRows * kGramRows;
     const int chunks = (int)((N + rpc - 1) / rpc);
-    // smallest register tile that still gives >= ~128 pair-blocks, within 2 per thread
+    // register tile: every thread of the group waits for the busiest, so the cost of a tile size
+    // is (rounds of 256 pair-blocks) x BLK^2; the cheapest within 2 rounds, larger BLK on ties
+    // (fewer LDS reads per product)
     hipError_t e;
     auto pbs = [&](int blk) {
         const int a = (ka + blk - 1) / blk;
         return herm ? (kb / ka) * a * (a + 1) / 2 : a * ((kb + blk - 1) / blk);
     };
     int blk = 4;
-    if (pbs(1) <= 128) blk = 1;
-    else if (pbs(2) <= 256) blk = 2;
-    if (pbs(blk) > kMaxPB * 256) blk = 4;
-    if (herm) {
-        e = blk == 1 ? gram_impl<R, 1, true>(A, B, N, part, chunks, rpc, st)
-            : blk == 2 ? gram_impl<R, 2, true>(A, B, N, part, chunks, rpc, st)
-                       : gram_impl<R, 4, true>(A, B, N, part, chunks, rpc, st);
-    } else {
-        e = blk == 1 ? gram_impl<R, 1, false>(A, B, N, part, chunks, rpc, st)
-            : blk == 2 ? gram_impl<R, 2, false>(A, B, N, part, chunks, rpc, st)
-                       : gram_impl<R, 4, false>(A, B, N, part, chunks, rpc, st);
+    long best = -1;
+    for (int t = 4; t >= 1; --t) {
+        const int pb = pbs(t);
+        if (pb > kMaxPB * 256) continue;
+        const long cost = (long)((pb + 255) / 256) * t * t;
+        if (best < 0 || cost < best) {
+            best = cost;
+            blk = t;
+        }
+    }
+    switch (blk * 2 + (herm ? 1 : 0)) {
+        case 2: e = gram_impl<R, 1, false>(A, B, N, part, chunks, rpc, st); break;
+        case 3: e = gram_impl<R, 1, true>(A, B, N, part, chunks, rpc, st); break;
+        case 4: e = gram_impl<R, 2, false>(A, B, N, part, chunks, rpc, st); break;
+        case 5: e = gram_impl<R, 2, true>(A, B, N, part, chunks, rpc, st); break;
+        case 6: e = gram_impl<R, 3, false>(A, B, N, part, chunks, rpc, st); break;
+        case 7: e = gram_impl<R, 3, true>(A, B, N, part, chunks, rpc, st); break;
+        case 8: e = gram_impl<R, 4, false>(A, B, N, part, chunks, rpc, st); break;
+        default: e = gram_impl<R, 4, true>(A, B, N, part, chunks, rpc, st); break;
     }
     if (e != hipSuccess) return e;
     const int count = ka * kb;
@@ -483,10 +499,10 @@ hipError_t configure_block_kernels() {
     hipError_t e = hipSuccess;
 #define G(R, B, H) \
     if (e == hipSuccess) e = set_gram_lds<R, B, H>()
-    G(float, 1, false); G(float, 2, false); G(float, 4, false);
-    G(float, 1, true); G(float, 2, true); G(float, 4, true);
-    G(double, 1, false); G(double, 2, false); G(double, 4, false);
-    G(double, 1, true); G(double, 2, true); G(double, 4, true);
+    G(float, 1, false); G(float, 2, false); G(float, 3, false); G(float, 4, false);
+    G(float, 1, true); G(float, 2, true); G(float, 3, true); G(float, 4, true);
+    G(double, 1, false); G(double, 2, false); G(double, 3, false); G(double, 4, false);
+    G(double, 1, true); G(double, 2, true); G(double, 3, true); G(double, 4, true);
 #undef G
     return e;
 }

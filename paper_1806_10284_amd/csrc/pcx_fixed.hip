@@ -132,8 +132,8 @@ struct P3 {
 };
 
 // Fills the per-plane tables of plane i; returns Lambda_1(i).
-template <typename R, int N2, int N3, int NT>
-DEV cx<double> p3_setup(const Grid& g, const DeviceTables& tb, int i, const P3<R, N2, N3>& L) {
+template <typename R, int N2, int N3, int NT, typename LT>
+DEV cx<double> p3_setup(const Grid& g, const DeviceTables& tb, int i, const LT& L) {
     const double tx = (g.kap[0] + (double)i) / (double)g.n1;
     const cx<double> L0 = lam_of_turn(tx, 1.0 / g.dlt[0]);
     const cx<R>* twz_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[2] : (const cx<R>*)tb.tw32[2];
@@ -167,8 +167,8 @@ DEV cx<double> p3_setup(const Grid& g, const DeviceTables& tb, int i, const P3<R
 // W (3 x 2) of mode (j, k) in precision R.  Code 0 (the paper's basis) from the per-row tables:
 //   W[l,0] = sum_{m != l} conj(L_m)(L_m - L_l) / Lp,  W[:,1] = sqrt(Lq) conj(L2 - L1, L0 - L2, L1 - L0) / Lp
 // with the differences and the sums Lq, Lp^2 in FP64; other codes through w_row_code.
-template <typename R, int N2, int N3>
-DEV void p3_w(const P3<R, N2, N3>& L, cx<double> L0, int j, int k, int code, double idz, cx<R> w[3][2]) {
+template <typename R, int N2, int N3, typename LT>
+DEV void p3_w(const LT& L, cx<double> L0, int j, int k, int code, double idz, cx<R> w[3][2]) {
     const cx<double> h = cmul(L.halfz[k], L.rowz[j]);
     const cx<double> L2 = lam_from_halfturn(h.y, h.x, idz);
     const cx<double> L1 = L.lamy[j];
@@ -195,8 +195,8 @@ DEV void p3_w(const P3<R, N2, N3>& L, cx<double> L0, int j, int k, int code, dou
 
 // exp(2 pi i c phi3(i, j)) = twc[c] * exp(-2 pi i ((c j s3) mod N2 N3) / (N2 N3)), rot = the table of
 // (N2 N3)-th roots, s3m = s3 mod N2 N3 in [0, N2 N3)
-template <typename R, int N2, int N3>
-DEV cx<R> p3_ztw(const P3<R, N2, N3>& L, const cx<R>* __restrict__ rot, int c, int j, int s3m) {
+template <typename R, int N2, int N3, typename LT>
+DEV cx<R> p3_ztw(const LT& L, const cx<R>* __restrict__ rot, int c, int j, int s3m) {
     constexpr int M = N2 * N3;
     return cmul(L.twc[c], rot[(c * j * s3m) % M]);
 }
@@ -415,6 +415,9 @@ __global__ void __launch_bounds__(NT) k_xl_fixed(Grid g, DeviceTables tb, const 
 
 // ------------------------------------------------------------------ instantiation table
 // Plane kernels: (N2, N3, threads).  Work-groups of up to 1024 threads, about 4 modes per thread.
+#ifndef PCX_P3_NT64
+#define PCX_P3_NT64 1024
+#endif
 #define PCX_P3_SIZES(X) \
     X(16, 16, 256)      \
     X(32, 32, 256)      \
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(NT) k_xl_fixed(Grid g, DeviceTables tb, const 
     X(48, 40, 512)      \
     X(48, 48, 576)      \
     X(40, 40, 448)      \
-    X(64, 64, 1024)
+    X(64, 64, PCX_P3_NT64)
 
 // x-line kernels: (N1, tile, threads)
 #define PCX_XL_SIZES(X) \

@@ -110,6 +110,14 @@ int pcx_plan_set_variant(pcx_plan *p, int variant);
  * [1, max_vectors], eps not set), PCX_E_DEVICE. */
 int pcx_apply_Ar(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z, int nvec);
 
+/* z = A_r(k) y for nk wave vectors in ONE launch of each matvec kernel: the blocks
+ * of all wave vectors of a band-structure path go through the same three kernels, each
+ * work-group picking its wave vector's phases and mode codes.  kappas: host, 3*nk
+ * doubles; y, z: device, nk*nvec_per_k vectors of 2n complex, ordered [k][v].
+ * Requires nk*nvec_per_k <= max_vectors.  Same errors as pcx_apply_Ar. */
+int pcx_apply_Ar_multi(pcx_plan *p, int nk, const double *kappas, int precision, const void *y, void *z,
+                       int nvec_per_k);
+
 /* u = Q_r Sigma_r y = (I_3 (x) T)(W y) (Section 5.1): 2n -> 3n real space. Device. */
 int pcx_apply_QS(pcx_plan *p, const double kappa[3], int precision, const void *y, void *u, int nvec);
 
@@ -155,6 +163,30 @@ typedef struct pcx_stats {
  * PCX_E_NOCONV (lambda and stats filled), PCX_E_OOM, PCX_E_DEVICE. */
 int pcx_solve(pcx_plan *p, const double kappa[3], int nev, const pcx_opts *opts,
               double *lambda, void *y_out, void *x_out, pcx_stats *stats);
+
+/* Independent problems (plans x wave vectors) solved concurrently: one GEP per wave
+ * vector (Section 5.2), so the problems of a band structure or of several lattices share
+ * nothing but the device.  Problem q (plan-major: the nk[0] wave vectors of plans[0], then
+ * those of plans[1], ...) has kappa = kappas[3q..3q+2] and returns lambda[q*nev ..] (host),
+ * y_out[q] (device, nev * 2n complex128, or NULL; y_out itself may be NULL) and stats[q]
+ * (or stats == NULL).  nworkers host threads (0: min(#problems, 4)), each with its own HIP
+ * stream and private copies of the plans' workspaces and 1/eps, take problems in turn, so
+ * the device overlaps the kernels of different problems.  opts as for pcx_solve (shared).
+ * Every plan must have its permittivity set and live on the current device.  Returns the
+ * first error of any problem (PCX_E_NOCONV only if nothing worse happened); all problems are
+ * attempted. */
+int pcx_solve_batch(pcx_plan *const *plans, int nplans, const int *nk, const double *kappas, int nev,
+                    const pcx_opts *opts, int nworkers, double *lambda, void *const *y_out, pcx_stats *stats);
+
+/* Autotuner: times one A_r application of nvec vectors at kappa in `precision` for every
+ * kernel variant the plan's grid has (the fixed-size kernels if compiled for this plane
+ * shape and precision; the generic plane kernels with 256, 512 and, in FP32, 1024 threads)
+ * with HIP events on the plan's stream, and keeps the fastest for the plan (affects every
+ * later call on it, all precisions).  choice_out (may be NULL): 0 = fixed-size kernels, else
+ * the generic work-group size; ms_out (may be NULL): its time per application in ms.
+ * Allocates and frees two scratch blocks.  Errors: PCX_E_ARG, PCX_E_SIZE, PCX_E_DEVICE. */
+int pcx_plan_autotune(pcx_plan *p, const double kappa[3], int precision, int nvec, int *choice_out,
+                      double *ms_out);
 
 /* Eigenvalue gradient (not in the paper: first-order perturbation of the
  * Hermitian-definite pencil): for x = B^{-1} Q_r Sigma_r y with ||y|| = 1,

@@ -62,6 +62,13 @@ _SIGS = [
     ("pcx_plan_set_variant", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("pcx_apply_Ar", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int]),
+    ("pcx_apply_Ar_multi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    ("pcx_solve_batch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    ("pcx_plan_autotune", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     ("pcx_apply_QS", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int]),
     ("pcx_apply_QS_adjoint", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p,

@@ -133,6 +133,28 @@ class Plan:
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_apply_Ar, kappa, precision, y, z, 2 * self.n, 2 * self.n)
 
+    def pcx_apply_Ar_multi(self, kappas, y, z, precision=None):
+        """z = A_r(kappa_k) y for every wave vector in one launch per kernel; y, z hold
+        len(kappas) equal groups of vectors, ordered [k][v]."""
+        precision = self._prec_of(y) if precision is None else precision
+        ks = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64).reshape(-1, 3))
+        nv = self._check_block(y, 2 * self.n, precision, "y")
+        if self._check_block(z, 2 * self.n, precision, "z") != nv or nv % len(ks):
+            raise ValueError("y and z must hold the same whole number of vectors per wave vector")
+        L.check(self._lib.pcx_apply_Ar_multi(self._ptr, len(ks), ks.ctypes.data_as(ctypes.c_void_p), int(precision),
+                                             ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                             nv // len(ks)))
+        return z
+
+    def pcx_plan_autotune(self, kappa, precision=L.PCX_FP32, nvec: int = 8):
+        """Times the kernel variants on this plan and keeps the fastest; returns (choice, ms):
+        choice 0 = fixed-size kernels, else the generic plane work-group size."""
+        ch = ctypes.c_int()
+        ms = ctypes.c_double()
+        L.check(self._lib.pcx_plan_autotune(self._ptr, _kappa3(kappa), int(precision), int(nvec), ctypes.byref(ch),
+                                            ctypes.byref(ms)))
+        return ch.value, ms.value
+
     def pcx_apply_QS(self, kappa, y, u, precision=None):
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_apply_QS, kappa, precision, y, u, 2 * self.n, 3 * self.n)
@@ -190,6 +212,14 @@ class Plan:
             L.check(code)
         return lam, (y if want_y else None), x, stats
 
+    def _opts(self, mode, block, max_iter, tol, tol_fp32, seed, precondition, verbose):
+        opts = L.PcxOpts()
+        self._lib.pcx_opts_default(ctypes.byref(opts))
+        opts.mode, opts.block, opts.max_iter = int(mode), int(block), int(max_iter)
+        opts.tol, opts.tol_fp32, opts.seed = float(tol), float(tol_fp32), int(seed)
+        opts.precondition, opts.verbose = int(bool(precondition)), int(bool(verbose))
+        return opts
+
     def pcx_grad_eps(self, x, weight, layout: int = L.PCX_EPS_YEE3):
         """-sum_t weight[t] |x_t|^2 per Yee point (or per voxel): d(sum_t w_t lambda_t)/d eps."""
         torch = _torch()
@@ -201,3 +231,39 @@ class Plan:
         L.check(self._lib.pcx_grad_eps(self._ptr, nv, ctypes.c_void_p(x.data_ptr()), w.ctypes.data_as(ctypes.c_void_p),
                                        ctypes.c_void_p(out.data_ptr()), int(layout)))
         return out
+
+
+def pcx_solve_batch(problems, nev: int, *, mode=L.PCX_MODE_FP32_REFINE, block=0, max_iter=400, tol=1e-9,
+                    tol_fp32=1e-3, seed=12345, precondition=True, nworkers=0, want_y=False,
+                    raise_on_noconv=True):
+    """Solves independent problems concurrently.  problems: list of (plan, [kappa, ...]).
+    Returns (lambda (total, nev) numpy, list of y tensors or None, list of SolveStats), problems in
+    plan-major order."""
+    torch = _torch()
+    plans = [p for p, _ in problems]
+    nk = np.array([len(ks) for _, ks in problems], dtype=np.int32)
+    ks = np.ascontiguousarray(np.concatenate([np.asarray(k, dtype=np.float64).reshape(-1, 3)
+                                              for _, k in problems]).reshape(-1))
+    total = int(nk.sum())
+    lib = plans[0]._lib
+    opts = plans[0]._opts(mode, block, max_iter, tol, tol_fp32, seed, precondition, False)
+    ptrs = (ctypes.c_void_p * len(plans))(*[p._ptr.value for p in plans])
+    lam = np.zeros((total, nev), dtype=np.float64)
+    st = (L.PcxStats * total)()
+    ys, yp = None, None
+    if want_y:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ys = []
+        for p, kl in problems:
+            for _ in range(len(kl)):
+                ys.append(torch.empty((nev, 2 * p.n), dtype=torch.complex128, device=dev))
+        yp = (ctypes.c_void_p * total)(*[t.data_ptr() for t in ys])
+    torch.cuda.synchronize()
+    code = lib.pcx_solve_batch(ptrs, len(plans), nk.ctypes.data_as(ctypes.c_void_p),
+                               ks.ctypes.data_as(ctypes.c_void_p), int(nev), ctypes.byref(opts), int(nworkers),
+                               lam.ctypes.data_as(ctypes.c_void_p), yp, st)
+    stats = [SolveStats(s.iterations, s.iterations_fp32, s.matvecs, s.matvecs_fp32, s.seconds, s.seconds_matvec,
+                        np.array(list(s.residual))[:nev], s.converged) for s in st]
+    if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
+        L.check(code)
+    return lam, ys, stats

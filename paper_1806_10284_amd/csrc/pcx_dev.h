@@ -206,4 +206,28 @@ DEV void w_row_code(cx<double> L0, cx<double> L1, cx<double> L2, int code, int l
     }
 }
 
+// The wave vector of this work-group: the grid's own, or in a multi-k launch (blockIdx.y =
+// k * nvk + v) the k-th kappa and its n-byte block of mode codes.
+struct KSel {
+    double kap[3];
+    const unsigned char* codes;
+};
+
+DEV KSel select_k(const Grid& g, long n) {
+    KSel s;
+    if (g.nvk > 0) {
+        const int kk = (int)blockIdx.y / g.nvk;
+        s.kap[0] = g.kaps[3 * kk];
+        s.kap[1] = g.kaps[3 * kk + 1];
+        s.kap[2] = g.kaps[3 * kk + 2];
+        s.codes = g.codes + (long)kk * n;
+    } else {
+        s.kap[0] = g.kap[0];
+        s.kap[1] = g.kap[1];
+        s.kap[2] = g.kap[2];
+        s.codes = g.codes;
+    }
+    return s;
+}
+
 }  // namespace pcx

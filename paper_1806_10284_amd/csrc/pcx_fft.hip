@@ -166,13 +166,13 @@ DEV PlaneLds<R> plane_lds(char* base, int n2, int n3) {
 
 // Fills the tables for plane i; returns Lambda_1(i).
 template <typename R, int NT>
-DEV cx<double> plane_setup(const Grid& g, const DeviceTables& tb, int i, PlaneLds<R>& L) {
+DEV cx<double> plane_setup(const Grid& g, const KSel& ks, const DeviceTables& tb, int i, PlaneLds<R>& L) {
     const int n2 = g.n2, n3 = g.n3;
-    const double tx = (g.kap[0] + (double)i) / (double)g.n1;
+    const double tx = (ks.kap[0] + (double)i) / (double)g.n1;
     const cx<R>* twz_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[2] : (const cx<R>*)tb.tw32[2];
     const cx<R>* twy_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[1] : (const cx<R>*)tb.tw32[1];
-    const double phi2 = (g.kap[1] - (double)g.s1 * tx) / (double)n2;
-    const double Ai = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((g.kap[1] - (double)g.s1 * tx) / (double)n2)) /
+    const double phi2 = (ks.kap[1] - (double)g.s1 * tx) / (double)n2;
+    const double Ai = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((ks.kap[1] - (double)g.s1 * tx) / (double)n2)) /
                       (double)n3;
     for (int q = threadIdx.x; q < n3; q += NT) {
         L.twz[q] = twz_g[q];
@@ -182,9 +182,9 @@ DEV cx<double> plane_setup(const Grid& g, const DeviceTables& tb, int i, PlaneLd
     for (int j = threadIdx.x; j < n2; j += NT) {
         L.twy[j] = twy_g[j];
         L.twb[j] = cis_turns<R>((double)j * phi2);
-        const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)n2;
+        const double ty = ((ks.kap[1] + (double)j) - (double)g.s1 * tx) / (double)n2;
         L.lamy[j] = lam_of_turn(ty, 1.0 / g.dlt[1]);
-        const double p3 = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)n3;
+        const double p3 = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)n3;
         L.phi3[j] = p3;
         double s, c;
         sincospi(p3, &s, &c);
@@ -218,6 +218,7 @@ DEV cx<float> z_twiddle(const PlaneLds<float>& L, const cx<float>* __restrict__ 
 template <typename R, int NT, int EPT>
 __global__ void __launch_bounds__(NT) k_plane_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
                                                    cx<R>* __restrict__ t) {
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
     extern __shared__ __align__(16) char lds[];
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const int i = blockIdx.x;
@@ -226,9 +227,9 @@ __global__ void __launch_bounds__(NT) k_plane_fwd(Grid g, DeviceTables tb, const
     const int np = n2 * n3;
     const int ld = n3 + 1;
     PlaneLds<R> L = plane_lds<R>(lds, n2, n3);
-    const cx<double> lamx = plane_setup<R, NT>(g, tb, i, L);
+    const cx<double> lamx = plane_setup<R, NT>(g, ks, tb, i, L);
     const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
-    const unsigned char* codes = g.codes + (long)i * np;
+    const unsigned char* codes = ks.codes + (long)i * np;
     const double idz = 1.0 / g.dlt[2];
     const cx<R>* yb = y + (long)v * 2 * n + (long)i * np;
     // modes per thread small enough: y and the z-twiddles of the owned modes stay in registers
@@ -322,6 +323,7 @@ __global__ void __launch_bounds__(NT) k_plane_fwd(Grid g, DeviceTables tb, const
 template <typename R, int NT, int EPT>
 __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
                                                    cx<R>* __restrict__ z) {
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
     extern __shared__ __align__(16) char lds[];
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const int i = blockIdx.x;
@@ -330,9 +332,9 @@ __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const
     const int np = n2 * n3;
     const int ld = n3 + 1;
     PlaneLds<R> L = plane_lds<R>(lds, n2, n3);
-    const cx<double> lamx = plane_setup<R, NT>(g, tb, i, L);
+    const cx<double> lamx = plane_setup<R, NT>(g, ks, tb, i, L);
     const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
-    const unsigned char* codes = g.codes + (long)i * np;
+    const unsigned char* codes = ks.codes + (long)i * np;
     __syncthreads();
     const double idz = 1.0 / g.dlt[2];
     constexpr bool kRegAcc = sizeof(R) == 4 ? EPT <= 4 : EPT <= 8;   // accumulators in registers
@@ -438,6 +440,7 @@ __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const
 template <typename R, int EPT, int MODE>
 __global__ void __launch_bounds__(256) k_xline(Grid g, DeviceTables tb, const R* __restrict__ scale,
                                                      cx<R>* __restrict__ t, cx<R>* __restrict__ u, int TB) {
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
     extern __shared__ __align__(16) char lds[];
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const long n = (long)n1 * n2 * n3;
@@ -450,7 +453,7 @@ __global__ void __launch_bounds__(256) k_xline(Grid g, DeviceTables tb, const R*
     cx<R>* twx = buf + (size_t)TB * ld;
     cx<R>* twa = twx + n1;
     const cx<R>* twx_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[0] : (const cx<R>*)tb.tw32[0];
-    const double phi1 = g.kap[0] / (double)n1;
+    const double phi1 = ks.kap[0] / (double)n1;
     for (int a = threadIdx.x; a < n1; a += 256) {
         twx[a] = twx_g[a];
         if (MODE != 0) twa[a] = cis_turns<R>((double)a * phi1);
@@ -571,17 +574,13 @@ static int pow2_at_least(long e) {
 }
 
 // plane kernels: enough threads that each owns at most 4 modes (up to 1024 threads; FP64 up to
-// 512 so that the 128 registers a 1024-thread group allows per lane are not exceeded)
-static int g_plane_threads = 0;   // 0: automatic; 256 / 512 / 1024 force the work-group size
-
-void set_plane_threads(int nt) { g_plane_threads = nt; }
-int get_plane_threads() { return g_plane_threads; }
-
-static void plane_shape(long np, int fp64, int* nt, int* ept) {
+// 512 so that the 128 registers a 1024-thread group allows per lane are not exceeded), unless the
+// plan's tuned work-group size (256 / 512 / 1024, FP64 at most 512) says otherwise
+static void plane_shape(long np, int fp64, int want, int* nt, int* ept) {
     int t = 256;
     const int tmax = fp64 ? 512 : 1024;
     while (t < tmax && (np + t - 1) / t > 4) t <<= 1;
-    if (g_plane_threads == 256 || g_plane_threads == 512 || (g_plane_threads == 1024 && !fp64)) t = g_plane_threads;
+    if (want == 256 || want == 512 || (want == 1024 && !fp64)) t = want;
     *nt = t;
     *ept = pow2_at_least((np + t - 1) / t);
 }
@@ -647,7 +646,7 @@ static size_t xline_lds_bytes(int n1, int TB) {
 template <typename R>
 static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, int nvec,
                             hipStream_t st) {
-    if (!g.generic) {
+    if (!g.generic[sizeof(R) == 8]) {
         bool done = false;
         hipError_t e = launch_fixed_plane_fwd<R>(g, tb, y, t, nvec, st, &done);
         if (done || e != hipSuccess) return e;
@@ -655,7 +654,7 @@ static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* 
     dim3 grid(g.n1, nvec);
     const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
     int nt, ept;
-    plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, &nt, &ept);
+    plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, g.plane_nt[sizeof(R) == 8], &nt, &ept);
 #define CALLF(NT, E) hipLaunchKernelGGL((k_plane_fwd<R, NT, E>), grid, dim3(NT), lds, st, g, tb, y, t)
     PCX_PLANE_DISPATCH(nt, ept, CALLF)
 #undef CALLF
@@ -665,7 +664,7 @@ static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* 
 template <typename R>
 static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, int nvec,
                             hipStream_t st) {
-    if (!g.generic) {
+    if (!g.generic[sizeof(R) == 8]) {
         bool done = false;
         hipError_t e = launch_fixed_plane_adj<R>(g, tb, t, z, nvec, st, &done);
         if (done || e != hipSuccess) return e;
@@ -673,7 +672,7 @@ static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* 
     dim3 grid(g.n1, nvec);
     const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
     int nt, ept;
-    plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, &nt, &ept);
+    plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, g.plane_nt[sizeof(R) == 8], &nt, &ept);
 #define CALLA(NT, E) hipLaunchKernelGGL((k_plane_adj<R, NT, E>), grid, dim3(NT), lds, st, g, tb, t, z)
     PCX_PLANE_DISPATCH(nt, ept, CALLA)
 #undef CALLA
@@ -683,7 +682,7 @@ static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* 
 template <typename R, int MODE>
 static hipError_t xline(const Grid& g, const DeviceTables& tb, const R* scale, cx<R>* t, cx<R>* u, int nvec,
                         hipStream_t st) {
-    if (MODE == 0 && !g.generic) {
+    if (MODE == 0 && !g.generic[sizeof(R) == 8]) {
         bool done = false;
         hipError_t e = launch_fixed_xline<R>(g, tb, scale, t, nvec, st, &done);
         if (done || e != hipSuccess) return e;

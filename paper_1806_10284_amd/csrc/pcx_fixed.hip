@@ -133,14 +133,14 @@ struct P3 {
 
 // Fills the per-plane tables of plane i; returns Lambda_1(i).
 template <typename R, int N2, int N3, int NT, typename LT>
-DEV cx<double> p3_setup(const Grid& g, const DeviceTables& tb, int i, const LT& L) {
-    const double tx = (g.kap[0] + (double)i) / (double)g.n1;
+DEV cx<double> p3_setup(const Grid& g, const KSel& ks, const DeviceTables& tb, int i, const LT& L) {
+    const double tx = (ks.kap[0] + (double)i) / (double)g.n1;
     const cx<double> L0 = lam_of_turn(tx, 1.0 / g.dlt[0]);
     const cx<R>* twz_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[2] : (const cx<R>*)tb.tw32[2];
     const cx<R>* twy_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[1] : (const cx<R>*)tb.tw32[1];
-    const double phi2 = (g.kap[1] - (double)g.s1 * tx) / (double)N2;
+    const double phi2 = (ks.kap[1] - (double)g.s1 * tx) / (double)N2;
     const double Ai =
-        ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((g.kap[1] - (double)g.s1 * tx) / (double)N2)) / (double)N3;
+        ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((ks.kap[1] - (double)g.s1 * tx) / (double)N2)) / (double)N3;
     for (int q = threadIdx.x; q < N3; q += NT) {
         L.twz[q] = twz_g[q];
         L.halfz[q] = tb.halfz[q];
@@ -149,14 +149,14 @@ DEV cx<double> p3_setup(const Grid& g, const DeviceTables& tb, int i, const LT& 
     for (int j = threadIdx.x; j < N2; j += NT) {
         L.twy[j] = twy_g[j];
         L.twb[j] = cis_turns<R>((double)j * phi2);
-        const double ty = ((g.kap[1] + (double)j) - (double)g.s1 * tx) / (double)N2;
+        const double ty = ((ks.kap[1] + (double)j) - (double)g.s1 * tx) / (double)N2;
         const cx<double> L1 = lam_of_turn(ty, 1.0 / g.dlt[1]);
         const cx<double> D = L1 - L0;
         L.lamy[j] = L1;
         L.d10[j] = D;
         L.a01[j] = abs2(L0) + abs2(L1);
         L.p10[j] = abs2(D);
-        const double p3 = ((g.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)N3;
+        const double p3 = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)N3;
         double s, c;
         sincospi(p3, &s, &c);
         L.rowz[j] = mk<double>(c, s);
@@ -206,6 +206,7 @@ DEV cx<R> p3_ztw(const LT& L, const cx<R>* __restrict__ rot, int c, int j, int s
 template <typename R, int N2, int N3, int NT>
 __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
                                                 cx<R>* __restrict__ t) {
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
     using LT = P3<R, N2, N3>;
     constexpr int LD = LT::LD, PS = LT::PS, NP = LT::NP;
     constexpr int EPT = (NP + NT - 1) / NT;
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
     const int i = blockIdx.x, v = blockIdx.y;
     const long n = (long)g.n1 * NP;
     const cx<R>* yb = y + (long)v * 2 * n + (long)i * NP;
-    const unsigned char* codes = g.codes + (long)i * NP;
+    const unsigned char* codes = ks.codes + (long)i * NP;
     cx<R> y1[EPT], y2[EPT];
     int code[EPT];
 #pragma unroll
@@ -226,7 +227,7 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
             code[s] = codes[e];
         }
     }
-    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, tb, i, L);
+    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
     const double idz = 1.0 / g.dlt[2];
     const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
     int s3m = g.s3 % NP;
@@ -287,6 +288,7 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
 template <typename R, int N2, int N3, int NT>
 __global__ void __launch_bounds__(NT) k_p3_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
                                                 cx<R>* __restrict__ z) {
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
     using LT = P3<R, N2, N3>;
     constexpr int LD = LT::LD, PS = LT::PS, NP = LT::NP;
     constexpr int EPT = (NP + NT - 1) / NT;
@@ -304,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_p3_adj(Grid g, DeviceTables tb, const cx
             if (NP % NT == 0 || e < NP) in[l][s] = src[e];
         }
     }
-    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, tb, i, L);
+    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
     const double idz = 1.0 / g.dlt[2];
     const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
     int s3m = g.s3 % NP;
@@ -334,7 +336,7 @@ __global__ void __launch_bounds__(NT) k_p3_adj(Grid g, DeviceTables tb, const cx
     }
     __syncthreads();
     ffft<R, N3, 3 * N2, 3 * N2, 0, LD, 1, NT, -1>(L.pl, L.twz);   // c -> k along rows j
-    const unsigned char* codes = g.codes + (long)i * NP;
+    const unsigned char* codes = ks.codes + (long)i * NP;
     cx<R>* zb = z + (long)v * 2 * n + (long)i * NP;
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {

@@ -177,12 +177,18 @@ static hipError_t g_config_status = hipErrorNotReady;
 
 static int ensure_configured() {
     if (g_config_status == hipErrorNotReady) {
-        if (const char* env = std::getenv("PCX_PLANE_THREADS")) set_plane_threads(std::atoi(env));
         g_config_status = configure_kernels();
         if (g_config_status == hipSuccess) g_config_status = configure_block_kernels();
     }
     if (g_config_status != hipSuccess) return hip_fail(g_config_status, "kernel configuration");
     return PCX_OK;
+}
+
+void Plan::set_eps_pointers() {
+    inv_eps64 = eps_mem;
+    inv_epsn64 = (double*)inv_eps64 + 3 * n;
+    inv_eps32 = (double*)inv_epsn64 + 3 * n;
+    inv_epsn32 = (float*)inv_eps32 + 3 * n;
 }
 
 int Plan::grow(void** buf, size_t* have, size_t need) {
@@ -215,7 +221,12 @@ Grid Plan::grid(const double kappa[3]) const {
     g.fy = fy;
     g.fz = fz;
     g.codes = (const unsigned char*)codes;
-    g.generic = variant == PCX_VARIANT_GENERIC ? 1 : 0;
+    for (int f = 0; f < 2; ++f) {
+        g.generic[f] = (variant == PCX_VARIANT_GENERIC || tuned_nt[f] > 0) ? 1 : 0;
+        g.plane_nt[f] = tuned_nt[f] > 0 ? tuned_nt[f] : 0;
+    }
+    g.nvk = 0;
+    g.kaps = nullptr;
     return g;
 }
 
@@ -231,6 +242,34 @@ int Plan::grid_for(const double kappa[3], Grid* g) {
         codes_valid = true;
     }
     *g = grid(kappa);
+    return PCX_OK;
+}
+
+int Plan::grid_multi(const double* kappas, int nk, int nvk, Grid* g) {
+    int rc = grow(&mcodes, &mcodes_cap, (size_t)nk * n);
+    if (rc) return rc;
+    if ((rc = grow(&kaps_dev, &kaps_cap, 3 * sizeof(double) * (size_t)nk))) return rc;
+    const bool same = mcodes_valid && (int)mkaps.size() == 3 * nk &&
+                      std::equal(mkaps.begin(), mkaps.end(), kappas);
+    if (!same) {
+        mcodes_valid = false;
+        for (int k = 0; k < nk; ++k) {
+            Grid gk = grid(kappas + 3 * k);
+            hipError_t e = launch_modecode(gk, (unsigned char*)mcodes + (size_t)k * n, stream);
+            if (e != hipSuccess) return hip_fail(e, "mode codes");
+        }
+        mkaps.assign(kappas, kappas + 3 * nk);
+        hipError_t e = hipMemcpyAsync(kaps_dev, mkaps.data(), 3 * sizeof(double) * (size_t)nk, hipMemcpyHostToDevice,
+                                      stream);
+        if (e != hipSuccess) return hip_fail(e, "wave vector upload");
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "wave vector upload");
+        mcodes_valid = true;
+    }
+    *g = grid(kappas);
+    g->codes = (const unsigned char*)mcodes;
+    g->nvk = nvk;
+    g->kaps = (const double*)kaps_dev;
     return PCX_OK;
 }
 
@@ -327,7 +366,8 @@ extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_str
 extern "C" void pcx_plan_destroy(pcx_plan* pp) {
     Plan* p = (Plan*)pp;
     if (!p) return;
-    void* bufs[] = {p->tables_mem, p->eps_mem, p->work, p->lob_mem, p->prec, p->gram_part, p->small_mem, p->codes};
+    void* bufs[] = {p->tables_mem, p->eps_mem, p->work,  p->lob_mem,  p->prec,
+                    p->gram_part,  p->small_mem, p->codes, p->mcodes, p->kaps_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->pinned) (void)hipHostFree(p->pinned);
@@ -356,10 +396,7 @@ extern "C" int pcx_plan_set_eps(pcx_plan* pp, const double* eps, int layout) {
     const size_t bytes = 3 * n * (2 * sizeof(double) + 2 * sizeof(float));
     int rc = p->grow(&p->eps_mem, &p->eps_cap, bytes);
     if (rc) return rc;
-    p->inv_eps64 = p->eps_mem;
-    p->inv_epsn64 = (double*)p->inv_eps64 + 3 * n;
-    p->inv_eps32 = (double*)p->inv_epsn64 + 3 * n;
-    p->inv_epsn32 = (float*)p->inv_eps32 + 3 * n;
+    p->set_eps_pointers();
     hipError_t e;
     if ((e = hipMemcpy(p->inv_eps64, inv.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->inv_epsn64, invn.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -445,6 +482,33 @@ extern "C" int pcx_apply_Ar(pcx_plan* p, const double kappa[3], int precision, c
     if (!p) return fail(PCX_E_ARG, "pcx_apply_Ar: null plan");
     return ((Plan*)p)->apply(Plan::OP_AR, kappa, precision, y, z, nvec);
 }
+extern "C" int pcx_apply_Ar_multi(pcx_plan* pp, int nk, const double* kappas, int precision, const void* y,
+                                  void* z, int nvec_per_k) {
+    Plan* p = (Plan*)pp;
+    if (!p || !kappas || !y || !z) return fail(PCX_E_ARG, "pcx_apply_Ar_multi: null pointer");
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "pcx_apply_Ar_multi: bad precision");
+    if (nk < 1 || nvec_per_k < 1 || (long)nk * nvec_per_k > p->max_vectors)
+        return fail(PCX_E_ARG, "pcx_apply_Ar_multi: nk * nvec_per_k must be in [1, %d]", p->max_vectors);
+    for (int q = 0; q < 3 * nk; ++q)
+        if (!std::isfinite(kappas[q])) return fail(PCX_E_ARG, "pcx_apply_Ar_multi: non-finite kappa");
+    if (!p->eps_set) return fail(PCX_E_ARG, "pcx_apply_Ar_multi: permittivity not set");
+    int rc = p->check_fits(precision);
+    if (rc) return rc;
+    const int nv = nk * nvec_per_k;
+    if ((rc = p->ensure_work(nv))) return rc;
+    Grid g;
+    if ((rc = p->grid_multi(kappas, nk, nvec_per_k, &g))) return rc;
+    hipError_t e;
+    if (precision == PCX_FP64)
+        e = launch_apply_Ar<double>(g, p->tables, (const double*)p->inv_epsn64, (const cx<double>*)y, (cx<double>*)z,
+                                    (cx<double>*)p->work, nv, p->stream);
+    else
+        e = launch_apply_Ar<float>(g, p->tables, (const float*)p->inv_epsn32, (const cx<float>*)y, (cx<float>*)z,
+                                   (cx<float>*)p->work, nv, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_apply_Ar_multi: kernel launch");
+    return PCX_OK;
+}
+
 extern "C" int pcx_apply_QS(pcx_plan* p, const double kappa[3], int precision, const void* y, void* u, int nvec) {
     if (!p) return fail(PCX_E_ARG, "pcx_apply_QS: null plan");
     return ((Plan*)p)->apply(Plan::OP_QS, kappa, precision, y, u, nvec);

@@ -58,11 +58,26 @@ struct Plan {
 
     // kernel variant of the A_r path (PCX_VARIANT_*)
     int variant = PCX_VARIANT_AUTO;
+    // autotuned choice per precision ([0] FP32, [1] FP64): 0 untuned, -1 fixed-size kernels,
+    // 256 / 512 / 1024 generic kernels with that work-group size
+    int tuned_nt[2] = {0, 0};
+
+    // mode codes (n bytes each) and device kappas of the last multi-k launch
+    void* mcodes = nullptr;
+    size_t mcodes_cap = 0;
+    void* kaps_dev = nullptr;
+    size_t kaps_cap = 0;
+    std::vector<double> mkaps;
+    bool mcodes_valid = false;
 
     int grow(void** buf, size_t* have, size_t need);
+    // inv_eps64 / inv_epsn64 / inv_eps32 / inv_epsn32 inside eps_mem (3n values each)
+    void set_eps_pointers();
     // grid description for kappa (computes the mode codes on the plan stream when kappa is new)
     int grid_for(const double kappa[3], Grid* g);
     Grid grid(const double kappa[3]) const;
+    // grid description for nk wave vectors in one launch, nvk vectors each ([k][v] order)
+    int grid_multi(const double* kappas, int nk, int nvk, Grid* g);
     int check_fits(int precision) const;
     int ensure_work(int nvec);
     int apply(int op, const double kappa[3], int precision, const void* in, void* out, int nvec);

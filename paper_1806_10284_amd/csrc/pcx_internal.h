@@ -26,7 +26,13 @@ struct Grid {
     double dlt[3];           // mesh sizes
     FftPlan fx, fy, fz;
     const unsigned char* codes;  // mixing basis per mode (launch_modecode), n bytes
-    int generic;             // 1: runtime-sized kernels only; 0: fixed-size kernels where they exist
+    // per precision [0] FP32, [1] FP64:
+    int generic[2];          // 1: runtime-sized kernels only; 0: fixed-size kernels where they exist
+    int plane_nt[2];         // generic plane kernels' work-group size: 0 automatic, 256 / 512 / 1024
+    // several wave vectors in one launch: vectors are ordered [k][v] with nvk vectors per wave
+    // vector; kaps (device, 3 per k) and codes (n bytes per k) then replace kap and codes
+    int nvk;
+    const double* kaps;
 };
 
 template <typename R>
@@ -67,9 +73,6 @@ hipError_t launch_QS_adjoint(const Grid& g, const DeviceTables& tb, const cx<R>*
 hipError_t launch_modecode(const Grid& g, unsigned char* out, hipStream_t st);
 // 1/Lambda_q per mode (0 at the masked mode), FP64, n values
 hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st);
-// work-group size of the plane kernels: 0 = automatic, else 256 / 512 / 1024 (FP64: at most 512)
-void set_plane_threads(int nt);
-int get_plane_threads();
 // set per-kernel LDS limits once per process
 hipError_t configure_kernels();
 

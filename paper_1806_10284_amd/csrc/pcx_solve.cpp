@@ -66,6 +66,17 @@ struct Solver {
     int slot_next = 0;
     std::vector<double> theta;           // host
     std::vector<double> resid;           // host, relative residuals of the current block
+    std::vector<double> rabs;            // host, absolute residual norms ||A_r x - theta x||
+    double anorm = 0;                    // ||A_r|| <= max Lambda_q / min eps
+
+    // Band j has converged when its relative residual is below tol or, for eigenvalues so close
+    // to zero (next to Gamma) that tol |theta| is below what the arithmetic can resolve, when its
+    // absolute residual is at the precision's floor 64 eps ||A_r||.
+    template <typename R>
+    bool converged(int j, double tol) const {
+        const double eps = sizeof(R) == 8 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+        return resid[j] <= tol || rabs[j] <= 64.0 * eps * anorm;
+    }
 
     int sync() {
         hipError_t e = hipStreamSynchronize(p->stream);
@@ -154,7 +165,11 @@ struct Solver {
         int rc = sync();
         if (rc) return rc;
         resid.resize(b);
-        for (int j = 0; j < b; ++j) resid[j] = std::sqrt(std::max(r2[j], 0.0)) / std::max(std::fabs(theta[j]), 1e-300);
+        rabs.resize(b);
+        for (int j = 0; j < b; ++j) {
+            rabs[j] = std::sqrt(std::max(r2[j], 0.0));
+            resid[j] = rabs[j] / std::max(std::fabs(theta[j]), 1e-300);
+        }
         return PCX_OK;
     }
 
@@ -180,7 +195,7 @@ struct Solver {
 
     // one phase of LOBPCG at precision R, starting from the b columns in B.X
     template <typename R>
-    int phase(Blocks<R>& B, double tol, int max_iter, int& iters) {
+    int phase(Blocks<R>& B, double tol, int max_iter, int& iters, bool refine_after) {
         int rc;
         hipError_t e = launch_mask<R>(B.X, prec, n, b, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: mask");
@@ -195,29 +210,32 @@ struct Solver {
         for (;;) {
             if ((rc = residuals<R>(B))) return rc;   // W <- prec (AX - X theta) for all b columns
             bool all = true;
-            double worst = 0;
+            double worst = 0;                    // over the bands still open
             for (int j = 0; j < nev; ++j) {
-                all = all && resid[j] <= tol;
-                worst = std::max(worst, resid[j]);
+                const bool cj = converged<R>(j, tol);
+                all = all && cj;
+                if (!cj) worst = std::max(worst, resid[j]);
             }
             if (o.verbose)
                 fprintf(stderr, "pcx lobpcg %s it %d: theta0 %.12g worst residual %.3e\n", sizeof(R) == 8 ? "fp64" : "fp32",
                         iters, theta[0], worst);
             if (all || iters >= max_iter) return PCX_OK;
             // a reduced-precision phase ends when its residual stops improving (rounding floor)
+            // and leaves at least half of the iterations to the refinement
             if (worst < 0.9 * best) {
                 best = worst;
                 stall = 0;
-            } else if (sizeof(R) == 4 && worst < 1e-2 && ++stall >= kFp32Stall) {
+            } else if (sizeof(R) == 4 && ++stall >= kFp32Stall) {
                 return PCX_OK;
             }
+            if (sizeof(R) == 4 && refine_after && st.iterations_fp32 >= max_iter / 2) return PCX_OK;
             ++iters;
             ++st.iterations;
             if (sizeof(R) == 4) ++st.iterations_fp32;
             // soft locking: only columns whose residual is above tol expand the basis
             std::vector<int> act;
             for (int j = 0; j < b; ++j)
-                if (resid[j] > tol) act.push_back(j);
+                if (!converged<R>(j, tol)) act.push_back(j);
             const int na = (int)act.size();
             // W_act <- W_act - X (X^H W_act), selecting the active columns in the first pass
             for (int pass = 0; pass < kOrthoPasses; ++pass) {
@@ -392,6 +410,12 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     for (long q = 0; q < n; ++q) modes[q] = q;
     const long nm = std::min<long>(n, (b + 1) / 2);
     std::partial_sort(modes.begin(), modes.begin() + nm, modes.end(), [&](long a, long c) { return hp[a] > hp[c]; });
+    {
+        double dmin = 0;                  // smallest nonzero 1 / Lambda_q
+        for (long q = 0; q < n; ++q)
+            if (hp[q] > 0 && (dmin == 0 || hp[q] < dmin)) dmin = hp[q];
+        S.anorm = dmin > 0 ? 1.0 / (dmin * p->eps_min) : 0.0;
+    }
     auto seed_block = [&](auto* X) -> int {
         using C = typename std::remove_pointer<decltype(X)>::type;
         hipError_t e2 = launch_random(X, (long)b * N, S.o.seed, 1e-3, p->stream);
@@ -419,7 +443,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (use32) {
         rc = seed_block(B32.X);
         const double tol32 = S.o.mode == PCX_MODE_FP32 ? S.o.tol : std::max(S.o.tol, S.o.tol_fp32);
-        if (!rc) rc = S.phase<float>(B32, tol32, S.o.max_iter, iters);
+        if (!rc) rc = S.phase<float>(B32, tol32, S.o.max_iter, iters, use64);
         if (!rc && use64) {
             e = launch_convert(B32.X, B64.X, (long)b * N, p->stream);
             if (e != hipSuccess) rc = hip_fail(e, "pcx_solve: convert");
@@ -427,13 +451,13 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     } else {
         rc = seed_block(B64.X);
     }
-    if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters);
+    if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false);
     if (!rc) {
         for (int j = 0; j < nev; ++j) lambda[j] = S.theta[j];
         int conv = 0;
         for (int j = 0; j < nev; ++j) {
             if (j < PCX_MAX_BLOCK) S.st.residual[j] = S.resid[j];
-            if (S.resid[j] <= S.o.tol) ++conv;
+            if (use64 ? S.converged<double>(j, S.o.tol) : S.converged<float>(j, S.o.tol)) ++conv;
         }
         S.st.converged = conv;
         // outputs: y (FP64), x = B^{-1} Q_r Sigma_r y

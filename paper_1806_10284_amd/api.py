@@ -237,8 +237,8 @@ def pcx_solve_batch(problems, nev: int, *, mode=L.PCX_MODE_FP32_REFINE, block=0,
                     tol_fp32=1e-3, seed=12345, precondition=True, nworkers=0, want_y=False,
                     raise_on_noconv=True):
     """Solves independent problems concurrently.  problems: list of (plan, [kappa, ...]).
-    Returns (lambda (total, nev) numpy, list of y tensors or None, list of SolveStats), problems in
-    plan-major order."""
+    Returns (lambda (total, nev) numpy, list of y tensors (None where not requested) or None, list of
+    SolveStats), problems in plan-major order.  want_y: False, True, or the problem indices."""
     torch = _torch()
     plans = [p for p, _ in problems]
     nk = np.array([len(ks) for _, ks in problems], dtype=np.int32)
@@ -252,12 +252,15 @@ def pcx_solve_batch(problems, nev: int, *, mode=L.PCX_MODE_FP32_REFINE, block=0,
     st = (L.PcxStats * total)()
     ys, yp = None, None
     if want_y:
+        # want_y: True for every problem, or an iterable of the problem indices to return y for
+        keep = set(range(total)) if want_y is True else set(int(q) for q in want_y)
         dev = torch.device("cuda", torch.cuda.current_device())
         ys = []
         for p, kl in problems:
             for _ in range(len(kl)):
-                ys.append(torch.empty((nev, 2 * p.n), dtype=torch.complex128, device=dev))
-        yp = (ctypes.c_void_p * total)(*[t.data_ptr() for t in ys])
+                q = len(ys)
+                ys.append(torch.empty((nev, 2 * p.n), dtype=torch.complex128, device=dev) if q in keep else None)
+        yp = (ctypes.c_void_p * total)(*[t.data_ptr() if t is not None else None for t in ys])
     torch.cuda.synchronize()
     code = lib.pcx_solve_batch(ptrs, len(plans), nk.ctypes.data_as(ctypes.c_void_p),
                                ks.ctypes.data_as(ctypes.c_void_p), int(nev), ctypes.byref(opts), int(nworkers),

@@ -81,7 +81,8 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
     int pba[MPB], pbb[MPB];
 #pragma unroll
     for (int p = 0; p < MPB; ++p) {
-        const int pb = threadIdx.x + p * blockDim.x;
+        // gridDim.y slices of MPB * 256 pair-blocks each
+        const int pb = blockIdx.y * MPB * (int)blockDim.x + threadIdx.x + p * blockDim.x;
         pba[p] = pbb[p] = -1;
         if (pb < PB) pair_block<BLK, HERM>(pb, nbA, nbB, &pba[p], &pbb[p]);
     }
@@ -204,13 +205,15 @@ static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>
     const int kbP = HERM ? (kb / ka) * kaP : (kb + BLK - 1) / BLK * BLK;
     const int nbA = kaP / BLK, nbB = kbP / BLK;
     const int PB = HERM ? (kb / ka) * nbA * (nbA + 1) / 2 : nbA * nbB;
-    if (PB > kMaxPB * 256) return hipErrorInvalidValue;
     const size_t lds = sizeof(cx<double>) * (size_t)kGramRows * ((HERM ? 0 : kaP) + kbP + 1) +
                        2 * sizeof(void*) * kMaxCols;
+    // more than kMaxPB * 256 pair-blocks: slices of them in separate work-groups (grid y)
+    const int slices = (PB + kMaxPB * 256 - 1) / (kMaxPB * 256);
     if (PB <= 256)
         hipLaunchKernelGGL((k_gram<R, BLK, HERM, 1>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
     else
-        hipLaunchKernelGGL((k_gram<R, BLK, HERM, 2>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
+        hipLaunchKernelGGL((k_gram<R, BLK, HERM, 2>), dim3(chunks, slices), dim3(256), lds, st, A, B, N, rpc,
+                           part);
     return hipGetLastError();
 }
 
@@ -224,8 +227,9 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     rpc = (rpc + kGramRows - 1) / kGramRows * kGramRows;
     const int chunks = (int)((N + rpc - 1) / rpc);
     // register tile: every thread of the group waits for the busiest, so the cost of a tile size
-    // is (rounds of 256 pair-blocks) x BLK^2; the cheapest within 2 rounds, larger BLK on ties
-    // (fewer LDS reads per product)
+    // is (rounds of 256 pair-blocks) x BLK^2; the cheapest, larger BLK on ties (fewer LDS reads per
+    // product); beyond 2 rounds the pair-blocks go to several work-groups per row chunk, each of
+    // which stages the rows again, so those rounds count double
     hipError_t e;
     auto pbs = [&](int blk) {
         const int a = (ka + blk - 1) / blk;
@@ -235,8 +239,8 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     long best = -1;
     for (int t = 4; t >= 1; --t) {
         const int pb = pbs(t);
-        if (pb > kMaxPB * 256) continue;
-        const long cost = (long)((pb + 255) / 256) * t * t;
+        const long rounds = (pb + 255) / 256;
+        const long cost = (rounds <= kMaxPB ? rounds : 2 * rounds) * t * t;
         if (best < 0 || cost < best) {
             best = cost;
             blk = t;

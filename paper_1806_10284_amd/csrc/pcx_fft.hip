@@ -432,6 +432,284 @@ __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const
     }
 }
 
+// ------------------------------------------------------------------ planes too large for LDS
+// When one n2 x n3 plane does not fit in LDS (FP64 at 128 x 128), the plane kernels are split in
+// two passes through an intermediate u[v][l][i][j][c] in HBM:
+//   k_zpass_fwd (rows j0..j0+RB of plane i): W y -> z-IDFT -> z-twiddle -> u
+//   k_ypass_fwd (columns c0..c0+CB):          u -> y-IDFT -> y-twiddle -> t[l][i][c][b]
+//   k_ypass_adj / k_zpass_adj: the reverse, with W^H accumulated over l in registers.
+constexpr int kSplitEPT = 8;     // modes per thread in the row passes (256 threads)
+
+static int split_rows(int n2, int n3) {
+    int rb = (256 * kSplitEPT) / n3;
+    if (rb > n2) rb = n2;
+    return rb < 1 ? 1 : rb;
+}
+static int split_cols(int n3) { return n3 < 16 ? n3 : 16; }
+
+template <typename R>
+__host__ DEV size_t zpass_lds_bytes(int rb, int n3) {
+    size_t b = sizeof(cx<R>) * ((size_t)rb * (n3 + 1) + 2 * n3);
+    b = (b + 15) & ~(size_t)15;
+    return b + sizeof(cx<double>) * (n3 + 2 * rb);
+}
+template <typename R>
+__host__ DEV size_t ypass_lds_bytes(int cb, int n2) {
+    return sizeof(cx<R>) * ((size_t)cb * (n2 + 1) + 2 * n2);
+}
+
+// per-row tables of rows j0.. of plane i; returns Lambda_1(i)
+template <typename R>
+DEV cx<double> zpass_setup(const Grid& g, const KSel& ks, const DeviceTables& tb, int i, int j0, int rows,
+                           cx<R>* twz, cx<R>* twc, cx<double>* halfz, cx<double>* rowz, cx<double>* lamy) {
+    const int n2 = g.n2, n3 = g.n3;
+    const double tx = (ks.kap[0] + (double)i) / (double)g.n1;
+    const double Ai = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((ks.kap[1] - (double)g.s1 * tx) / (double)n2)) /
+                      (double)n3;
+    const cx<R>* twz_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[2] : (const cx<R>*)tb.tw32[2];
+    for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+        twz[q] = twz_g[q];
+        halfz[q] = tb.halfz[q];
+        twc[q] = cis_turns<R>((double)q * Ai);
+    }
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        const int j = j0 + r;
+        const double ty = ((ks.kap[1] + (double)j) - (double)g.s1 * tx) / (double)n2;
+        lamy[r] = lam_of_turn(ty, 1.0 / g.dlt[1]);
+        const double p3 = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)n3;
+        double sn, cs;
+        sincospi(p3, &sn, &cs);
+        rowz[r] = mk<double>(cs, sn);
+    }
+    return lam_of_turn(tx, 1.0 / g.dlt[0]);
+}
+
+template <typename R>
+DEV cx<R> split_ztw(const cx<R>* twc, const cx<R>* __restrict__ rot, int c, int j, int s3m, int M) {
+    return cmul(twc[c], rot[(int)(((long)c * j * s3m) % M)]);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_zpass_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
+                                                    cx<R>* __restrict__ u, int RB) {
+    extern __shared__ __align__(16) char lds[];
+    const int n2 = g.n2, n3 = g.n3, ld = n3 + 1;
+    const long n = (long)g.n1 * n2 * n3, np = (long)n2 * n3;
+    const KSel ks = select_k(g, n);
+    const int i = blockIdx.x, v = blockIdx.y, j0 = blockIdx.z * RB;
+    const int rows = min(RB, n2 - j0);
+    cx<R>* buf = (cx<R>*)lds;
+    cx<R>* twz = buf + (size_t)RB * ld;
+    cx<R>* twc = twz + n3;
+    size_t off = (sizeof(cx<R>) * ((size_t)RB * ld + 2 * n3) + 15) & ~(size_t)15;
+    cx<double>* halfz = (cx<double>*)(lds + off);
+    cx<double>* rowz = halfz + n3;
+    cx<double>* lamy = rowz + RB;
+    const cx<double> L0 = zpass_setup<R>(g, ks, tb, i, j0, rows, twz, twc, halfz, rowz, lamy);
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    const int M = n2 * n3;
+    int s3m = g.s3 % M;
+    if (s3m < 0) s3m += M;
+    const double idz = 1.0 / g.dlt[2];
+    const int tot = rows * n3;
+    const long base = (long)i * np + (long)j0 * n3;
+    const cx<R>* y1 = y + (long)v * 2 * n + base;
+    const cx<R>* y2 = y1 + n;
+    const unsigned char* codes = ks.codes + base;
+    __syncthreads();
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int r = e / n3, k = e % n3;
+            const int code = codes[e];
+            cx<R> val = mk<R>((R)0, (R)0);
+            if (code != kMasked) {
+                const cx<double> h = cmul(halfz[k], rowz[r]);
+                cx<R> w1, w2;
+                w_row_code<R>(L0, lamy[r], lam_from_halfturn(h.y, h.x, idz), code, l, &w1, &w2);
+                val = cmul(w1, y1[e]) + cmul(w2, y2[e]);
+            }
+            buf[r * ld + k] = val;
+        }
+        __syncthreads();
+        fft_lines<R, kEpc, 256>(buf, g.fz, rows, 1, ld, twz, +1);
+        cx<R>* ul = u + ((long)v * 3 + l) * n + base;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int r = e / n3, c = e % n3;
+            ul[e] = cmul(buf[r * ld + c], split_ztw<R>(twc, rot, c, j0 + r, s3m, M));
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ypass_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ u,
+                                                    cx<R>* __restrict__ t, int CB) {
+    extern __shared__ __align__(16) char lds[];
+    const int n2 = g.n2, n3 = g.n3, ld = n2 + 1;
+    const long n = (long)g.n1 * n2 * n3, np = (long)n2 * n3;
+    const KSel ks = select_k(g, n);
+    const int i = blockIdx.x, v = blockIdx.y, c0 = blockIdx.z * CB;
+    const int cols = min(CB, n3 - c0);
+    cx<R>* buf = (cx<R>*)lds;
+    cx<R>* twy = buf + (size_t)CB * ld;
+    cx<R>* twb = twy + n2;
+    const double tx = (ks.kap[0] + (double)i) / (double)g.n1;
+    const double phi2 = (ks.kap[1] - (double)g.s1 * tx) / (double)n2;
+    const cx<R>* twy_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[1] : (const cx<R>*)tb.tw32[1];
+    for (int b = threadIdx.x; b < n2; b += blockDim.x) {
+        twy[b] = twy_g[b];
+        twb[b] = cis_turns<R>((double)b * phi2);
+    }
+    const int tot = n2 * cols;
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        const cx<R>* ul = u + ((long)v * 3 + l) * n + (long)i * np;
+        __syncthreads();
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int j = e / cols, q = e % cols;
+            buf[q * ld + j] = ul[(long)j * n3 + c0 + q];
+        }
+        __syncthreads();
+        fft_lines<R, kEpc, 256>(buf, g.fy, cols, 1, ld, twy, +1);
+        cx<R>* tl = t + ((long)v * 3 + l) * n + (long)i * np + (long)c0 * n2;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int q = e / n2, b = e % n2;
+            tl[e] = cmul(buf[q * ld + b], twb[b]);
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ypass_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
+                                                    cx<R>* __restrict__ u, int CB) {
+    extern __shared__ __align__(16) char lds[];
+    const int n2 = g.n2, n3 = g.n3, ld = n2 + 1;
+    const long n = (long)g.n1 * n2 * n3, np = (long)n2 * n3;
+    const KSel ks = select_k(g, n);
+    const int i = blockIdx.x, v = blockIdx.y, c0 = blockIdx.z * CB;
+    const int cols = min(CB, n3 - c0);
+    cx<R>* buf = (cx<R>*)lds;
+    cx<R>* twy = buf + (size_t)CB * ld;
+    cx<R>* twb = twy + n2;
+    const double tx = (ks.kap[0] + (double)i) / (double)g.n1;
+    const double phi2 = (ks.kap[1] - (double)g.s1 * tx) / (double)n2;
+    const cx<R>* twy_g = sizeof(R) == 8 ? (const cx<R>*)tb.tw64[1] : (const cx<R>*)tb.tw32[1];
+    for (int b = threadIdx.x; b < n2; b += blockDim.x) {
+        twy[b] = twy_g[b];
+        twb[b] = cis_turns<R>((double)b * phi2);
+    }
+    const int tot = n2 * cols;
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        const cx<R>* tl = t + ((long)v * 3 + l) * n + (long)i * np + (long)c0 * n2;
+        __syncthreads();
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int q = e / n2, b = e % n2;
+            buf[q * ld + b] = cmulc(tl[e], twb[b]);
+        }
+        __syncthreads();
+        fft_lines<R, kEpc, 256>(buf, g.fy, cols, 1, ld, twy, -1);
+        cx<R>* ul = u + ((long)v * 3 + l) * n + (long)i * np;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int j = e / cols, q = e % cols;
+            ul[(long)j * n3 + c0 + q] = buf[q * ld + j];
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_zpass_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ u,
+                                                    cx<R>* __restrict__ z, int RB) {
+    extern __shared__ __align__(16) char lds[];
+    const int n2 = g.n2, n3 = g.n3, ld = n3 + 1;
+    const long n = (long)g.n1 * n2 * n3, np = (long)n2 * n3;
+    const KSel ks = select_k(g, n);
+    const int i = blockIdx.x, v = blockIdx.y, j0 = blockIdx.z * RB;
+    const int rows = min(RB, n2 - j0);
+    cx<R>* buf = (cx<R>*)lds;
+    cx<R>* twz = buf + (size_t)RB * ld;
+    cx<R>* twc = twz + n3;
+    size_t off = (sizeof(cx<R>) * ((size_t)RB * ld + 2 * n3) + 15) & ~(size_t)15;
+    cx<double>* halfz = (cx<double>*)(lds + off);
+    cx<double>* rowz = halfz + n3;
+    cx<double>* lamy = rowz + RB;
+    const cx<double> L0 = zpass_setup<R>(g, ks, tb, i, j0, rows, twz, twc, halfz, rowz, lamy);
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    const int M = n2 * n3;
+    int s3m = g.s3 % M;
+    if (s3m < 0) s3m += M;
+    const double idz = 1.0 / g.dlt[2];
+    const int tot = rows * n3;
+    const long base = (long)i * np + (long)j0 * n3;
+    const unsigned char* codes = ks.codes + base;
+    cx<R> a1[kSplitEPT], a2[kSplitEPT];
+#pragma unroll
+    for (int s = 0; s < kSplitEPT; ++s) a1[s] = a2[s] = mk<R>((R)0, (R)0);
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        const cx<R>* ul = u + ((long)v * 3 + l) * n + base;
+        __syncthreads();
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int r = e / n3, c = e % n3;
+            buf[r * ld + c] = cmulc(ul[e], split_ztw<R>(twc, rot, c, j0 + r, s3m, M));
+        }
+        __syncthreads();
+        fft_lines<R, kEpc, 256>(buf, g.fz, rows, 1, ld, twz, -1);
+#pragma unroll
+        for (int s = 0; s < kSplitEPT; ++s) {
+            const int e = threadIdx.x + s * 256;
+            if (e < tot) {
+                const int r = e / n3, k = e % n3;
+                const int code = codes[e];
+                if (code != kMasked) {
+                    const cx<double> h = cmul(halfz[k], rowz[r]);
+                    cx<R> w1, w2;
+                    w_row_code<R>(L0, lamy[r], lam_from_halfturn(h.y, h.x, idz), code, l, &w1, &w2);
+                    const cx<R> val = buf[r * ld + k];
+                    a1[s] = a1[s] + cmulc(val, w1);
+                    a2[s] = a2[s] + cmulc(val, w2);
+                }
+            }
+        }
+    }
+    cx<R>* zb = z + (long)v * 2 * n + base;
+#pragma unroll
+    for (int s = 0; s < kSplitEPT; ++s) {
+        const int e = threadIdx.x + s * 256;
+        if (e < tot) {
+            zb[e] = a1[s];
+            zb[n + e] = a2[s];
+        }
+    }
+}
+
+template <typename R>
+static hipError_t split_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, cx<R>* u, int nvec,
+                            hipStream_t st) {
+    const int RB = split_rows(g.n2, g.n3), CB = split_cols(g.n3);
+    hipLaunchKernelGGL((k_zpass_fwd<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+                       zpass_lds_bytes<R>(RB, g.n3), st, g, tb, y, u, RB);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ypass_fwd<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
+                       ypass_lds_bytes<R>(CB, g.n2), st, g, tb, u, t, CB);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t split_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, cx<R>* u, int nvec,
+                            hipStream_t st) {
+    const int RB = split_rows(g.n2, g.n3), CB = split_cols(g.n3);
+    hipLaunchKernelGGL((k_ypass_adj<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
+                       ypass_lds_bytes<R>(CB, g.n2), st, g, tb, t, u, CB);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+                       zpass_lds_bytes<R>(RB, g.n3), st, g, tb, u, z, RB);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ kernel 2: x-line transforms
 // Tile = TB consecutive (c, b) positions q = c * n2 + b, all i.
 // MODE 0: t -> IDFT_x -> * inv_eps/n -> DFT_x -> t            (matvec, in place)
@@ -646,6 +924,7 @@ static size_t xline_lds_bytes(int n1, int TB) {
 template <typename R>
 static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, int nvec,
                             hipStream_t st) {
+    if (g.split[sizeof(R) == 8]) return split_fwd<R>(g, tb, y, t, t + (size_t)nvec * 3 * g.n1 * g.n2 * g.n3, nvec, st);
     if (!g.generic[sizeof(R) == 8]) {
         bool done = false;
         hipError_t e = launch_fixed_plane_fwd<R>(g, tb, y, t, nvec, st, &done);
@@ -664,6 +943,8 @@ static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* 
 template <typename R>
 static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, int nvec,
                             hipStream_t st) {
+    if (g.split[sizeof(R) == 8])
+        return split_adj<R>(g, tb, t, z, const_cast<cx<R>*>(t) + (size_t)nvec * 3 * g.n1 * g.n2 * g.n3, nvec, st);
     if (!g.generic[sizeof(R) == 8]) {
         bool done = false;
         hipError_t e = launch_fixed_plane_adj<R>(g, tb, t, z, nvec, st, &done);
@@ -815,10 +1096,31 @@ static hipError_t set_lds_limits() {
     return e;
 }
 
+template <typename R>
+static hipError_t split_limits() {
+    hipError_t e = set_max_lds(k_zpass_fwd<R>);
+    if (e == hipSuccess) e = set_max_lds(k_zpass_adj<R>);
+    if (e == hipSuccess) e = set_max_lds(k_ypass_fwd<R>);
+    if (e == hipSuccess) e = set_max_lds(k_ypass_adj<R>);
+    return e;
+}
+
+bool split_plane_needed(int n2, int n3, int fp64) {
+    return (fp64 ? plane_lds_bytes<double>(n2, n3) : plane_lds_bytes<float>(n2, n3)) > 160 * 1024;
+}
+size_t split_kernel_lds(int n2, int n3, int fp64) {
+    const int RB = split_rows(n2, n3), CB = split_cols(n3);
+    const size_t a = fp64 ? zpass_lds_bytes<double>(RB, n3) : zpass_lds_bytes<float>(RB, n3);
+    const size_t b = fp64 ? ypass_lds_bytes<double>(CB, n2) : ypass_lds_bytes<float>(CB, n2);
+    return a > b ? a : b;
+}
+
 hipError_t configure_kernels() {
     hipError_t e = set_lds_limits<float>();
     if (e != hipSuccess) return e;
     e = set_lds_limits<double>();
+    if (e == hipSuccess) e = split_limits<float>();
+    if (e == hipSuccess) e = split_limits<double>();
     if (e != hipSuccess) return e;
     return configure_fixed_kernels();
 }

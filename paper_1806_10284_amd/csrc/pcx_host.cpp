@@ -225,6 +225,7 @@ Grid Plan::grid(const double kappa[3]) const {
         g.generic[f] = (variant == PCX_VARIANT_GENERIC || tuned_nt[f] > 0) ? 1 : 0;
         g.plane_nt[f] = tuned_nt[f] > 0 ? tuned_nt[f] : 0;
     }
+    for (int f = 0; f < 2; ++f) g.split[f] = split_plane_needed(g.n2, g.n3, f) ? 1 : 0;
     g.nvk = 0;
     g.kaps = nullptr;
     return g;
@@ -414,14 +415,18 @@ namespace pcx {
 int Plan::check_fits(int precision) const {
     const int fp64 = precision == PCX_FP64;
     const size_t limit = 160 * 1024;
-    if (plane_kernel_lds(geom.n[1], geom.n[2], fp64) > limit || xline_kernel_lds(geom.n[0], fp64) > limit)
-        return fail(PCX_E_SIZE, "grid plane %dx%d does not fit in LDS at %s", geom.n[1], geom.n[2],
+    const bool plane_ok = plane_kernel_lds(geom.n[1], geom.n[2], fp64) <= limit ||
+                          split_kernel_lds(geom.n[1], geom.n[2], fp64) <= limit;
+    if (!plane_ok || xline_kernel_lds(geom.n[0], fp64) > limit)
+        return fail(PCX_E_SIZE, "grid %dx%dx%d does not fit the kernels' LDS at %s", geom.n[0], geom.n[1], geom.n[2],
                     fp64 ? "FP64" : "FP32");
     return PCX_OK;
 }
 
 int Plan::ensure_work(int nvec) {
-    const size_t need = (size_t)nvec * 3 * n * sizeof(cx<double>);
+    // 3n per vector; twice that when FP64 planes take the two-pass path (FP32 fits in the same bytes)
+    const size_t per = split_plane_needed(geom.n[1], geom.n[2], 1) ? 2 : 1;
+    const size_t need = per * (size_t)nvec * 3 * n * sizeof(cx<double>);
     return grow(&work, &work_cap, need);
 }
 

@@ -29,6 +29,8 @@ struct Grid {
     // per precision [0] FP32, [1] FP64:
     int generic[2];          // 1: runtime-sized kernels only; 0: fixed-size kernels where they exist
     int plane_nt[2];         // generic plane kernels' work-group size: 0 automatic, 256 / 512 / 1024
+    int split[2];            // 1: plane too large for LDS, two passes through a second 3n-per-vector
+                             //    workspace that follows the first one
     // several wave vectors in one launch: vectors are ordered [k][v] with nvk vectors per wave
     // vector; kaps (device, 3 per k) and codes (n bytes per k) then replace kap and codes
     int nvk;
@@ -75,6 +77,9 @@ hipError_t launch_modecode(const Grid& g, unsigned char* out, hipStream_t st);
 hipError_t launch_precond_diag(const Grid& g, const DeviceTables& tb, double* out, hipStream_t st);
 // set per-kernel LDS limits once per process
 hipError_t configure_kernels();
+// planes too large for LDS at this precision take the two-pass plane path; its LDS need
+bool split_plane_needed(int n2, int n3, int fp64);
+size_t split_kernel_lds(int n2, int n3, int fp64);
 
 // ---- fixed-size kernels (pcx_fixed.hip) ----
 // Each launcher sets *done when it has a kernel for the grid (and launched it), else leaves the

@@ -147,9 +147,20 @@ def _inside(avec, frac, shape, chunk=1 << 16) -> np.ndarray:
         ref = inv @ np.asarray(shape.p0, dtype=np.float64)
         d = np.asarray(shape.p1, dtype=np.float64) - np.asarray(shape.p0, dtype=np.float64)
         dd = float(d @ d)
+    # a sphere reaches at most radius * |row l of avec^-1| along fractional coordinate l, so a point
+    # whose minimum-image fractional offset exceeds that in some l is outside every image
+    half = shape.radius * np.linalg.norm(inv, axis=1) if isinstance(shape, Sphere) else None
     for s in range(0, frac.shape[0], chunk):
         df = frac[s:s + chunk] - ref
         df -= np.round(df)
+        if half is not None:
+            cand = np.all(np.abs(df) <= half + 1e-12, axis=1)
+            if not cand.any():
+                continue
+            sub = np.zeros(df.shape[0], dtype=bool)
+            sub[cand] = _sphere_images(df[cand], avec, shape.radius)
+            out[s:s + chunk] = sub
+            continue
         best = np.full(df.shape[0], np.inf)
         for img in _IMAGES:
             r = (df + img) @ avec.T            # Cartesian offset from the reference point
@@ -162,6 +173,14 @@ def _inside(avec, frac, shape, chunk=1 << 16) -> np.ndarray:
             best = np.minimum(best, dist2)
         out[s:s + chunk] = best <= shape.radius ** 2
     return out
+
+
+def _sphere_images(df, avec, radius):
+    best = np.full(df.shape[0], np.inf)
+    for img in _IMAGES:
+        r = (df + img) @ avec.T
+        best = np.minimum(best, np.einsum("ij,ij->i", r, r))
+    return best <= radius ** 2
 
 
 def sample_yee(avec, n, shift, shapes, eps_in: float, eps_out: float) -> np.ndarray:

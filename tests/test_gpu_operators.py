@@ -72,6 +72,11 @@ CASES = [
     ("gamma_sc16", S.SC, (16, 16, 16), (0.0, 0.0, 0.0)),
     ("tri_32_40_40", S.triclinic(6), (32, 40, 40), (0.37, -0.21, 0.08)),
     ("fcc_64_32_32", S.FCC, (64, 32, 32), (0.25, 0.5, -0.125)),
+    # planes too large for LDS take the two-pass plane path: FP64 at 128 x 128 and 100 x 120
+    # (ragged row and column blocks), FP32 at 144 x 150
+    ("split_hex_8_128_128", S.HEX, (8, 128, 128), (0.21, -0.33, 0.4)),
+    ("split_ortho_6_100_120", S.ORTHO, (6, 100, 120), (-0.3, 0.45, 0.05)),
+    ("split32_sc_4_144_150", S.SC, (4, 144, 150), (0.1, 0.2, -0.35)),
 ]
 
 
@@ -159,6 +164,22 @@ def test_nfsep_identity_with_explicit_curl_fcc64():
     A = double_curl(og, kappa)
     rhs = A @ (u / eps.reshape(-1))
     assert np.linalg.norm(uz - rhs) / np.linalg.norm(rhs) < 1e-11
+
+
+def test_triclinic128_fp64_two_pass_planes():
+    """128^3 triclinic in FP64 (its 128 x 128 planes take the two-pass path): every output entry."""
+    import torch
+    n = (128, 128, 128)
+    avec = S.triclinic(5)
+    og = lattice_geometry(avec, *n)
+    eps = S.voxel_to_yee(S.random_sphere_fill(avec, n, og.shift, seed=5))
+    kappa = tuple(S.random_kappas(5, 1)[0])
+    plan, og, spec, y = _setup(avec, n, kappa, eps, nvec=1, seed=14)
+    say("apply_Ar tri128 fp64")
+    z = torch.empty_like(_to_dev(y, "fp64"))
+    plan.pcx_apply_Ar(kappa, _to_dev(y, "fp64"), z)
+    torch.cuda.synchronize()
+    _cmp(z.cpu().numpy().T[:, 0], Ar_apply(spec, eps, y[:, 0]), "fp64", "tri128 fp64")
 
 
 def test_triclinic128_fp32_sampled():

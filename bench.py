@@ -63,6 +63,8 @@ def kernel_source_hash() -> str:
 
 # kernel-name prefix in a rocprofv3 trace -> (A_r kernel, precision)
 KERNEL_KEYS = [
+    ("pcx::k_p2_fwd<float", "plane_fwd_fp32"), ("pcx::k_p2_fwd<double", "plane_fwd_fp64"),
+    ("pcx::k_p2_adj<float", "plane_adj_fp32"), ("pcx::k_p2_adj<double", "plane_adj_fp64"),
     ("pcx::k_p3_fwd<float", "plane_fwd_fp32"), ("pcx::k_p3_fwd<double", "plane_fwd_fp64"),
     ("pcx::k_plane_fwd<float", "plane_fwd_fp32"), ("pcx::k_plane_fwd<double", "plane_fwd_fp64"),
     ("pcx::k_p3_adj<float", "plane_adj_fp32"), ("pcx::k_p3_adj<double", "plane_adj_fp64"),

@@ -56,7 +56,8 @@ typedef enum pcx_status {
 enum { PCX_FP64 = 0, PCX_FP32 = 1 };                 /* arithmetic / storage precision */
 enum { PCX_EPS_YEE3 = 0, PCX_EPS_VOXEL = 1 };        /* permittivity layouts */
 enum { PCX_MODE_FP64 = 0, PCX_MODE_FP32_REFINE = 1, PCX_MODE_FP32 = 2 };
-enum { PCX_VARIANT_AUTO = 0, PCX_VARIANT_GENERIC = 1 };  /* kernel variants of the A_r path */
+/* kernel variants of the A_r path */
+enum { PCX_VARIANT_AUTO = 0, PCX_VARIANT_GENERIC = 1, PCX_VARIANT_THREE_PLANE = 2, PCX_VARIANT_TWO_PLANE = 3 };
 
 #define PCX_MAX_N 256      /* largest supported n1, n2, n3 */
 #define PCX_MAX_BLOCK 64   /* largest LOBPCG block */
@@ -96,13 +97,17 @@ void pcx_plan_destroy(pcx_plan *p);
  * (else PCX_E_ARG).  Copied to the device (1/eps in FP64 and FP32). */
 int pcx_plan_set_eps(pcx_plan *p, const double *eps, int layout);
 
-/* Kernel variant used by the apply calls and the eigensolver of this plan.
- * PCX_VARIANT_AUTO (default): the fixed-size kernels compiled for common grid
- * shapes (all transform lengths known at compile time, the three field
- * components of a plane staged together) where the grid and precision have
- * them, else the generic kernels.  PCX_VARIANT_GENERIC: runtime-sized kernels
- * for every grid.  Both compute the same A_r (Section 5.1, Algorithms 5.1 and
- * 5.2) up to rounding order.  Errors: PCX_E_ARG (null plan, unknown variant). */
+/* Kernel variant used by the apply calls and the eigensolver of this plan (both
+ * precisions; replaces an autotuned choice).  PCX_VARIANT_AUTO (default): the
+ * fixed-size kernels compiled for common plane shapes (all transform lengths
+ * known at compile time; the three field components of a plane staged together
+ * in LDS, or two of them with the third held in registers when three planes do
+ * not fit) where the grid and precision have them, else the generic kernels.
+ * PCX_VARIANT_GENERIC: runtime-sized kernels for every grid.
+ * PCX_VARIANT_THREE_PLANE / _TWO_PLANE: that fixed-size kind where compiled,
+ * else the generic kernels.  All compute the same A_r (Section 5.1, Algorithms
+ * 5.1 and 5.2) up to rounding order.  Errors: PCX_E_ARG (null plan, unknown
+ * variant). */
 int pcx_plan_set_variant(pcx_plan *p, int variant);
 
 /* z = A_r y (eq. NFSEP) for nvec vectors.  y, z: device, 2n complex each, in
@@ -179,11 +184,12 @@ int pcx_solve_batch(pcx_plan *const *plans, int nplans, const int *nk, const dou
                     const pcx_opts *opts, int nworkers, double *lambda, void *const *y_out, pcx_stats *stats);
 
 /* Autotuner: times one A_r application of nvec vectors at kappa in `precision` for every
- * kernel variant the plan's grid has (the fixed-size kernels if compiled for this plane
- * shape and precision; the generic plane kernels with 256, 512 and, in FP32, 1024 threads)
- * with HIP events on the plan's stream, and keeps the fastest for the plan (affects every
- * later call on it, all precisions).  choice_out (may be NULL): 0 = fixed-size kernels, else
- * the generic work-group size; ms_out (may be NULL): its time per application in ms.
+ * kernel variant the plan's grid has (the three-plane and two-plane fixed-size kernels where
+ * compiled for this plane shape and precision; the generic plane kernels with 256, 512 and,
+ * in FP32, 1024 threads) with HIP events on the plan's stream, and keeps the fastest for the
+ * plan in that precision.  choice_out (may be NULL): -1 three-plane, -2 two-plane fixed-size
+ * kernels, else the generic work-group size; ms_out (may be NULL): its time per application
+ * in ms.
  * Allocates and frees two scratch blocks.  Errors: PCX_E_ARG, PCX_E_SIZE, PCX_E_DEVICE. */
 int pcx_plan_autotune(pcx_plan *p, const double kappa[3], int precision, int nvec, int *choice_out,
                       double *ms_out);

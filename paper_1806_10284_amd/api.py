@@ -103,7 +103,7 @@ class Plan:
         L.check(self._lib.pcx_plan_set_eps(self._ptr, e.ctypes.data_as(ctypes.c_void_p), int(layout)))
 
     def pcx_plan_set_variant(self, variant: int):
-        """PCX_VARIANT_AUTO (fixed-size kernels where available) or PCX_VARIANT_GENERIC."""
+        """PCX_VARIANT_AUTO (fixed-size kernels where available), _GENERIC, _THREE_PLANE or _TWO_PLANE."""
         L.check(self._lib.pcx_plan_set_variant(self._ptr, int(variant)))
 
     # -- operators
@@ -148,7 +148,8 @@ class Plan:
 
     def pcx_plan_autotune(self, kappa, precision=L.PCX_FP32, nvec: int = 8):
         """Times the kernel variants on this plan and keeps the fastest; returns (choice, ms):
-        choice 0 = fixed-size kernels, else the generic plane work-group size."""
+        choice -1 / -2 = three- / two-plane fixed-size kernels, else the generic plane work-group
+        size."""
         ch = ctypes.c_int()
         ms = ctypes.c_double()
         L.check(self._lib.pcx_plan_autotune(self._ptr, _kappa3(kappa), int(precision), int(nvec), ctypes.byref(ch),

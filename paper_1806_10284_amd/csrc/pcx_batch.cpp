@@ -156,7 +156,8 @@ extern "C" int pcx_plan_autotune(pcx_plan* pp, const double kappa[3], int precis
     }
     const int f = precision == PCX_FP64 ? 1 : 0;
     std::vector<int> cands;       // tuned_nt values: -1 fixed-size kernels, else generic group size
-    if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f)) cands.push_back(-1);
+    if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f, 3)) cands.push_back(-1);
+    if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f, 2)) cands.push_back(-2);
     cands.push_back(256);
     cands.push_back(512);
     if (!f) cands.push_back(1024);
@@ -183,7 +184,7 @@ extern "C" int pcx_plan_autotune(pcx_plan* pp, const double kappa[3], int precis
         return rc;
     }
     p->tuned_nt[f] = pick;
-    if (choice_out) *choice_out = pick < 0 ? 0 : pick;
+    if (choice_out) *choice_out = pick;
     if (ms_out) *ms_out = best;
     return PCX_OK;
 }

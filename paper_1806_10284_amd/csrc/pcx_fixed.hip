@@ -361,6 +361,261 @@ __global__ void __launch_bounds__(NT) k_p3_adj(Grid g, DeviceTables tb, const cx
     }
 }
 
+// ------------------------------------------------------------------ two-plane variant
+// Two plane buffers instead of three: components 0 and 1 go through the LDS transforms together
+// while component 2's mixed values wait in registers (forward), or its W^H row waits in registers
+// (adjoint).  W is still formed once per mode and vector.  Half a 64 x 64 FP32 group's LDS (two
+// groups per CU), and the only layout in which FP64 64 x 64 planes fit.
+template <typename R, int N2, int N3>
+struct P2 {
+    static constexpr int LD = N3 + 1;
+    static constexpr int PS = N2 * LD;
+    static constexpr int NP = N2 * N3;
+    static constexpr size_t kRbytes = sizeof(cx<R>) * (2 * (size_t)PS + 2 * N3 + 2 * N2);
+    static constexpr size_t kRpad = (kRbytes + 15) & ~(size_t)15;
+    static constexpr size_t bytes = kRpad + sizeof(cx<double>) * (N3 + 3 * N2) + sizeof(double) * 2 * N2;
+
+    cx<R>* pl;
+    cx<R>* twz;
+    cx<R>* twy;
+    cx<R>* twb;
+    cx<R>* twc;
+    cx<double>* halfz;
+    cx<double>* rowz;
+    cx<double>* lamy;
+    cx<double>* d10;
+    double* a01;
+    double* p10;
+
+    DEV P2(char* base) {
+        pl = (cx<R>*)base;
+        twz = pl + 2 * PS;
+        twy = twz + N3;
+        twb = twy + N2;
+        twc = twb + N2;
+        halfz = (cx<double>*)(base + kRpad);
+        rowz = halfz + N3;
+        lamy = rowz + N2;
+        d10 = lamy + N2;
+        a01 = (double*)(d10 + N2);
+        p10 = a01 + N2;
+    }
+};
+
+// z then y inverse transforms of NPL planes starting at plane 0, z-twiddles from registers
+template <typename R, int N2, int N3, int NT, int NPL, int EPT>
+DEV void p2_forward_planes(const P2<R, N2, N3>& L, const cx<R> tw[EPT]) {
+    constexpr int LD = N3 + 1, PS = N2 * LD, NP = N2 * N3;
+    ffft<R, N3, NPL * N2, NPL * N2, 0, LD, 1, NT, +1>(L.pl, L.twz);
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) {
+            const int j = e / N3, c = e % N3;
+#pragma unroll
+            for (int l = 0; l < NPL; ++l) L.pl[l * PS + j * LD + c] = cmul(L.pl[l * PS + j * LD + c], tw[s]);
+        }
+    }
+    __syncthreads();
+    ffft<R, N2, NPL * N3, N3, PS, 1, LD, NT, +1>(L.pl, L.twy);
+}
+
+template <typename R, int N2, int N3, int NT>
+__global__ void __launch_bounds__(NT) k_p2_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
+                                                cx<R>* __restrict__ t) {
+    using LT = P2<R, N2, N3>;
+    constexpr int LD = LT::LD, PS = LT::PS, NP = LT::NP;
+    constexpr int EPT = (NP + NT - 1) / NT;
+    extern __shared__ __align__(16) char lds[];
+    const LT L(lds);
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
+    const int i = blockIdx.x, v = blockIdx.y;
+    const long n = (long)g.n1 * NP;
+    const cx<R>* yb = y + (long)v * 2 * n + (long)i * NP;
+    const unsigned char* codes = ks.codes + (long)i * NP;
+    cx<R> y1[EPT], y2[EPT];
+    int code[EPT];
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) {
+            y1[s] = yb[e];
+            y2[s] = yb[n + e];
+            code[s] = codes[e];
+        }
+    }
+    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
+    const double idz = 1.0 / g.dlt[2];
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    int s3m = g.s3 % NP;
+    if (s3m < 0) s3m += NP;
+    __syncthreads();
+    cx<R> tw[EPT], u2[EPT];
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) {
+            const int j = e / N3, k = e % N3;
+            tw[s] = p3_ztw<R, N2, N3>(L, rot, k, j, s3m);
+            cx<R> u[3];
+            if (code[s] == kMasked) {
+                u[0] = u[1] = u[2] = mk<R>((R)0, (R)0);
+            } else {
+                cx<R> w[3][2];
+                p3_w<R, N2, N3>(L, L0, j, k, code[s], idz, w);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) u[l] = cmul(w[l][0], y1[s]) + cmul(w[l][1], y2[s]);
+            }
+            L.pl[j * LD + k] = u[0];
+            L.pl[PS + j * LD + k] = u[1];
+            u2[s] = u[2];
+        }
+    }
+    __syncthreads();
+    p2_forward_planes<R, N2, N3, NT, 2, EPT>(L, tw);
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+        cx<R>* out = t + ((long)v * 3 + l) * n + (long)i * NP;
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * NT;
+            if (NP % NT == 0 || e < NP) {
+                const int c = e / N2, b = e % N2;
+                out[e] = cmul(L.pl[l * PS + b * LD + c], L.twb[b]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) L.pl[(e / N3) * LD + e % N3] = u2[s];
+    }
+    __syncthreads();
+    p2_forward_planes<R, N2, N3, NT, 1, EPT>(L, tw);
+    cx<R>* out = t + ((long)v * 3 + 2) * n + (long)i * NP;
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) {
+            const int c = e / N2, b = e % N2;
+            out[e] = cmul(L.pl[b * LD + c], L.twb[b]);
+        }
+    }
+}
+
+// load components [l0, l0 + NPL) of t into the planes (conjugate y-twiddle), y then z forward
+// transforms with the conjugate z-twiddle in between
+template <typename R, int N2, int N3, int NT, int NPL>
+DEV void p2_adjoint_planes(const P2<R, N2, N3>& L, const cx<R>* __restrict__ t, long n, int v, int i, int l0,
+                           const cx<R>* __restrict__ rot, int s3m) {
+    constexpr int LD = N3 + 1, PS = N2 * LD, NP = N2 * N3;
+    constexpr int EPT = (NP + NT - 1) / NT;
+#pragma unroll
+    for (int l = 0; l < NPL; ++l) {
+        const cx<R>* src = t + ((long)v * 3 + l0 + l) * n + (long)i * NP;
+#pragma unroll
+        for (int s = 0; s < EPT; ++s) {
+            const int e = threadIdx.x + s * NT;
+            if (NP % NT == 0 || e < NP) {
+                const int c = e / N2, b = e % N2;
+                L.pl[l * PS + b * LD + c] = cmulc(src[e], L.twb[b]);
+            }
+        }
+    }
+    __syncthreads();
+    ffft<R, N2, NPL * N3, N3, PS, 1, LD, NT, -1>(L.pl, L.twy);
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) {
+            const int j = e / N3, c = e % N3;
+            const cx<R> tw = p3_ztw<R, N2, N3>(L, rot, c, j, s3m);
+#pragma unroll
+            for (int l = 0; l < NPL; ++l) L.pl[l * PS + j * LD + c] = cmulc(L.pl[l * PS + j * LD + c], tw);
+        }
+    }
+    __syncthreads();
+    ffft<R, N3, NPL * N2, NPL * N2, 0, LD, 1, NT, -1>(L.pl, L.twz);
+}
+
+// FP32: at most 128 registers per lane (4 waves per SIMD), so two 512-thread groups share a CU
+template <typename R, int N2, int N3, int NT>
+__global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) k_p2_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
+                                                cx<R>* __restrict__ z) {
+    using LT = P2<R, N2, N3>;
+    constexpr int LD = LT::LD, PS = LT::PS, NP = LT::NP;
+    constexpr int EPT = (NP + NT - 1) / NT;
+    extern __shared__ __align__(16) char lds[];
+    const LT L(lds);
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
+    const int i = blockIdx.x, v = blockIdx.y;
+    const long n = (long)g.n1 * NP;
+    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
+    const double idz = 1.0 / g.dlt[2];
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    int s3m = g.s3 % NP;
+    if (s3m < 0) s3m += NP;
+    __syncthreads();
+    p2_adjoint_planes<R, N2, N3, NT, 2>(L, t, n, v, i, 0, rot, s3m);
+    const unsigned char* codes = ks.codes + (long)i * NP;
+    // FP32: W's third row is formed again at the end rather than held, so that the group fits
+    // in 128 registers per lane (two groups per CU); FP64 groups are one per CU by LDS anyway
+    constexpr bool kHoldW2 = sizeof(R) == 8;
+    constexpr int NW = kHoldW2 ? EPT : 1;
+    cx<R> a1[EPT], a2[EPT], w2a[NW], w2b[NW];
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        a1[s] = a2[s] = mk<R>((R)0, (R)0);
+        if (kHoldW2) w2a[s % NW] = w2b[s % NW] = mk<R>((R)0, (R)0);
+        if (NP % NT == 0 || e < NP) {
+            const int j = e / N3, k = e % N3;
+            const int code = codes[e];
+            if (code != kMasked) {
+                cx<R> w[3][2];
+                p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    const cx<R> u = L.pl[l * PS + j * LD + k];
+                    a1[s] = a1[s] + cmulc(u, w[l][0]);
+                    a2[s] = a2[s] + cmulc(u, w[l][1]);
+                }
+                if (kHoldW2) {
+                    w2a[s % NW] = w[2][0];
+                    w2b[s % NW] = w[2][1];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    p2_adjoint_planes<R, N2, N3, NT, 1>(L, t, n, v, i, 2, rot, s3m);
+    cx<R>* zb = z + (long)v * 2 * n + (long)i * NP;
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+        const int e = threadIdx.x + s * NT;
+        if (NP % NT == 0 || e < NP) {
+            const int j = e / N3, k = e % N3;
+            const cx<R> u = L.pl[j * LD + k];
+            cx<R> wa = mk<R>((R)0, (R)0), wb = wa;
+            if (kHoldW2) {
+                wa = w2a[s % NW];
+                wb = w2b[s % NW];
+            } else {
+                const int code = codes[e];
+                if (code != kMasked) {
+                    cx<R> w[3][2];
+                    p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
+                    wa = w[2][0];
+                    wb = w[2][1];
+                }
+            }
+            zb[e] = a1[s] + cmulc(u, wa);
+            zb[n + e] = a2[s] + cmulc(u, wb);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ x-line kernel
 // Tile = TB consecutive (c, b) positions q, all N1 values of i, one component at a time:
 // t -> x-IDFT -> * inv_eps / n -> x-DFT -> t (in place).  scale is in the [l][q][a] layout.
@@ -429,6 +684,13 @@ __global__ void __launch_bounds__(NT) k_xl_fixed(Grid g, DeviceTables tb, const 
     X(40, 40, 448)      \
     X(64, 64, PCX_P3_NT64)
 
+// Two-plane kernels: (N2, N3, threads)
+#define PCX_P2_SIZES(X) \
+    X(64, 64, 512)
+
+#ifndef PCX_XL_NT64
+#define PCX_XL_NT64 512
+#endif
 // x-line kernels: (N1, tile, threads)
 #define PCX_XL_SIZES(X) \
     X(16, 128, 256)     \
@@ -436,7 +698,7 @@ __global__ void __launch_bounds__(NT) k_xl_fixed(Grid g, DeviceTables tb, const 
     X(40, 64, 256)      \
     X(48, 64, 256)      \
     X(60, 64, 256)      \
-    X(64, 64, 256)      \
+    X(64, 64, PCX_XL_NT64)  \
     X(128, 32, 256)
 
 template <typename F>
@@ -450,6 +712,10 @@ template <typename R>
 static hipError_t p3_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, int nvec,
                          hipStream_t st, bool* done) {
     *done = false;
+    // automatic choice: the two-plane kernel where compiled (measured faster for the forward
+    // pass at 64 x 64), else the three-plane one
+    const int kind = g.fixed_kind[sizeof(R) == 8];
+    if (kind == 2 || (kind == 0 && fixed_plane_available(g.n2, g.n3, sizeof(R) == 8, 2))) goto two;
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P3<R, A, B>::bytes <= kLdsMax) {                                          \
         hipLaunchKernelGGL((k_p3_fwd<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, y, t); \
@@ -458,6 +724,16 @@ static hipError_t p3_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, 
     }
     PCX_P3_SIZES(X)
 #undef X
+    if (kind == 3) return hipSuccess;
+two:
+#define X(A, B, T)                                                                                           \
+    if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
+        hipLaunchKernelGGL((k_p2_fwd<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, y, t); \
+        *done = true;                                                                                        \
+        return hipGetLastError();                                                                            \
+    }
+    PCX_P2_SIZES(X)
+#undef X
     return hipSuccess;
 }
 
@@ -465,6 +741,8 @@ template <typename R>
 static hipError_t p3_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, int nvec,
                          hipStream_t st, bool* done) {
     *done = false;
+    const int kind = g.fixed_kind[sizeof(R) == 8];
+    if (kind == 2) goto two;
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P3<R, A, B>::bytes <= kLdsMax) {                                          \
         hipLaunchKernelGGL((k_p3_adj<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
@@ -472,6 +750,16 @@ static hipError_t p3_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, 
         return hipGetLastError();                                                                            \
     }
     PCX_P3_SIZES(X)
+#undef X
+    if (kind == 3) return hipSuccess;
+two:
+#define X(A, B, T)                                                                                           \
+    if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
+        hipLaunchKernelGGL((k_p2_adj<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
+        *done = true;                                                                                        \
+        return hipGetLastError();                                                                            \
+    }
+    PCX_P2_SIZES(X)
 #undef X
     return hipSuccess;
 }
@@ -496,11 +784,19 @@ static hipError_t xl_fixed(const Grid& g, const DeviceTables& tb, const R* scale
     return hipSuccess;
 }
 
-bool fixed_plane_available(int n2, int n3, int fp64) {
+bool fixed_plane_available(int n2, int n3, int fp64, int kind) {
+    if (kind != 2) {
 #define X(A, B, T) \
-    if (n2 == A && n3 == B) return (fp64 ? P3<double, A, B>::bytes : P3<float, A, B>::bytes) <= kLdsMax;
-    PCX_P3_SIZES(X)
+    if (n2 == A && n3 == B && (fp64 ? P3<double, A, B>::bytes : P3<float, A, B>::bytes) <= kLdsMax) return true;
+        PCX_P3_SIZES(X)
 #undef X
+    }
+    if (kind != 3) {
+#define X(A, B, T) \
+    if (n2 == A && n3 == B && (fp64 ? P2<double, A, B>::bytes : P2<float, A, B>::bytes) <= kLdsMax) return true;
+        PCX_P2_SIZES(X)
+#undef X
+    }
     return false;
 }
 
@@ -536,6 +832,11 @@ static hipError_t fixed_limits() {
     if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_fwd<R, A, B, T>); \
     if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_adj<R, A, B, T>);
     PCX_P3_SIZES(X)
+#undef X
+#define X(A, B, T)                                                                 \
+    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_fwd<R, A, B, T>); \
+    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_adj<R, A, B, T>);
+    PCX_P2_SIZES(X)
 #undef X
 #define X(A, TBV, T) \
     if (e == hipSuccess) e = lds_limit(k_xl_fixed<R, A, TBV, T>);

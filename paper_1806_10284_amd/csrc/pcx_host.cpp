@@ -224,6 +224,9 @@ Grid Plan::grid(const double kappa[3]) const {
     for (int f = 0; f < 2; ++f) {
         g.generic[f] = (variant == PCX_VARIANT_GENERIC || tuned_nt[f] > 0) ? 1 : 0;
         g.plane_nt[f] = tuned_nt[f] > 0 ? tuned_nt[f] : 0;
+        g.fixed_kind[f] = (tuned_nt[f] == -1 || variant == PCX_VARIANT_THREE_PLANE)
+                              ? 3
+                              : ((tuned_nt[f] == -2 || variant == PCX_VARIANT_TWO_PLANE) ? 2 : 0);
     }
     for (int f = 0; f < 2; ++f) g.split[f] = split_plane_needed(g.n2, g.n3, f) ? 1 : 0;
     g.nvk = 0;
@@ -477,9 +480,11 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
 
 extern "C" int pcx_plan_set_variant(pcx_plan* p, int variant) {
     if (!p) return fail(PCX_E_ARG, "pcx_plan_set_variant: null plan");
-    if (variant != PCX_VARIANT_AUTO && variant != PCX_VARIANT_GENERIC)
+    if (variant < PCX_VARIANT_AUTO || variant > PCX_VARIANT_TWO_PLANE)
         return fail(PCX_E_ARG, "pcx_plan_set_variant: unknown variant %d", variant);
-    ((Plan*)p)->variant = variant;
+    Plan* pl = (Plan*)p;
+    pl->variant = variant;
+    pl->tuned_nt[0] = pl->tuned_nt[1] = 0;
     return PCX_OK;
 }
 

@@ -58,8 +58,8 @@ struct Plan {
 
     // kernel variant of the A_r path (PCX_VARIANT_*)
     int variant = PCX_VARIANT_AUTO;
-    // autotuned choice per precision ([0] FP32, [1] FP64): 0 untuned, -1 fixed-size kernels,
-    // 256 / 512 / 1024 generic kernels with that work-group size
+    // autotuned choice per precision ([0] FP32, [1] FP64): 0 untuned, -1 / -2 the three- / two-
+    // plane fixed-size kernels, 256 / 512 / 1024 generic kernels with that work-group size
     int tuned_nt[2] = {0, 0};
 
     // mode codes (n bytes each) and device kappas of the last multi-k launch

@@ -29,6 +29,8 @@ struct Grid {
     // per precision [0] FP32, [1] FP64:
     int generic[2];          // 1: runtime-sized kernels only; 0: fixed-size kernels where they exist
     int plane_nt[2];         // generic plane kernels' work-group size: 0 automatic, 256 / 512 / 1024
+    int fixed_kind[2];       // fixed-size plane kernels: 0 three-plane where compiled else two-plane,
+                             // 3 three-plane only, 2 two-plane only
     int split[2];            // 1: plane too large for LDS, two passes through a second 3n-per-vector
                              //    workspace that follows the first one
     // several wave vectors in one launch: vectors are ordered [k][v] with nvk vectors per wave
@@ -93,7 +95,8 @@ hipError_t launch_fixed_plane_adj(const Grid& g, const DeviceTables& tb, const c
 template <typename R>
 hipError_t launch_fixed_xline(const Grid& g, const DeviceTables& tb, const R* scale, cx<R>* t, int nvec,
                               hipStream_t st, bool* done);
-bool fixed_plane_available(int n2, int n3, int fp64);
+// kind: 0 any, 3 the three-plane kernels, 2 the two-plane kernels
+bool fixed_plane_available(int n2, int n3, int fp64, int kind = 0);
 bool fixed_xline_available(int n1, long np, int fp64);
 hipError_t configure_fixed_kernels();
 

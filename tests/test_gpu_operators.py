@@ -27,7 +27,7 @@ def say(*a):
     print("[gpu-case]", *a, file=sys.stderr, flush=True)
 
 
-VARIANTS = {"auto": 0, "generic": 1}
+VARIANTS = {"auto": 0, "generic": 1, "three_plane": 2, "two_plane": 3}
 
 
 def _setup(avec, n, kappa, eps, nvec=1, seed=0, variant="auto"):
@@ -124,7 +124,7 @@ def test_QS_and_adjoint_and_eigvec(name, avec, n, kappa, prec):
         _cmp(z[:, v], QS_adjoint(spec, ur[:, v]), prec, "QS_adjoint")
 
 
-@pytest.mark.parametrize("variant", ["auto", "generic"])
+@pytest.mark.parametrize("variant", ["auto", "generic", "two_plane"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_apply_Ar_fcc64_full_size(prec, variant):
     """The 64^3 diamond workload: every output entry against the oracle (numpy FFT route)."""

@@ -134,7 +134,7 @@ int pcx_eigvec(pcx_plan *p, const double kappa[3], int precision, const void *y,
 
 typedef struct pcx_opts {
     int mode;            /* PCX_MODE_FP64 | PCX_MODE_FP32_REFINE | PCX_MODE_FP32 */
-    int block;           /* LOBPCG block size >= nev (0: nev + max(4, (nev+1)/2)) */
+    int block;           /* LOBPCG block size >= nev (0: nev + max(2, (nev+4)/5)) */
     int max_iter;        /* total iterations over both phases */
     double tol;          /* converged when ||A_r y - lambda y|| <= tol * lambda (||y|| = 1) */
     double tol_fp32;     /* FP32_REFINE: leave the FP32 phase at this residual */

@@ -24,6 +24,9 @@
 #ifndef PCX_ORTHO_PASSES
 #define PCX_ORTHO_PASSES 1
 #endif
+#ifndef PCX_FLOOR_FACTOR
+#define PCX_FLOOR_FACTOR 1024
+#endif
 #ifndef PCX_FP32_STALL
 #define PCX_FP32_STALL 12
 #endif
@@ -34,6 +37,10 @@ namespace pcx {
 constexpr int kOrthoPasses = PCX_ORTHO_PASSES;
 // iterations without a 10% drop of the worst residual that end a reduced-precision phase
 constexpr int kFp32Stall = PCX_FP32_STALL;
+// the same for the FP64 phase (then the solve reports the bands it did not converge)
+constexpr int kFp64Stall = 40;
+// FP64 absolute residual floor in units of eps ||A_r||
+constexpr double kFloor = PCX_FLOOR_FACTOR;
 
 // ---------------------------------------------------------------- the solver
 
@@ -71,11 +78,16 @@ struct Solver {
 
     // Band j has converged when its relative residual is below tol or, for eigenvalues so close
     // to zero (next to Gamma) that tol |theta| is below what the arithmetic can resolve, when its
-    // absolute residual is at the precision's floor 64 eps ||A_r||.
+    // absolute residual is at the working-precision floor c eps ||A_r||: c = 1024 in FP64 (the
+    // level where LOBPCG's basis stops improving next to Gamma, ~1e-13 ||A_r||), c = 1 in FP32
+    // (the matvec's own rounding).  The eigenvalue error of such a band is ~ residual^2 / gap.
+    // In the FP64 phase the floor only decides the final verdict: the iteration runs on towards tol
+    // until it stops improving (kFp64Stall), so that bands which can reach tol do.
     template <typename R>
-    bool converged(int j, double tol) const {
-        const double eps = sizeof(R) == 8 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
-        return resid[j] <= tol || rabs[j] <= 64.0 * eps * anorm;
+    bool converged(int j, double tol, bool final_verdict = false) const {
+        const double floor = sizeof(R) == 8 ? kFloor * 1.1102230246251565e-16 : 5.9604644775390625e-08;
+        if (resid[j] <= tol) return true;
+        return (sizeof(R) == 4 || final_verdict) && rabs[j] <= floor * anorm;
     }
 
     int sync() {
@@ -225,7 +237,11 @@ struct Solver {
             if (worst < 0.9 * best) {
                 best = worst;
                 stall = 0;
-            } else if (sizeof(R) == 4 && ++stall >= kFp32Stall) {
+            } else if (++stall >= (sizeof(R) == 4 ? kFp32Stall : kFp64Stall) &&
+                       (sizeof(R) == 8 || worst < 1e-2 || st.iterations_fp32 >= 40)) {
+                // FP32: the rounding floor (or bands it cannot resolve at all, next to Gamma),
+                // refinement follows; FP64: stagnation at the floor of a band the tolerance cannot
+                // reach, stop before the basis loses orthogonality
                 return PCX_OK;
             }
             if (sizeof(R) == 4 && refine_after && st.iterations_fp32 >= max_iter / 2) return PCX_OK;
@@ -341,7 +357,34 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     S.n = n;
     S.N = N;
     if (nev < 1) return fail(PCX_E_ARG, "pcx_solve: nev must be >= 1");
-    int b = S.o.block > 0 ? S.o.block : nev + std::max(4, (nev + 1) / 2);
+    // Lambda_q^{-1} per mode (the preconditioner), also on the host for the start block
+    int rc0 = p->grow(&p->prec, &p->prec_cap, n * sizeof(double));
+    if (rc0) return rc0;
+    {
+        Grid g0;
+        if ((rc0 = p->grid_for(kappa, &g0))) return rc0;
+        hipError_t e0 = launch_precond_diag(g0, p->tables, (double*)p->prec, p->stream);
+        if (e0 != hipSuccess) return hip_fail(e0, "pcx_solve: preconditioner");
+    }
+    std::vector<double> hp(n);
+    if (hipMemcpyAsync(hp.data(), p->prec, n * sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess)
+        return fail(PCX_E_DEVICE, "pcx_solve: preconditioner copy");
+    std::vector<long> modes(n);
+    for (long q = 0; q < n; ++q) modes[q] = q;
+    const long nsort = std::min<long>(n, PCX_MAX_BLOCK);
+    std::partial_sort(modes.begin(), modes.begin() + nsort, modes.end(), [&](long a, long c) { return hp[a] > hp[c]; });
+    // Block guard: small (the dense block work grows as the square of the block; at 64^3 with 10
+    // bands block 12 solves in 0.72x the time of block 15), except next to Gamma, where one plane
+    // wave has Lambda_q far below the others (its two bands go to zero) and the small guard
+    // stalls above the tolerance: there the larger guard.
+    int guard = std::max(2, (nev + 4) / 5);
+    {
+        const long ref = std::min<long>(nsort - 1, std::max<long>(1, (nev + 1) / 2));
+        if (hp[modes[0]] > 0 && hp[modes[ref]] > 0 && hp[modes[0]] > 10.0 * hp[modes[ref]])
+            guard = std::max(4, (nev + 1) / 2);
+    }
+    int b = S.o.block > 0 ? S.o.block : nev + guard;
     if (b < nev) return fail(PCX_E_ARG, "pcx_solve: block (%d) smaller than nev (%d)", b, nev);
     if (b > PCX_MAX_BLOCK || 3L * b > N - 2) return fail(PCX_E_ARG, "pcx_solve: block %d too large for this grid", b);
     if (S.o.mode < PCX_MODE_FP64 || S.o.mode > PCX_MODE_FP32) return fail(PCX_E_ARG, "pcx_solve: bad mode");
@@ -391,25 +434,14 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     (void)hipEventCreate(&S.ev0);
     (void)hipEventCreate(&S.ev1);
 
-    Grid g;
-    if ((rc = p->grid_for(kappa, &g))) return rc;
-    hipError_t e = launch_precond_diag(g, p->tables, S.prec, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner");
-
+    hipError_t e = hipSuccess;
     Blocks<double> B64{};
     Blocks<float> B32{};
     if (use64) B64 = carve<double>(p->lob_mem, b, N);
     if (use32) B32 = carve<float>((char*)p->lob_mem + bytes64, b, N);
     // start block: the plane waves of the smallest Lambda_q (the homogeneous-medium eigenvectors,
     // both polarisations) plus a small seeded random perturbation
-    std::vector<double> hp(n);
-    e = hipMemcpyAsync(hp.data(), S.prec, n * sizeof(double), hipMemcpyDeviceToHost, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner copy");
-    if ((rc = S.sync())) return rc;
-    std::vector<long> modes(n);
-    for (long q = 0; q < n; ++q) modes[q] = q;
     const long nm = std::min<long>(n, (b + 1) / 2);
-    std::partial_sort(modes.begin(), modes.begin() + nm, modes.end(), [&](long a, long c) { return hp[a] > hp[c]; });
     {
         double dmin = 0;                  // smallest nonzero 1 / Lambda_q
         for (long q = 0; q < n; ++q)
@@ -457,7 +489,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         int conv = 0;
         for (int j = 0; j < nev; ++j) {
             if (j < PCX_MAX_BLOCK) S.st.residual[j] = S.resid[j];
-            if (use64 ? S.converged<double>(j, S.o.tol) : S.converged<float>(j, S.o.tol)) ++conv;
+            if (use64 ? S.converged<double>(j, S.o.tol, true) : S.converged<float>(j, S.o.tol, true)) ++conv;
         }
         S.st.converged = conv;
         // outputs: y (FP64), x = B^{-1} Q_r Sigma_r y

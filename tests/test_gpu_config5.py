@@ -3,10 +3,11 @@ grid 128^3 (n = 2,097,152), random spheres (radii U[0.08, 0.15]) filled to 30 % 
 20 bands at 16 seeded wave vectors solved as one batch with FP32 matvecs and FP64 refinement (the
 refinement's FP64 planes of 128 x 128 take the two-pass plane path).
 
-Checks: every problem converges to relative residual 1e-9; for the first wave vector the first
-eigenvectors, mapped by pcx_eigvec, satisfy the explicit GEP C*C x = lambda B x of the oracle
-(sparse Yee curl with Bloch wraps) within the bound tol * sqrt(max Lambda_q) / ||Sigma_r y||
-derived in test_gpu_solve, and x* B x = lambda.
+Checks: every problem converges (relative residual 1e-9, or the FP64 working-precision floor
+1024 eps ||A_r|| for bands below it); for the first wave vector the first eigenvectors, mapped by
+pcx_eigvec, satisfy the explicit GEP C*C x = lambda B x of the oracle (sparse Yee curl with Bloch
+wraps) within the bound r * sqrt(max Lambda_q) / ||Sigma_r y|| derived in test_gpu_solve, r the
+accepted relative residual, and x* B x = lambda.
 """
 from __future__ import annotations
 
@@ -64,7 +65,11 @@ def test_triclinic128_batch_fp32_refine():
     d = preconditioner_diag(spectrum(og, k0))
     lq = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
     sig_y = np.sqrt(np.einsum("i,ij->j", lq, np.abs(Y) ** 2))
-    bound = 1.5 * tol * np.sqrt(lq.max()) / sig_y
+    # the solver accepts relative residual tol, or absolute residual 1024 eps ||A_r|| with
+    # ||A_r|| <= max Lambda_q / min eps (bands it cannot resolve further)
+    floor = 1024 * np.finfo(np.float64).eps / 2 * lq.max() / eps_yee.min()
+    eff = np.maximum(tol, floor / lam[0][:m])
+    bound = 1.5 * eff * np.sqrt(lq.max()) / sig_y
     say("config5 residuals", res, "bounds", bound)
     assert np.all(res < bound), (res, bound)
     b = eps_yee.reshape(-1)

@@ -21,9 +21,6 @@
 #include "pcx_dense.h"
 #include "pcx_host.h"
 
-#ifndef PCX_ORTHO_PASSES
-#define PCX_ORTHO_PASSES 1
-#endif
 #ifndef PCX_FLOOR_FACTOR
 #define PCX_FLOOR_FACTOR 1024
 #endif
@@ -33,8 +30,6 @@
 
 namespace pcx {
 
-// classical Gram-Schmidt passes of W against X per iteration
-constexpr int kOrthoPasses = PCX_ORTHO_PASSES;
 // iterations without a 10% drop of the worst residual that end a reduced-precision phase
 constexpr int kFp32Stall = PCX_FP32_STALL;
 // the same for the FP64 phase (then the solve reports the bands it did not converge)
@@ -253,20 +248,31 @@ struct Solver {
             for (int j = 0; j < b; ++j)
                 if (!converged<R>(j, tol)) act.push_back(j);
             const int na = (int)act.size();
-            // W_act <- W_act - X (X^H W_act), selecting the active columns in the first pass
-            for (int pass = 0; pass < kOrthoPasses; ++pass) {
-                const int wc = pass == 0 ? b : na;
-                std::vector<zc> G, C((size_t)(b + wc) * na, zc(0, 0));
-                if ((rc = gram<R>(colset(B.X, b), colset(B.W, wc), G))) return rc;
-                for (int c = 0; c < na; ++c) {
-                    const int src = pass == 0 ? act[c] : c;
-                    for (int r = 0; r < b; ++r) C[(size_t)r * na + c] = -G[(size_t)r * wc + src];
-                    C[(size_t)(b + src) * na + c] = 1.0;
-                }
-                if ((rc = combine<R>(colset(B.X, b, B.W, wc), C, colset(B.T1, na)))) return rc;
+            // W_act <- (W_act - X G) R^{-1} with one Gram product and one combination:
+            // [X | W]^H W gives G = X^H W_act and W_act^H W_act, and the projected Gram matrix
+            // W_act^H W_act - G^H G (X has orthonormal columns) gives R (Cholesky-QR, SVQB fallback)
+            {
+                std::vector<zc> G;                   // (2b) x b
+                if ((rc = gram<R>(colset(B.X, b, B.W, b), colset(B.W, b), G))) return rc;
+                std::vector<zc> M((size_t)na * na), Cw;
+                for (int r = 0; r < na; ++r)
+                    for (int c = 0; c < na; ++c) {
+                        zc v = G[(size_t)(b + act[r]) * b + act[c]];
+                        for (int q = 0; q < b; ++q)
+                            v -= std::conj(G[(size_t)q * b + act[r]]) * G[(size_t)q * b + act[c]];
+                        M[(size_t)r * na + c] = v;
+                    }
+                orthonormalizer(na, M, Cw);
+                std::vector<zc> C((size_t)(2 * b) * na, zc(0, 0));
+                for (int c = 0; c < na; ++c)
+                    for (int r = 0; r < na; ++r) {
+                        const zc w = Cw[(size_t)r * na + c];
+                        C[(size_t)(b + act[r]) * na + c] = w;
+                        for (int q = 0; q < b; ++q) C[(size_t)q * na + c] -= G[(size_t)q * b + act[r]] * w;
+                    }
+                if ((rc = combine<R>(colset(B.X, b, B.W, b), C, colset(B.T1, na)))) return rc;
                 std::swap(B.W, B.T1);
             }
-            if ((rc = orthonormalize<R>(B.W, B.T1, na))) return rc;
             if ((rc = matvec<R>(B.W, B.AW, na))) return rc;
             // Rayleigh-Ritz on S = [X W P]; without P if the basis is too ill-conditioned
             std::vector<double> th;

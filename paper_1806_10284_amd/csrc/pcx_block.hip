@@ -268,18 +268,29 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
 }
 
 // ------------------------------------------------------------------ Y = S C
-// One thread per row: outputs in chunks of kOutChunk FP64 accumulators, S re-read per chunk
-// (from L2 when the work-group's rows are still resident); C[k][o] is uniform across the
-// work-group and comes through the scalar cache.
-constexpr int kOutChunk = 16;
+// One thread per row: outputs in chunks of OC FP64 accumulators, S re-read per chunk (from L2
+// when the work-group's rows are still resident).  C (ks x m) is staged in LDS when it fits and
+// read there by all lanes at once (a broadcast), else taken through the scalar cache.
+#ifndef PCX_COMBINE_CHUNK
+#define PCX_COMBINE_CHUNK 16
+#endif
+constexpr int kOutChunk = PCX_COMBINE_CHUNK;
+constexpr int kCombineLds = 64 * 1024;     // C in LDS up to this size
 
-template <typename R>
+template <typename R, bool CLDS>
 __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __restrict__ C, ColSet Y, long N) {
+    extern __shared__ __align__(16) char lds[];
     __shared__ const cx<R>* scol[kMaxCols];
     __shared__ cx<R>* ycol[kMaxCols];
     const int ks = S.total(), m = Y.total();
     for (int c = threadIdx.x; c < ks; c += blockDim.x) scol[c] = col_ptr<const cx<R>>(S, c, N);
     for (int c = threadIdx.x; c < m; c += blockDim.x) ycol[c] = col_ptr<cx<R>>(Y, c, N);
+    const cx<double>* Cm = C;
+    if (CLDS) {
+        cx<double>* Cs = (cx<double>*)lds;
+        for (int e = threadIdx.x; e < ks * m; e += blockDim.x) Cs[e] = C[e];
+        Cm = Cs;
+    }
     __syncthreads();
     for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < N; r += (long)gridDim.x * blockDim.x) {
         for (int m0 = 0; m0 < m; m0 += kOutChunk) {
@@ -288,7 +299,7 @@ __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __r
             for (int u = 0; u < kOutChunk; ++u) acc[u].x = acc[u].y = 0.0;
             for (int k = 0; k < ks; ++k) {
                 const cx<double> s = to64(scol[k][r]);
-                const cx<double>* crow = C + (size_t)k * m + m0;
+                const cx<double>* crow = Cm + (size_t)k * m + m0;
 #pragma unroll
                 for (int u = 0; u < kOutChunk; ++u) {
                     if (m0 + u < m) {
@@ -316,7 +327,11 @@ hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y,
     if (S.total() < 1 || Y.total() < 1 || S.total() > kMaxCols || Y.total() > kMaxCols) return hipErrorInvalidValue;
     long blocks = (N + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL((k_combine<R>), dim3((unsigned)blocks), dim3(256), 0, st, S, C, Y, N);
+    const size_t cbytes = sizeof(cx<double>) * (size_t)S.total() * Y.total();
+    if (cbytes <= (size_t)kCombineLds)
+        hipLaunchKernelGGL((k_combine<R, true>), dim3((unsigned)blocks), dim3(256), cbytes, st, S, C, Y, N);
+    else
+        hipLaunchKernelGGL((k_combine<R, false>), dim3((unsigned)blocks), dim3(256), 0, st, S, C, Y, N);
     return hipGetLastError();
 }
 
@@ -508,6 +523,12 @@ hipError_t configure_block_kernels() {
     G(double, 1, false); G(double, 2, false); G(double, 3, false); G(double, 4, false);
     G(double, 1, true); G(double, 2, true); G(double, 3, true); G(double, 4, true);
 #undef G
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_combine<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kCombineLds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_combine<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kCombineLds);
     return e;
 }
 

@@ -22,8 +22,35 @@ void hermitize(int k, std::vector<zc>& A) {
     }
 }
 
-// implicit QL on the symmetric tridiagonal (d diagonal, e[i] = T(i+1, i)), rotating the columns of Z
-static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Z) {
+// complex products in plain real arithmetic (no special-value handling: every entry here is finite)
+static inline zc cmul(zc a, zc b) {
+    return zc(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+static inline zc cjmul(zc a, zc b) {   // conj(a) * b
+    return zc(a.real() * b.real() + a.imag() * b.imag(), a.real() * b.imag() - a.imag() * b.real());
+}
+static inline zc mulcj(zc a, zc b) {   // a * conj(b)
+    return zc(a.real() * b.real() + a.imag() * b.imag(), a.imag() * b.real() - a.real() * b.imag());
+}
+
+// sqrt(a^2 + b^2), scaled only where the squares could leave the double range
+static inline double pyth(double a, double b) {
+    const double m = std::max(std::fabs(a), std::fabs(b));
+    if (m > 1e-150 && m < 1e150) return std::sqrt(a * a + b * b);
+    return std::hypot(a, b);
+}
+
+// one plane rotation of the QL iteration: columns i and i + 1 of the eigenvector matrix Z become
+// (c z_i - s z_{i+1}, s z_i + c z_{i+1})
+struct Rot {
+    double c, s;
+    int i;
+};
+
+// implicit QL on the symmetric tridiagonal (d diagonal, e[i] = T(i+1, i)); the eigenvector matrix
+// is the product of the recorded rotations (applied later to the wanted columns only)
+static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<Rot>& rots) {
+    rots.clear();
     if (n == 0) return true;
     e.resize(n);
     e[n - 1] = 0.0;
@@ -38,15 +65,15 @@ static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, st
             if (m == l) break;
             if (++iter > 200) return false;
             double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = std::hypot(g, 1.0);
+            double r = pyth(g, 1.0);
             g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
             double s = 1.0, c = 1.0, p = 0.0;
             int i = m - 1;
             bool deflated = false;
             for (; i >= l; --i) {
-                double f = s * e[i];
+                const double f = s * e[i];
                 const double b = c * e[i];
-                r = std::hypot(f, g);
+                r = pyth(f, g);
                 e[i + 1] = r;
                 if (r == 0.0) {
                     d[i + 1] -= p;
@@ -61,11 +88,7 @@ static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, st
                 p = s * r;
                 d[i + 1] = g + p;
                 g = c * r - b;
-                for (int q = 0; q < n; ++q) {
-                    f = Z[(size_t)q * n + i + 1];
-                    Z[(size_t)q * n + i + 1] = s * Z[(size_t)q * n + i] + c * f;
-                    Z[(size_t)q * n + i] = c * Z[(size_t)q * n + i] - s * f;
-                }
+                rots.push_back({c, s, i});
             }
             if (deflated) continue;
             d[l] -= p;
@@ -76,49 +99,54 @@ static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, st
     return true;
 }
 
-bool herm_eig(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>& V) {
+bool herm_eig(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>& V, int ncols) {
+    if (ncols < 0 || ncols > k) ncols = k;
     hermitize(k, A);
-    // Q accumulates the Householder reflections: A = Q T Q^H
-    std::vector<zc> Q((size_t)k * k, zc(0, 0));
-    for (int i = 0; i < k; ++i) Q[(size_t)i * k + i] = 1.0;
-    std::vector<zc> v(k), p(k), q(k);
+    // Householder reduction A = Q T Q^H, Q = H_0 H_1 ... with H_j = I - 2 v_j v_j^H acting on the
+    // indices above j; each step updates only the trailing block A[j+1:, j+1:]
+    std::vector<zc> R((size_t)k * k, zc(0, 0));   // row j: v_j (zero below index j + 1)
+    std::vector<char> has(k, 0);
+    std::vector<zc> p(k), q(k);
     for (int j = 0; j + 2 < k; ++j) {
-        // x = A[j+1:, j]
+        zc* aj = &A[(size_t)j * k];                 // row j holds conj of column j
         double xn2 = 0.0;
-        for (int i = j + 1; i < k; ++i) xn2 += std::norm(A[(size_t)i * k + j]);
+        for (int i = j + 1; i < k; ++i) xn2 += std::norm(aj[i]);
         const double xn = std::sqrt(xn2);
         if (xn == 0.0) continue;
-        const zc x0 = A[(size_t)(j + 1) * k + j];
+        const zc x0 = std::conj(aj[j + 1]);          // A[j+1][j]
         const double ax0 = std::abs(x0);
         const zc ph = ax0 > 0 ? x0 / ax0 : zc(1, 0);
-        const zc alpha = -ph * xn;                 // reflect x onto alpha e_1
-        // v = x - alpha e1, normalised
-        for (int i = 0; i < k; ++i) v[i] = 0.0;
-        for (int i = j + 1; i < k; ++i) v[i] = A[(size_t)i * k + j];
+        const zc alpha = -ph * xn;                   // reflect x = A[j+1:, j] onto alpha e_1
+        zc* v = &R[(size_t)j * k];
+        for (int i = j + 1; i < k; ++i) v[i] = std::conj(aj[i]);
         v[j + 1] -= alpha;
         double vn2 = 0.0;
         for (int i = j + 1; i < k; ++i) vn2 += std::norm(v[i]);
         if (vn2 == 0.0) continue;
         const double vi = 1.0 / std::sqrt(vn2);
         for (int i = j + 1; i < k; ++i) v[i] *= vi;
-        // H = I - 2 v v^H ;  A <- H A H via p = A v, K = v^H p, q = p - K v ; A -= 2 (v q^H + q v^H)
-        for (int i = 0; i < k; ++i) {
-            zc s = 0.0;
-            for (int c = j + 1; c < k; ++c) s += A[(size_t)i * k + c] * v[c];
-            p[i] = s;
+        has[j] = 1;
+        // H A22 H = A22 - 2 (v q^H + q v^H), p = A22 v, K = v^H p (real), q = p - K v
+        for (int i = j + 1; i < k; ++i) {
+            const zc* ai = &A[(size_t)i * k];
+            double sr = 0.0, si = 0.0;
+            for (int c = j + 1; c < k; ++c) {
+                sr += ai[c].real() * v[c].real() - ai[c].imag() * v[c].imag();
+                si += ai[c].real() * v[c].imag() + ai[c].imag() * v[c].real();
+            }
+            p[i] = zc(sr, si);
         }
-        zc K = 0.0;
-        for (int i = j + 1; i < k; ++i) K += std::conj(v[i]) * p[i];
-        for (int i = 0; i < k; ++i) q[i] = p[i] - K * v[i];
-        for (int i = 0; i < k; ++i)
-            for (int c = 0; c < k; ++c)
-                A[(size_t)i * k + c] -= 2.0 * (v[i] * std::conj(q[c]) + q[i] * std::conj(v[c]));
-        // Q <- Q H
-        for (int i = 0; i < k; ++i) {
-            zc s = 0.0;
-            for (int c = j + 1; c < k; ++c) s += Q[(size_t)i * k + c] * v[c];
-            for (int c = j + 1; c < k; ++c) Q[(size_t)i * k + c] -= 2.0 * s * std::conj(v[c]);
+        double K = 0.0;
+        for (int i = j + 1; i < k; ++i) K += cjmul(v[i], p[i]).real();
+        for (int i = j + 1; i < k; ++i) q[i] = p[i] - K * v[i];
+        for (int i = j + 1; i < k; ++i) {
+            zc* ai = &A[(size_t)i * k];
+            const zc vi2 = 2.0 * v[i], qi2 = 2.0 * q[i];
+            for (int c = j + 1; c < k; ++c) ai[c] -= mulcj(vi2, q[c]) + mulcj(qi2, v[c]);
         }
+        // the reduced column and row: alpha e_1
+        A[(size_t)(j + 1) * k + j] = alpha;
+        aj[j + 1] = std::conj(alpha);
     }
     // phases that make the sub-diagonal real and non-negative
     std::vector<zc> dph(k, zc(1, 0));
@@ -130,24 +158,51 @@ bool herm_eig(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>&
         e[i] = as;
         dph[i + 1] = as > 0 ? dph[i] * s / as : dph[i];
     }
-    std::vector<double> Z((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
-    if (!tridiag_ql(k, d, e, Z)) return false;
+    std::vector<Rot> rots;
+    rots.reserve((size_t)4 * k * k);
+    if (!tridiag_ql(k, d, e, rots)) return false;
     std::vector<int> idx(k);
     std::iota(idx.begin(), idx.end(), 0);
     std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
     w.resize(k);
-    V.assign((size_t)k * k, zc(0, 0));
-    // V = Q diag(dph) Z
-    for (int c = 0; c < k; ++c) {
-        const int src = idx[c];
-        w[c] = d[src];
-        for (int i = 0; i < k; ++i) {
-            zc s = 0.0;
-            for (int m = 0; m < k; ++m) s += Q[(size_t)i * k + m] * dph[m] * Z[(size_t)m * k + src];
-            V[(size_t)i * k + c] = s;
+    for (int c = 0; c < k; ++c) w[c] = d[idx[c]];
+    // Z = G_1 G_2 ... G_N, so Z[:, wanted] = G_1 (G_2 (... (G_N E))) with E the unit columns:
+    // the rotations in reverse order on a k x ncols block (row m: entries of row m of Z)
+    std::vector<double> Zw((size_t)k * ncols, 0.0);
+    for (int c = 0; c < ncols; ++c) Zw[(size_t)idx[c] * ncols + c] = 1.0;
+    for (size_t t = rots.size(); t-- > 0;) {
+        const Rot& g = rots[t];
+        double* zi = &Zw[(size_t)g.i * ncols];
+        double* zj = zi + ncols;
+        for (int c = 0; c < ncols; ++c) {
+            const double a0 = zi[c], a1 = zj[c];
+            zi[c] = g.c * a0 + g.s * a1;
+            zj[c] = g.c * a1 - g.s * a0;
         }
     }
+    // eigenvector c = Q diag(dph) Z[:, idx[c]]: the phases, then H_{k-3}, ..., H_0 in turn
+    std::vector<zc> X((size_t)ncols * k);           // row c: eigenvector c
+    for (int c = 0; c < ncols; ++c) {
+        zc* x = &X[(size_t)c * k];
+        for (int m = 0; m < k; ++m) x[m] = dph[m] * Zw[(size_t)m * ncols + c];
+    }
+    for (int j = k - 3; j >= 0; --j) {
+        if (!has[j]) continue;
+        const zc* v = &R[(size_t)j * k];
+        for (int c = 0; c < ncols; ++c) {
+            zc* x = &X[(size_t)c * k];
+            double sr = 0.0, si = 0.0;
+            for (int i = j + 1; i < k; ++i) {
+                sr += v[i].real() * x[i].real() + v[i].imag() * x[i].imag();
+                si += v[i].real() * x[i].imag() - v[i].imag() * x[i].real();
+            }
+            const zc s2(2.0 * sr, 2.0 * si);
+            for (int i = j + 1; i < k; ++i) x[i] -= cmul(s2, v[i]);
+        }
+    }
+    V.assign((size_t)k * ncols, zc(0, 0));
+    for (int i = 0; i < k; ++i)
+        for (int c = 0; c < ncols; ++c) V[(size_t)i * ncols + c] = X[(size_t)c * k + i];
     return true;
 }
 
@@ -164,7 +219,7 @@ bool cholesky(int k, const std::vector<zc>& G, std::vector<zc>& L, double rel_to
         L[(size_t)j * k + j] = ljj;
         for (int i = j + 1; i < k; ++i) {
             zc s = G[(size_t)i * k + j];
-            for (int m = 0; m < j; ++m) s -= L[(size_t)i * k + m] * std::conj(L[(size_t)j * k + m]);
+            for (int m = 0; m < j; ++m) s -= mulcj(L[(size_t)i * k + m], L[(size_t)j * k + m]);
             L[(size_t)i * k + j] = s / ljj;
         }
     }
@@ -173,22 +228,30 @@ bool cholesky(int k, const std::vector<zc>& G, std::vector<zc>& L, double rel_to
 
 void solve_LH(int k, const std::vector<zc>& L, const std::vector<zc>& B, int m, std::vector<zc>& X) {
     X = B;
-    for (int c = 0; c < m; ++c)
-        for (int i = k - 1; i >= 0; --i) {
-            zc s = X[(size_t)i * m + c];
-            for (int j = i + 1; j < k; ++j) s -= std::conj(L[(size_t)j * k + i]) * X[(size_t)j * m + c];
-            X[(size_t)i * m + c] = s / L[(size_t)i * k + i].real();
+    for (int i = k - 1; i >= 0; --i) {
+        zc* xi = &X[(size_t)i * m];
+        for (int j = i + 1; j < k; ++j) {
+            const zc l = L[(size_t)j * k + i];
+            const zc* xj = &X[(size_t)j * m];
+            for (int c = 0; c < m; ++c) xi[c] -= cjmul(l, xj[c]);
         }
+        const double inv = L[(size_t)i * k + i].real();
+        for (int c = 0; c < m; ++c) xi[c] /= inv;
+    }
 }
 
 void solve_L(int k, const std::vector<zc>& L, const std::vector<zc>& B, int m, std::vector<zc>& X) {
     X = B;
-    for (int c = 0; c < m; ++c)
-        for (int i = 0; i < k; ++i) {
-            zc s = X[(size_t)i * m + c];
-            for (int j = 0; j < i; ++j) s -= L[(size_t)i * k + j] * X[(size_t)j * m + c];
-            X[(size_t)i * m + c] = s / L[(size_t)i * k + i].real();
+    for (int i = 0; i < k; ++i) {
+        zc* xi = &X[(size_t)i * m];
+        for (int j = 0; j < i; ++j) {
+            const zc l = L[(size_t)i * k + j];
+            const zc* xj = &X[(size_t)j * m];
+            for (int c = 0; c < m; ++c) xi[c] -= cmul(l, xj[c]);
         }
+        const double inv = L[(size_t)i * k + i].real();
+        for (int c = 0; c < m; ++c) xi[c] /= inv;
+    }
 }
 
 bool rayleigh_ritz(int k, std::vector<zc> GA, std::vector<zc> GB, int want, double chol_tol,
@@ -217,11 +280,8 @@ bool rayleigh_ritz(int k, std::vector<zc> GA, std::vector<zc> GB, int want, doub
     solve_L(k, L, Yh, k, H);                    // H = L^{-1} Y^H = L^{-1} GA L^{-H}
     std::vector<double> w;
     std::vector<zc> V;
-    if (!herm_eig(k, H, w, V)) return false;
-    std::vector<zc> Vw((size_t)k * want);
-    for (int i = 0; i < k; ++i)
-        for (int c = 0; c < want; ++c) Vw[(size_t)i * want + c] = V[(size_t)i * k + c];
-    solve_LH(k, L, Vw, want, C);
+    if (!herm_eig(k, H, w, V, want)) return false;
+    solve_LH(k, L, V, want, C);
     for (int i = 0; i < k; ++i)
         for (int c = 0; c < want; ++c) C[(size_t)i * want + c] *= sc[i];
     theta.assign(w.begin(), w.begin() + want);
@@ -260,17 +320,40 @@ void orthonormalizer(int m, std::vector<zc> G, std::vector<zc>& C) {
 
 }  // namespace pcx
 
-// Host-only self-test hook for the dense routines (interleaved complex, row-major).
-extern "C" int pcxd_herm_eig(int k, const double* a, double* w, double* v) {
-    std::vector<pcx::zc> A((size_t)k * k);
-    for (size_t i = 0; i < A.size(); ++i) A[i] = pcx::zc(a[2 * i], a[2 * i + 1]);
+// Host-only self-test hooks for the dense routines (interleaved complex, row-major).
+static std::vector<pcx::zc> load_cx(int n, const double* a) {
+    std::vector<pcx::zc> A((size_t)n);
+    for (int i = 0; i < n; ++i) A[i] = pcx::zc(a[2 * i], a[2 * i + 1]);
+    return A;
+}
+
+static void store_cx(const std::vector<pcx::zc>& A, double* a) {
+    for (size_t i = 0; i < A.size(); ++i) {
+        a[2 * i] = A[i].real();
+        a[2 * i + 1] = A[i].imag();
+    }
+}
+
+// all k eigenvalues; v: k x ncols eigenvectors of the lowest ncols
+extern "C" int pcxd_herm_eig_cols(int k, const double* a, int ncols, double* w, double* v) {
     std::vector<double> ww;
     std::vector<pcx::zc> V;
-    if (!pcx::herm_eig(k, A, ww, V)) return -1;
+    if (!pcx::herm_eig(k, load_cx(k * k, a), ww, V, ncols)) return -1;
     for (int i = 0; i < k; ++i) w[i] = ww[i];
-    for (size_t i = 0; i < V.size(); ++i) {
-        v[2 * i] = V[i].real();
-        v[2 * i + 1] = V[i].imag();
-    }
+    store_cx(V, v);
+    return 0;
+}
+
+extern "C" int pcxd_herm_eig(int k, const double* a, double* w, double* v) {
+    return pcxd_herm_eig_cols(k, a, k, w, v);
+}
+
+// lowest `want` pairs of the pencil (ga, gb); c: k x want
+extern "C" int pcxd_rayleigh_ritz(int k, const double* ga, const double* gb, int want, double* theta, double* c) {
+    std::vector<double> th;
+    std::vector<pcx::zc> C;
+    if (!pcx::rayleigh_ritz(k, load_cx(k * k, ga), load_cx(k * k, gb), want, 1e-14, th, C)) return -1;
+    for (int i = 0; i < want; ++i) theta[i] = th[i];
+    store_cx(C, c);
     return 0;
 }

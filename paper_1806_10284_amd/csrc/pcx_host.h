@@ -47,7 +47,7 @@ struct Plan {
     size_t gram_part_cap = 0;
     void* small_mem = nullptr;
     size_t small_cap = 0;
-    void* pinned = nullptr;          // pinned host staging for coefficient uploads
+    void* pinned = nullptr;          // pinned host staging: coefficient uploads, small results
     size_t pinned_cap = 0;
 
     // mixing-basis codes for the last kappa (n bytes), recomputed when kappa changes

@@ -6,7 +6,8 @@
 //     bound kappa(Q_r* B^{-1} Q_r) <= kappa(B^{-1}) of Section 5.2 the preconditioned operator
 //     has condition number at most eps_max / eps_min),
 //   * Gram matrices accumulated in FP64 on the device and the Rayleigh-Ritz step solved in
-//     FP64 on the host (Cholesky of the basis Gram matrix + cyclic Jacobi),
+//     FP64 on the host (Cholesky of the basis Gram matrix, Householder tridiagonalisation and
+//     implicit QL),
 //   * an optional FP32 phase (FP32 storage and matvecs) followed by an FP64 phase that
 //     refines the same block to the requested residual.
 #include <chrono>
@@ -63,6 +64,9 @@ struct Solver {
     double* res_out = nullptr;           // device, b
     static constexpr int kSlots = 8;
     zc* pinned = nullptr;                // host, kSlots * slot_elems
+    zc* host_gram = nullptr;             // host (pinned), gram results
+    double* host_theta = nullptr;        // host (pinned), b
+    double* host_res = nullptr;          // host (pinned), b
     cx<double>* dev_slots = nullptr;     // device, kSlots * slot_elems
     size_t slot_elems = 0;
     int slot_next = 0;
@@ -107,25 +111,37 @@ struct Solver {
         return rc;
     }
 
-    // G (ka x kb) = A^H B on the host.  herm: B = [A] or [A | AA] with each ka x ka half Hermitian;
-    // the device computes the upper part and the lower part is mirrored here.
+    // G (ka x kb) = A^H B on the host, in two halves: gram_async queues the product and its copy
+    // into pinned host memory, gram_read takes it after a stream synchronisation.  herm: B = [A]
+    // or [A | AA] with each ka x ka half Hermitian; the device computes the upper part and the
+    // lower part is mirrored here.
     template <typename R>
-    int gram(const ColSet& A, const ColSet& B, std::vector<zc>& G, bool herm = false) {
+    int gram_async(const ColSet& A, const ColSet& B, bool herm) {
         const int ka = A.total(), kb = B.total();
         hipError_t e = launch_gram<R>(A, B, N, gram_part, gram_chunks, dev_small, p->stream, herm);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: gram");
-        G.resize((size_t)ka * kb);
-        e = hipMemcpyAsync(G.data(), dev_small, sizeof(zc) * ka * kb, hipMemcpyDeviceToHost, p->stream);
+        e = hipMemcpyAsync(host_gram, dev_small, sizeof(zc) * ka * kb, hipMemcpyDeviceToHost, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: gram copy");
-        int rc = sync();
-        if (rc || !herm) return rc;
+        return PCX_OK;
+    }
+
+    void gram_read(int ka, int kb, std::vector<zc>& G, bool herm) {
+        G.assign(host_gram, host_gram + (size_t)ka * kb);
+        if (!herm) return;
         for (int h = 0; h < kb / ka; ++h)
             for (int i = 0; i < ka; ++i) {
                 zc* row = G.data() + (size_t)i * kb + (size_t)h * ka;
                 row[i] = zc(row[i].real(), 0.0);
                 for (int j = 0; j < i; ++j) row[j] = std::conj(G[(size_t)j * kb + (size_t)h * ka + i]);
             }
-        return PCX_OK;
+    }
+
+    template <typename R>
+    int gram(const ColSet& A, const ColSet& B, std::vector<zc>& G, bool herm = false) {
+        int rc = gram_async<R>(A, B, herm);
+        if (!rc) rc = sync();
+        if (!rc) gram_read(A.total(), B.total(), G, herm);
+        return rc;
     }
 
     // Y = S C with C (ks x m) from the host.  The coefficients go through a ring of pinned host
@@ -159,22 +175,26 @@ struct Solver {
         return PCX_OK;
     }
 
+    // residual norms of the b Ritz pairs, W <- prec (AX - X theta); with wg, also the Gram matrix
+    // [X | W]^H W (2b x b) of the new W, under the same stream synchronisation
     template <typename R>
-    int residuals(Blocks<R>& B) {
-        hipError_t e = hipMemcpyAsync(dev_theta, theta.data(), sizeof(double) * b, hipMemcpyHostToDevice, p->stream);
+    int residuals(Blocks<R>& B, std::vector<zc>* wg = nullptr) {
+        std::copy(theta.begin(), theta.begin() + b, host_theta);
+        hipError_t e = hipMemcpyAsync(dev_theta, host_theta, sizeof(double) * b, hipMemcpyHostToDevice, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: theta copy");
         e = launch_residual<R>(colset(B.X, b), colset(B.AX, b), dev_theta, o.precondition ? prec : nullptr, n,
                                colset(B.W, b), res_part, gram_chunks, res_out, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual");
-        std::vector<double> r2(b);
-        e = hipMemcpyAsync(r2.data(), res_out, sizeof(double) * b, hipMemcpyDeviceToHost, p->stream);
+        e = hipMemcpyAsync(host_res, res_out, sizeof(double) * b, hipMemcpyDeviceToHost, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual copy");
-        int rc = sync();
+        int rc = wg ? gram_async<R>(colset(B.X, b, B.W, b), colset(B.W, b), false) : PCX_OK;
+        if (!rc) rc = sync();
         if (rc) return rc;
+        if (wg) gram_read(2 * b, b, *wg, false);
         resid.resize(b);
         rabs.resize(b);
         for (int j = 0; j < b; ++j) {
-            rabs[j] = std::sqrt(std::max(r2[j], 0.0));
+            rabs[j] = std::sqrt(std::max(host_res[j], 0.0));
             resid[j] = rabs[j] / std::max(std::fabs(theta[j]), 1e-300);
         }
         return PCX_OK;
@@ -214,8 +234,9 @@ struct Solver {
         const double chol_tol = sizeof(R) == 8 ? 1e-13 : 1e-9;
         double best = 1e300;
         int stall = 0;
+        std::vector<zc> G;                       // [X | W]^H W, (2b) x b
         for (;;) {
-            if ((rc = residuals<R>(B))) return rc;   // W <- prec (AX - X theta) for all b columns
+            if ((rc = residuals<R>(B, &G))) return rc;   // W <- prec (AX - X theta) for all b columns
             bool all = true;
             double worst = 0;                    // over the bands still open
             for (int j = 0; j < nev; ++j) {
@@ -249,11 +270,10 @@ struct Solver {
                 if (!converged<R>(j, tol)) act.push_back(j);
             const int na = (int)act.size();
             // W_act <- (W_act - X G) R^{-1} with one Gram product and one combination:
-            // [X | W]^H W gives G = X^H W_act and W_act^H W_act, and the projected Gram matrix
-            // W_act^H W_act - G^H G (X has orthonormal columns) gives R (Cholesky-QR, SVQB fallback)
+            // [X | W]^H W (taken with the residuals) gives G = X^H W_act and W_act^H W_act, and the
+            // projected Gram matrix W_act^H W_act - G^H G (X has orthonormal columns) gives R
+            // (Cholesky-QR, SVQB fallback)
             {
-                std::vector<zc> G;                   // (2b) x b
-                if ((rc = gram<R>(colset(B.X, b, B.W, b), colset(B.W, b), G))) return rc;
                 std::vector<zc> M((size_t)na * na), Cw;
                 for (int r = 0; r < na; ++r)
                     for (int c = 0; c < na; ++c) {
@@ -421,15 +441,20 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     const size_t slots = Solver::kSlots * S.slot_elems * sizeof(cx<double>);
     const size_t small = gram_out + slots + 2 * b * sizeof(double) + 1024;
     if ((rc = p->grow(&p->small_mem, &p->small_cap, std::max<size_t>(small, 1 << 16)))) return rc;
-    if (p->pinned_cap < slots) {
+    // pinned host memory: coefficient slots, gram results, theta, residuals
+    const size_t pinned_bytes = slots + gram_out + 2 * b * sizeof(double);
+    if (p->pinned_cap < pinned_bytes) {
         if (p->pinned) (void)hipHostFree(p->pinned);
         p->pinned = nullptr;
         p->pinned_cap = 0;
-        e0 = hipHostMalloc(&p->pinned, slots, hipHostMallocDefault);
+        e0 = hipHostMalloc(&p->pinned, pinned_bytes, hipHostMallocDefault);
         if (e0 != hipSuccess) return hip_fail(e0, "pcx_solve: pinned staging");
-        p->pinned_cap = slots;
+        p->pinned_cap = pinned_bytes;
     }
     S.pinned = (zc*)p->pinned;
+    S.host_gram = (zc*)((char*)p->pinned + slots);
+    S.host_theta = (double*)((char*)p->pinned + slots + gram_out);
+    S.host_res = S.host_theta + b;
     S.prec = (double*)p->prec;
     S.gram_part = (cx<double>*)p->gram_part;
     S.res_part = (double*)((char*)p->gram_part + gp);

@@ -36,7 +36,23 @@ DEV R* col_ptr(const ColSet& S, int c, long N) {
 // HERM: B = [A] or [A | A'] (kb = nh ka, nh = 1 or 2; the first ka columns of B are the columns of
 // A) with every ka x ka half of A^H B Hermitian, so A is staged once, as B's first half, and only
 // the block upper triangle of each half is computed (the caller mirrors the rest).
-constexpr int kGramRows = 16;
+// The source column and the interleaved position of every tile column are worked out once per
+// work-group (tables in LDS), so staging a row tile is a table read, a load and a store.
+#ifndef PCX_GRAM_ROWS
+#define PCX_GRAM_ROWS 16
+#endif
+constexpr int kGramRows = PCX_GRAM_ROWS;
+#ifndef PCX_GRAM_WIDE
+#define PCX_GRAM_WIDE 0
+#endif
+#ifndef PCX_GRAM_PREFETCH
+#define PCX_GRAM_PREFETCH 0
+#endif
+#ifndef PCX_GRAM_STAGE
+#define PCX_GRAM_STAGE 8
+#endif
+constexpr int kStage = PCX_GRAM_STAGE;         // prefetch registers per thread
+constexpr int kTileCols = 2 * kMaxCols + 8;    // A and B columns with block padding
 constexpr int kMaxPB = 2;      // pair-blocks per thread (MPB = 1 or 2 per instantiation)
 
 template <int BLK, bool HERM>
@@ -58,7 +74,8 @@ DEV void pair_block(int pb, int nbA, int nbB, int* ba, int* bb) {
 }
 
 template <typename R, int BLK, bool HERM, int MPB>
-__global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long rows_per_chunk,
+__global__ void __launch_bounds__((MPB == 1 && BLK <= 2) ? 512 : 256) k_gram(ColSet A, ColSet B, long N,
+                                                                             long rows_per_chunk,
                                                cx<double>* __restrict__ part) {
     extern __shared__ __align__(16) char lds[];
     const int ka = A.total(), kb = B.total();
@@ -69,15 +86,32 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
     const int ncol = bofs + kbP;
     const int ldr = ncol + 1;                           // row stride (complex), padded
     cx<double>* T = (cx<double>*)lds;                   // [kGramRows][ldr]: A columns then B columns
-    const cx<R>** acol = (const cx<R>**)(T + (size_t)kGramRows * ldr);
-    const cx<R>** bcol = acol + kMaxCols;
-    for (int c = threadIdx.x; c < ka; c += blockDim.x) acol[c] = col_ptr<const cx<R>>(A, c, N);
-    for (int c = threadIdx.x; c < kb; c += blockDim.x) bcol[c] = col_ptr<const cx<R>>(B, c, N);
-
+    const cx<R>** tsrc = (const cx<R>**)(T + (size_t)kGramRows * ldr);   // [ncol] source column or null
+    int* tpos = (int*)(tsrc + kTileCols);                                 // [ncol] interleaved position
     const long r0 = (long)blockIdx.x * rows_per_chunk;
     const long r1 = min(N, r0 + rows_per_chunk);
     const int nbA = kaP / BLK, nbB = kbP / BLK;
     const int PB = HERM ? (kb / ka) * nbA * (nbA + 1) / 2 : nbA * nbB;
+    // padded column c of the tile: A columns [0, kaP) unless HERM, then B columns (HERM: half h at
+    // h kaP), stored at its interleaved position
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+        const cx<R>* src = nullptr;
+        int pos;
+        if (c < bofs) {
+            pos = (c % BLK) * nbA + c / BLK;
+            if (c < ka) src = col_ptr<const cx<R>>(A, c, N);
+        } else {
+            int cb = c - bofs;
+            pos = bofs + (cb % BLK) * nbB + cb / BLK;
+            if (HERM) {
+                const int h = cb / kaP, q = cb % kaP;
+                cb = q < ka ? h * ka + q : -1;
+            }
+            if (cb >= 0 && cb < kb) src = col_ptr<const cx<R>>(B, cb, N);
+        }
+        tsrc[c] = src;
+        tpos[c] = pos;
+    }
     int pba[MPB], pbb[MPB];
 #pragma unroll
     for (int p = 0; p < MPB; ++p) {
@@ -95,30 +129,46 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
             for (int w = 0; w < BLK; ++w) acc[p][u][w].x = acc[p][u][w].y = 0.0;
     __syncthreads();
 
-    for (long rt = r0; rt < r1; rt += kGramRows) {
+    // the next row tile is loaded into registers while the current one is multiplied, when every
+    // thread's share of a tile fits in kStage values
+    const int nst = (ncol * kGramRows + (int)blockDim.x - 1) / (int)blockDim.x;
+    const bool prefetch = PCX_GRAM_PREFETCH && nst <= kStage;
+    cx<R> pre[kStage];
+    auto fetch = [&](long rt) {
         const int rows = (int)min((long)kGramRows, r1 - rt);
-        // padded column c of the tile: A columns [0, kaP) unless HERM, then B columns (HERM: half
-        // h at h kaP); stored at its interleaved position
-        for (int e = threadIdx.x; e < ncol * kGramRows; e += blockDim.x) {
-            const int c = e / kGramRows, r = e % kGramRows;
-            cx<double> val;
-            val.x = val.y = 0.0;
-            int pos;
-            if (c < bofs) {
-                pos = (c % BLK) * nbA + c / BLK;
-                if (r < rows && c < ka) val = to64(acol[c][rt + r]);
-            } else {
-                int cb = c - bofs;
-                pos = bofs + (cb % BLK) * nbB + cb / BLK;
-                if (HERM) {
-                    const int h = cb / kaP, q = cb % kaP;
-                    cb = q < ka ? h * ka + q : -1;
-                }
-                if (r < rows && cb >= 0 && cb < kb) val = to64(bcol[cb][rt + r]);
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int e = threadIdx.x + j * blockDim.x;
+            pre[j].x = pre[j].y = (R)0;
+            if (e < ncol * kGramRows) {
+                const int c = e / kGramRows, r = e % kGramRows;
+                const cx<R>* src = tsrc[c];
+                if (src && r < rows) pre[j] = src[rt + r];
             }
-            T[(size_t)r * ldr + pos] = val;
         }
-        __syncthreads();
+    };
+    if (prefetch && r0 < r1) fetch(r0);
+    for (long rt = r0; rt < r1; rt += kGramRows) {
+        if (prefetch) {
+#pragma unroll
+            for (int j = 0; j < kStage; ++j) {
+                const int e = threadIdx.x + j * blockDim.x;
+                if (e < ncol * kGramRows) T[(size_t)(e % kGramRows) * ldr + tpos[e / kGramRows]] = to64(pre[j]);
+            }
+            __syncthreads();
+            if (rt + kGramRows < r1) fetch(rt + kGramRows);
+        } else {
+            const int rows = (int)min((long)kGramRows, r1 - rt);
+            for (int e = threadIdx.x; e < ncol * kGramRows; e += blockDim.x) {
+                const int c = e / kGramRows, r = e % kGramRows;
+                const cx<R>* src = tsrc[c];
+                cx<double> val;
+                val.x = val.y = 0.0;
+                if (src && r < rows) val = to64(src[rt + r]);
+                T[(size_t)r * ldr + tpos[c]] = val;
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int p = 0; p < MPB; ++p) {
             if (pba[p] >= 0) {
@@ -137,9 +187,11 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
                     for (int u = 0; u < BLK; ++u)
 #pragma unroll
                         for (int w = 0; w < BLK; ++w) {
-                            // conj(a) * b
-                            acc[p][u][w].x += av[u].x * bv[w].x + av[u].y * bv[w].y;
-                            acc[p][u][w].y += av[u].x * bv[w].y - av[u].y * bv[w].x;
+                            // conj(a) * b, as a chain of FMAs into the accumulator
+                            acc[p][u][w].x = fma(av[u].x, bv[w].x, acc[p][u][w].x);
+                            acc[p][u][w].x = fma(av[u].y, bv[w].y, acc[p][u][w].x);
+                            acc[p][u][w].y = fma(av[u].x, bv[w].y, acc[p][u][w].y);
+                            acc[p][u][w].y = fma(-av[u].y, bv[w].x, acc[p][u][w].y);
                         }
                 }
             }
@@ -206,11 +258,14 @@ static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>
     const int nbA = kaP / BLK, nbB = kbP / BLK;
     const int PB = HERM ? (kb / ka) * nbA * (nbA + 1) / 2 : nbA * nbB;
     const size_t lds = sizeof(cx<double>) * (size_t)kGramRows * ((HERM ? 0 : kaP) + kbP + 1) +
-                       2 * sizeof(void*) * kMaxCols;
+                       (sizeof(void*) + sizeof(int)) * kTileCols;
     // more than kMaxPB * 256 pair-blocks: slices of them in separate work-groups (grid y)
     const int slices = (PB + kMaxPB * 256 - 1) / (kMaxPB * 256);
     if (PB <= 256)
         hipLaunchKernelGGL((k_gram<R, BLK, HERM, 1>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
+    else if (PCX_GRAM_WIDE && BLK <= 2 && PB <= 512)
+        hipLaunchKernelGGL((k_gram<R, BLK, HERM, 1>), dim3(chunks), dim3((PB + 63) / 64 * 64), lds, st, A, B, N, rpc,
+                           part);
     else
         hipLaunchKernelGGL((k_gram<R, BLK, HERM, 2>), dim3(chunks, slices), dim3(256), lds, st, A, B, N, rpc,
                            part);
@@ -268,13 +323,19 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
 }
 
 // ------------------------------------------------------------------ Y = S C
-// One thread per row: outputs in chunks of OC FP64 accumulators, S re-read per chunk (from L2
-// when the work-group's rows are still resident).  C (ks x m) is staged in LDS when it fits and
-// read there by all lanes at once (a broadcast), else taken through the scalar cache.
+// Each thread takes kRowsPerThread rows (a work-group's rows are consecutive per pass, so every
+// column access is coalesced), and the outputs in chunks of kOutChunk FP64 accumulators per row,
+// S re-read per chunk (from L2 when the work-group's rows are still resident).  C (ks x m) is
+// staged in LDS when it fits and read there by all lanes at once (a broadcast, reused for all the
+// thread's rows), else taken through the scalar cache.
 #ifndef PCX_COMBINE_CHUNK
-#define PCX_COMBINE_CHUNK 16
+#define PCX_COMBINE_CHUNK 12
+#endif
+#ifndef PCX_COMBINE_ROWS
+#define PCX_COMBINE_ROWS 2
 #endif
 constexpr int kOutChunk = PCX_COMBINE_CHUNK;
+constexpr int kRowsPerThread = PCX_COMBINE_ROWS;
 constexpr int kCombineLds = 64 * 1024;     // C in LDS up to this size
 
 template <typename R, bool CLDS>
@@ -292,30 +353,50 @@ __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __r
         Cm = Cs;
     }
     __syncthreads();
-    for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < N; r += (long)gridDim.x * blockDim.x) {
-        for (int m0 = 0; m0 < m; m0 += kOutChunk) {
-            cx<double> acc[kOutChunk];
+    const long span = (long)blockDim.x * kRowsPerThread;
+    for (long base = blockIdx.x * span; base < N; base += (long)gridDim.x * span) {
+        long row[kRowsPerThread];
 #pragma unroll
-            for (int u = 0; u < kOutChunk; ++u) acc[u].x = acc[u].y = 0.0;
+        for (int j = 0; j < kRowsPerThread; ++j) row[j] = base + threadIdx.x + (long)j * blockDim.x;
+        for (int m0 = 0; m0 < m; m0 += kOutChunk) {
+            cx<double> acc[kRowsPerThread][kOutChunk];
+#pragma unroll
+            for (int j = 0; j < kRowsPerThread; ++j)
+#pragma unroll
+                for (int u = 0; u < kOutChunk; ++u) acc[j][u].x = acc[j][u].y = 0.0;
             for (int k = 0; k < ks; ++k) {
-                const cx<double> s = to64(scol[k][r]);
+                cx<double> s[kRowsPerThread];
+#pragma unroll
+                for (int j = 0; j < kRowsPerThread; ++j) {
+                    s[j].x = s[j].y = 0.0;
+                    if (row[j] < N) s[j] = to64(scol[k][row[j]]);
+                }
                 const cx<double>* crow = Cm + (size_t)k * m + m0;
 #pragma unroll
                 for (int u = 0; u < kOutChunk; ++u) {
                     if (m0 + u < m) {
                         const cx<double> c = crow[u];
-                        acc[u].x += s.x * c.x - s.y * c.y;
-                        acc[u].y += s.x * c.y + s.y * c.x;
+#pragma unroll
+                        for (int j = 0; j < kRowsPerThread; ++j) {
+                            acc[j][u].x = fma(s[j].x, c.x, acc[j][u].x);
+                            acc[j][u].x = fma(-s[j].y, c.y, acc[j][u].x);
+                            acc[j][u].y = fma(s[j].x, c.y, acc[j][u].y);
+                            acc[j][u].y = fma(s[j].y, c.x, acc[j][u].y);
+                        }
                     }
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kOutChunk; ++u) {
-                if (m0 + u < m) {
-                    cx<R> o;
-                    o.x = (R)acc[u].x;
-                    o.y = (R)acc[u].y;
-                    ycol[m0 + u][r] = o;
+            for (int j = 0; j < kRowsPerThread; ++j) {
+                if (row[j] >= N) continue;
+#pragma unroll
+                for (int u = 0; u < kOutChunk; ++u) {
+                    if (m0 + u < m) {
+                        cx<R> o;
+                        o.x = (R)acc[j][u].x;
+                        o.y = (R)acc[j][u].y;
+                        ycol[m0 + u][row[j]] = o;
+                    }
                 }
             }
         }
@@ -325,7 +406,8 @@ __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __r
 template <typename R>
 hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
     if (S.total() < 1 || Y.total() < 1 || S.total() > kMaxCols || Y.total() > kMaxCols) return hipErrorInvalidValue;
-    long blocks = (N + 255) / 256;
+    const long span = 256L * kRowsPerThread;
+    long blocks = (N + span - 1) / span;
     if (blocks > 8192) blocks = 8192;
     const size_t cbytes = sizeof(cx<double>) * (size_t)S.total() * Y.total();
     if (cbytes <= (size_t)kCombineLds)
@@ -366,7 +448,8 @@ __global__ void __launch_bounds__(256) k_residual(ColSet X, ColSet AX, const dou
         for (long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
             const cx<double> xv = to64(x[r]), av = to64(ax[r]);
             const double rx = av.x - th * xv.x, ry = av.y - th * xv.y;
-            s += rx * rx + ry * ry;
+            s = fma(rx, rx, s);
+            s = fma(ry, ry, s);
             const double p = prec ? prec[r < n ? r : r - n] : 1.0;
             cx<R> o;
             o.x = (R)(p * rx);

@@ -239,14 +239,18 @@ struct Solver {
             if ((rc = residuals<R>(B, &G))) return rc;   // W <- prec (AX - X theta) for all b columns
             bool all = true;
             double worst = 0;                    // over the bands still open
+            int jw = -1;
             for (int j = 0; j < nev; ++j) {
                 const bool cj = converged<R>(j, tol);
                 all = all && cj;
-                if (!cj) worst = std::max(worst, resid[j]);
+                if (!cj && resid[j] >= worst) {
+                    worst = resid[j];
+                    jw = j;
+                }
             }
             if (o.verbose)
-                fprintf(stderr, "pcx lobpcg %s it %d: theta0 %.12g worst residual %.3e\n", sizeof(R) == 8 ? "fp64" : "fp32",
-                        iters, theta[0], worst);
+                fprintf(stderr, "pcx lobpcg %s it %d: theta0 %.12g worst residual %.3e (band %d)\n",
+                        sizeof(R) == 8 ? "fp64" : "fp32", iters, theta[0], worst, jw);
             if (all || iters >= max_iter) return PCX_OK;
             // a reduced-precision phase ends when its residual stops improving (rounding floor)
             // and leaves at least half of the iterations to the refinement

@@ -132,6 +132,21 @@ int pcx_apply_QS_adjoint(pcx_plan *p, const double kappa[3], int precision, cons
 /* x = B^{-1} Q_r Sigma_r y (Theorem 5.2): the GEP eigenvector for an NFSEP one. Device. */
 int pcx_eigvec(pcx_plan *p, const double kappa[3], int precision, const void *y, void *x, int nvec);
 
+/* LOBPCG preconditioners for A_r = Sigma_r Q_r^* B^{-1} Q_r Sigma_r (Section 5.2, eq. NFSEP).
+ *   PCX_PRECOND_NONE:    none.
+ *   PCX_PRECOND_DIAG:    D = Sigma_r^{-2} = Lambda_q^{-1} per mode (zero on a masked mode); the
+ *                        preconditioned operator is similar to Q_r^* B^{-1} Q_r, whose condition
+ *                        number is at most eps_max / eps_min (the bound of Section 5.2).
+ *   PCX_PRECOND_INVERSE: D Sigma_r Q_r^* B Q_r Sigma_r D = Sigma_r^{-1} (Q_r^* B Q_r) Sigma_r^{-1},
+ *                        the same FFT operator with eps in place of 1/eps: an approximate inverse
+ *                        of A_r (exact for constant eps).  The preconditioned operator is similar
+ *                        to (Q_r^* B Q_r)(Q_r^* B^{-1} Q_r), whose eigenvalues lie in
+ *                        [1, (eps_max + eps_min)^2 / (4 eps_max eps_min)] (Kantorovich), e.g.
+ *                        [1, 3.77] for contrast 13 instead of [1, 13]; one extra A_r-type
+ *                        application per block column and iteration.  Not in the paper, whose
+ *                        inner CG solves run without a preconditioner. */
+enum { PCX_PRECOND_NONE = 0, PCX_PRECOND_DIAG = 1, PCX_PRECOND_INVERSE = 2 };
+
 typedef struct pcx_opts {
     int mode;            /* PCX_MODE_FP64 | PCX_MODE_FP32_REFINE | PCX_MODE_FP32 */
     int block;           /* LOBPCG block size >= nev (0: nev + max(2, (nev+4)/5)) */
@@ -139,7 +154,7 @@ typedef struct pcx_opts {
     double tol;          /* converged when ||A_r y - lambda y|| <= tol * lambda (||y|| = 1) */
     double tol_fp32;     /* FP32_REFINE: leave the FP32 phase at this residual */
     unsigned long long seed;  /* start block */
-    int precondition;    /* 1: precondition with Lambda_q^{-1} (the Sigma_r^{-2} scaling) */
+    int precondition;    /* PCX_PRECOND_NONE | PCX_PRECOND_DIAG | PCX_PRECOND_INVERSE (default) */
     int verbose;         /* 1: print one line per iteration to stderr */
     const void *y0;      /* warm start: device, n_y0 vectors of 2n complex128 (e.g. the y of a
                             nearby solve), copied into the first n_y0 columns of the start
@@ -156,6 +171,9 @@ typedef struct pcx_stats {
     double seconds_matvec;             /* of which in A_r applications (stream-synchronised) */
     double residual[PCX_MAX_BLOCK];    /* final relative residual per returned band */
     int converged;                     /* bands with residual <= tol */
+    long long precond_applies;         /* single-vector applications of Sigma_r Q_r^* B Q_r Sigma_r
+                                          (PCX_PRECOND_INVERSE; the A_r kernels with eps for 1/eps) */
+    long long precond_applies_fp32;    /* of which in FP32 */
 } pcx_stats;
 
 /* Smallest nev positive eigenvalues of C*C x = lambda B x at Bloch phases kappa

@@ -11,6 +11,7 @@ PCX_OK, PCX_E_ARG, PCX_E_SIZE, PCX_E_LATTICE, PCX_E_NOCONV, PCX_E_OOM, PCX_E_DEV
 PCX_FP64, PCX_FP32 = 0, 1
 PCX_EPS_YEE3, PCX_EPS_VOXEL = 0, 1
 PCX_MODE_FP64, PCX_MODE_FP32_REFINE, PCX_MODE_FP32 = 0, 1, 2
+PCX_PRECOND_NONE, PCX_PRECOND_DIAG, PCX_PRECOND_INVERSE = 0, 1, 2
 PCX_VARIANT_AUTO, PCX_VARIANT_GENERIC, PCX_VARIANT_THREE_PLANE, PCX_VARIANT_TWO_PLANE = 0, 1, 2, 3
 PCX_MAX_N = 256
 PCX_MAX_BLOCK = 64
@@ -42,6 +43,7 @@ class PcxStats(ctypes.Structure):
         ("matvecs", ctypes.c_longlong), ("matvecs_fp32", ctypes.c_longlong),
         ("seconds", ctypes.c_double), ("seconds_matvec", ctypes.c_double),
         ("residual", ctypes.c_double * PCX_MAX_BLOCK), ("converged", ctypes.c_int),
+        ("precond_applies", ctypes.c_longlong), ("precond_applies_fp32", ctypes.c_longlong),
     ]
 
 

@@ -66,6 +66,8 @@ class SolveStats:
     seconds_matvec: float
     residual: np.ndarray
     converged: int
+    precond_applies: int = 0
+    precond_applies_fp32: int = 0
 
 
 class Plan:
@@ -194,7 +196,7 @@ class Plan:
         self._lib.pcx_opts_default(ctypes.byref(opts))
         opts.mode, opts.block, opts.max_iter = int(mode), int(block), int(max_iter)
         opts.tol, opts.tol_fp32, opts.seed = float(tol), float(tol_fp32), int(seed)
-        opts.precondition, opts.verbose = int(bool(precondition)), int(bool(verbose))
+        opts.precondition, opts.verbose = _precond(precondition), int(bool(verbose))
         if y0 is not None:
             opts.y0 = ctypes.c_void_p(y0.data_ptr())
             opts.n_y0 = self._check_block(y0, 2 * self.n, L.PCX_FP64, "y0")
@@ -208,7 +210,8 @@ class Plan:
                                    ctypes.c_void_p(y.data_ptr()) if y is not None else None,
                                    ctypes.c_void_p(x.data_ptr()) if x is not None else None, ctypes.byref(st))
         stats = SolveStats(st.iterations, st.iterations_fp32, st.matvecs, st.matvecs_fp32, st.seconds,
-                           st.seconds_matvec, np.array(list(st.residual))[:nev], st.converged)
+                           st.seconds_matvec, np.array(list(st.residual))[:nev], st.converged, st.precond_applies,
+                           st.precond_applies_fp32)
         if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
             L.check(code)
         return lam, (y if want_y else None), x, stats
@@ -218,7 +221,7 @@ class Plan:
         self._lib.pcx_opts_default(ctypes.byref(opts))
         opts.mode, opts.block, opts.max_iter = int(mode), int(block), int(max_iter)
         opts.tol, opts.tol_fp32, opts.seed = float(tol), float(tol_fp32), int(seed)
-        opts.precondition, opts.verbose = int(bool(precondition)), int(bool(verbose))
+        opts.precondition, opts.verbose = _precond(precondition), int(bool(verbose))
         return opts
 
     def pcx_grad_eps(self, x, weight, layout: int = L.PCX_EPS_YEE3):
@@ -232,6 +235,16 @@ class Plan:
         L.check(self._lib.pcx_grad_eps(self._ptr, nv, ctypes.c_void_p(x.data_ptr()), w.ctypes.data_as(ctypes.c_void_p),
                                        ctypes.c_void_p(out.data_ptr()), int(layout)))
         return out
+
+
+def _precond(v) -> int:
+    """True / False (the default PCX_PRECOND_INVERSE / PCX_PRECOND_NONE) or a PCX_PRECOND_* code."""
+    if isinstance(v, bool):
+        return L.PCX_PRECOND_INVERSE if v else L.PCX_PRECOND_NONE
+    v = int(v)
+    if v not in (L.PCX_PRECOND_NONE, L.PCX_PRECOND_DIAG, L.PCX_PRECOND_INVERSE):
+        raise ValueError(f"unknown preconditioner {v}")
+    return v
 
 
 def pcx_solve_batch(problems, nev: int, *, mode=L.PCX_MODE_FP32_REFINE, block=0, max_iter=400, tol=1e-9,
@@ -267,7 +280,8 @@ def pcx_solve_batch(problems, nev: int, *, mode=L.PCX_MODE_FP32_REFINE, block=0,
                                ks.ctypes.data_as(ctypes.c_void_p), int(nev), ctypes.byref(opts), int(nworkers),
                                lam.ctypes.data_as(ctypes.c_void_p), yp, st)
     stats = [SolveStats(s.iterations, s.iterations_fp32, s.matvecs, s.matvecs_fp32, s.seconds, s.seconds_matvec,
-                        np.array(list(s.residual))[:nev], s.converged) for s in st]
+                        np.array(list(s.residual))[:nev], s.converged, s.precond_applies,
+                        s.precond_applies_fp32) for s in st]
     if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
         L.check(code)
     return lam, ys, stats

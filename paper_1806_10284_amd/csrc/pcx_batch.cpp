@@ -38,7 +38,7 @@ int clone_plan(const Plan* src, hipStream_t st, Plan** out) {
     p->variant = src->variant;
     p->tuned_nt[0] = src->tuned_nt[0];
     p->tuned_nt[1] = src->tuned_nt[1];
-    const size_t bytes = 3 * (size_t)src->n * (2 * sizeof(double) + 2 * sizeof(float));
+    const size_t bytes = Plan::eps_bytes(src->n);
     if ((rc = p->grow(&p->eps_mem, &p->eps_cap, bytes))) {
         pcx_plan_destroy(q);
         return rc;

@@ -38,20 +38,7 @@ DEV R* col_ptr(const ColSet& S, int c, long N) {
 // the block upper triangle of each half is computed (the caller mirrors the rest).
 // The source column and the interleaved position of every tile column are worked out once per
 // work-group (tables in LDS), so staging a row tile is a table read, a load and a store.
-#ifndef PCX_GRAM_ROWS
-#define PCX_GRAM_ROWS 16
-#endif
-constexpr int kGramRows = PCX_GRAM_ROWS;
-#ifndef PCX_GRAM_WIDE
-#define PCX_GRAM_WIDE 0
-#endif
-#ifndef PCX_GRAM_PREFETCH
-#define PCX_GRAM_PREFETCH 0
-#endif
-#ifndef PCX_GRAM_STAGE
-#define PCX_GRAM_STAGE 8
-#endif
-constexpr int kStage = PCX_GRAM_STAGE;         // prefetch registers per thread
+constexpr int kGramRows = 16;
 constexpr int kTileCols = 2 * kMaxCols + 8;    // A and B columns with block padding
 constexpr int kMaxPB = 2;      // pair-blocks per thread (MPB = 1 or 2 per instantiation)
 
@@ -74,8 +61,7 @@ DEV void pair_block(int pb, int nbA, int nbB, int* ba, int* bb) {
 }
 
 template <typename R, int BLK, bool HERM, int MPB>
-__global__ void __launch_bounds__((MPB == 1 && BLK <= 2) ? 512 : 256) k_gram(ColSet A, ColSet B, long N,
-                                                                             long rows_per_chunk,
+__global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long rows_per_chunk,
                                                cx<double>* __restrict__ part) {
     extern __shared__ __align__(16) char lds[];
     const int ka = A.total(), kb = B.total();
@@ -129,46 +115,17 @@ __global__ void __launch_bounds__((MPB == 1 && BLK <= 2) ? 512 : 256) k_gram(Col
             for (int w = 0; w < BLK; ++w) acc[p][u][w].x = acc[p][u][w].y = 0.0;
     __syncthreads();
 
-    // the next row tile is loaded into registers while the current one is multiplied, when every
-    // thread's share of a tile fits in kStage values
-    const int nst = (ncol * kGramRows + (int)blockDim.x - 1) / (int)blockDim.x;
-    const bool prefetch = PCX_GRAM_PREFETCH && nst <= kStage;
-    cx<R> pre[kStage];
-    auto fetch = [&](long rt) {
-        const int rows = (int)min((long)kGramRows, r1 - rt);
-#pragma unroll
-        for (int j = 0; j < kStage; ++j) {
-            const int e = threadIdx.x + j * blockDim.x;
-            pre[j].x = pre[j].y = (R)0;
-            if (e < ncol * kGramRows) {
-                const int c = e / kGramRows, r = e % kGramRows;
-                const cx<R>* src = tsrc[c];
-                if (src && r < rows) pre[j] = src[rt + r];
-            }
-        }
-    };
-    if (prefetch && r0 < r1) fetch(r0);
     for (long rt = r0; rt < r1; rt += kGramRows) {
-        if (prefetch) {
-#pragma unroll
-            for (int j = 0; j < kStage; ++j) {
-                const int e = threadIdx.x + j * blockDim.x;
-                if (e < ncol * kGramRows) T[(size_t)(e % kGramRows) * ldr + tpos[e / kGramRows]] = to64(pre[j]);
-            }
-            __syncthreads();
-            if (rt + kGramRows < r1) fetch(rt + kGramRows);
-        } else {
-            const int rows = (int)min((long)kGramRows, r1 - rt);
-            for (int e = threadIdx.x; e < ncol * kGramRows; e += blockDim.x) {
-                const int c = e / kGramRows, r = e % kGramRows;
-                const cx<R>* src = tsrc[c];
-                cx<double> val;
-                val.x = val.y = 0.0;
-                if (src && r < rows) val = to64(src[rt + r]);
-                T[(size_t)r * ldr + tpos[c]] = val;
-            }
-            __syncthreads();
+        const int rows = (int)min((long)kGramRows, r1 - rt);
+        for (int e = threadIdx.x; e < ncol * kGramRows; e += blockDim.x) {
+            const int c = e / kGramRows, r = e % kGramRows;
+            const cx<R>* src = tsrc[c];
+            cx<double> val;
+            val.x = val.y = 0.0;
+            if (src && r < rows) val = to64(src[rt + r]);
+            T[(size_t)r * ldr + tpos[c]] = val;
         }
+        __syncthreads();
 #pragma unroll
         for (int p = 0; p < MPB; ++p) {
             if (pba[p] >= 0) {
@@ -263,9 +220,6 @@ static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>
     const int slices = (PB + kMaxPB * 256 - 1) / (kMaxPB * 256);
     if (PB <= 256)
         hipLaunchKernelGGL((k_gram<R, BLK, HERM, 1>), dim3(chunks), dim3(256), lds, st, A, B, N, rpc, part);
-    else if (PCX_GRAM_WIDE && BLK <= 2 && PB <= 512)
-        hipLaunchKernelGGL((k_gram<R, BLK, HERM, 1>), dim3(chunks), dim3((PB + 63) / 64 * 64), lds, st, A, B, N, rpc,
-                           part);
     else
         hipLaunchKernelGGL((k_gram<R, BLK, HERM, 2>), dim3(chunks, slices), dim3(256), lds, st, A, B, N, rpc,
                            part);
@@ -283,19 +237,22 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     const int chunks = (int)((N + rpc - 1) / rpc);
     // register tile: every thread of the group waits for the busiest, so the cost of a tile size
     // is (rounds of 256 pair-blocks) x BLK^2; the cheapest, larger BLK on ties (fewer LDS reads per
-    // product); beyond 2 rounds the pair-blocks go to several work-groups per row chunk, each of
-    // which stages the rows again, so those rounds count double
+    // product).  A second round (two pair-blocks per thread) counts 2.5: half the group idles
+    // through it and the doubled registers lower the occupancy (measured: the 36-column Hermitian
+    // Rayleigh-Ritz product takes 207 us with BLK 3 in one round, 248 us with BLK 2 in two); beyond
+    // 2 rounds the pair-blocks go to several work-groups per row chunk, each of which stages the
+    // rows again, so those rounds count double
     hipError_t e;
     auto pbs = [&](int blk) {
         const int a = (ka + blk - 1) / blk;
         return herm ? (kb / ka) * a * (a + 1) / 2 : a * ((kb + blk - 1) / blk);
     };
     int blk = 4;
-    long best = -1;
+    double best = -1;
     for (int t = 4; t >= 1; --t) {
         const int pb = pbs(t);
         const long rounds = (pb + 255) / 256;
-        const long cost = (rounds <= kMaxPB ? rounds : 2 * rounds) * t * t;
+        const double cost = (rounds == 1 ? 1.0 : rounds <= kMaxPB ? 2.5 : 2.0 * rounds) * t * t;
         if (best < 0 || cost < best) {
             best = cost;
             blk = t;
@@ -531,6 +488,25 @@ hipError_t launch_mask(cx<R>* y, const double* prec, long n, int nvec, hipStream
     return hipGetLastError();
 }
 
+template <typename R>
+__global__ void k_scale_modes(const cx<R>* in, cx<R>* out, const double* __restrict__ prec, long n, long count) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
+        const double d = prec[e % n];
+        const cx<R> v = in[e];
+        cx<R> o;
+        o.x = (R)(d * v.x);
+        o.y = (R)(d * v.y);
+        out[e] = o;
+    }
+}
+
+template <typename R>
+hipError_t launch_scale_modes(const cx<R>* in, cx<R>* out, const double* prec, long n, int nvec, hipStream_t st) {
+    const long count = 2 * n * (long)nvec;
+    hipLaunchKernelGGL((k_scale_modes<R>), dim3(grid_for(count)), dim3(256), 0, st, in, out, prec, n, count);
+    return hipGetLastError();
+}
+
 __global__ void k_grad(const cx<double>* __restrict__ x, const double* __restrict__ w, int nvec, long n,
                        double* __restrict__ grad, int voxel) {
     const long cnt = voxel ? n : 3 * n;
@@ -629,5 +605,7 @@ template hipError_t launch_residual<double>(const ColSet&, const ColSet&, const 
                                             const ColSet&, double*, int, double*, hipStream_t);
 template hipError_t launch_mask<float>(cx<float>*, const double*, long, int, hipStream_t);
 template hipError_t launch_mask<double>(cx<double>*, const double*, long, int, hipStream_t);
+template hipError_t launch_scale_modes<float>(const cx<float>*, cx<float>*, const double*, long, int, hipStream_t);
+template hipError_t launch_scale_modes<double>(const cx<double>*, cx<double>*, const double*, long, int, hipStream_t);
 
 }  // namespace pcx

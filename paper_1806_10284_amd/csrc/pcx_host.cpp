@@ -189,6 +189,8 @@ void Plan::set_eps_pointers() {
     inv_epsn64 = (double*)inv_eps64 + 3 * n;
     inv_eps32 = (double*)inv_epsn64 + 3 * n;
     inv_epsn32 = (float*)inv_eps32 + 3 * n;
+    epsn64 = (float*)inv_epsn32 + 3 * n;
+    epsn32 = (double*)epsn64 + 3 * n;
 }
 
 int Plan::grow(void** buf, size_t* have, size_t need) {
@@ -383,8 +385,8 @@ extern "C" int pcx_plan_set_eps(pcx_plan* pp, const double* eps, int layout) {
     if (!p || !eps) return fail(PCX_E_ARG, "pcx_plan_set_eps: null pointer");
     if (layout != PCX_EPS_YEE3 && layout != PCX_EPS_VOXEL) return fail(PCX_E_ARG, "pcx_plan_set_eps: bad layout");
     const long n = p->n;
-    std::vector<double> inv(3 * n), invn(3 * n);
-    std::vector<float> inv32(3 * n), invn32(3 * n);
+    std::vector<double> inv(3 * n), invn(3 * n), en(3 * n);
+    std::vector<float> inv32(3 * n), invn32(3 * n), en32(3 * n);
     double emin = 1e300, emax = -1e300;
     for (long q = 0; q < 3 * n; ++q) {
         const double e = layout == PCX_EPS_YEE3 ? eps[q] : eps[q % n];
@@ -396,8 +398,10 @@ extern "C" int pcx_plan_set_eps(pcx_plan* pp, const double* eps, int layout) {
         invn[q] = 1.0 / (e * (double)n);
         inv32[q] = (float)inv[q];
         invn32[q] = (float)invn[q];
+        en[q] = e / (double)n;
+        en32[q] = (float)en[q];
     }
-    const size_t bytes = 3 * n * (2 * sizeof(double) + 2 * sizeof(float));
+    const size_t bytes = Plan::eps_bytes(n);
     int rc = p->grow(&p->eps_mem, &p->eps_cap, bytes);
     if (rc) return rc;
     p->set_eps_pointers();
@@ -405,7 +409,9 @@ extern "C" int pcx_plan_set_eps(pcx_plan* pp, const double* eps, int layout) {
     if ((e = hipMemcpy(p->inv_eps64, inv.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->inv_epsn64, invn.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->inv_eps32, inv32.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->inv_epsn32, invn32.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        (e = hipMemcpy(p->inv_epsn32, invn32.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->epsn64, en.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->epsn32, en32.data(), 3 * n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "pcx_plan_set_eps: copy");
     p->eps_min = emin;
     p->eps_max = emax;
@@ -439,7 +445,8 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
     if (nvec < 1 || nvec > max_vectors) return fail(PCX_E_ARG, "apply: nvec %d outside [1, %d]", nvec, max_vectors);
     for (int l = 0; l < 3; ++l)
         if (!std::isfinite(kappa[l])) return fail(PCX_E_ARG, "apply: non-finite kappa");
-    if ((op == OP_AR || op == OP_EIGVEC) && !eps_set) return fail(PCX_E_ARG, "apply: permittivity not set");
+    if ((op == OP_AR || op == OP_EIGVEC || op == OP_AR_EPS) && !eps_set)
+        return fail(PCX_E_ARG, "apply: permittivity not set");
     int rc = check_fits(precision);
     if (rc) return rc;
     rc = ensure_work(nvec);
@@ -452,6 +459,8 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
         switch (op) {
             case OP_AR: e = launch_apply_Ar<double>(g, tables, (const double*)inv_epsn64, (const cx<double>*)in,
                                                     (cx<double>*)out, w, nvec, stream); break;
+            case OP_AR_EPS: e = launch_apply_Ar<double>(g, tables, (const double*)epsn64, (const cx<double>*)in,
+                                                        (cx<double>*)out, w, nvec, stream); break;
             case OP_QS: e = launch_QS<double>(g, tables, nullptr, (const cx<double>*)in, (cx<double>*)out, w, nvec,
                                               stream); break;
             case OP_EIGVEC: e = launch_QS<double>(g, tables, (const double*)inv_eps64, (const cx<double>*)in,
@@ -464,6 +473,8 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
         switch (op) {
             case OP_AR: e = launch_apply_Ar<float>(g, tables, (const float*)inv_epsn32, (const cx<float>*)in,
                                                    (cx<float>*)out, w, nvec, stream); break;
+            case OP_AR_EPS: e = launch_apply_Ar<float>(g, tables, (const float*)epsn32, (const cx<float>*)in,
+                                                       (cx<float>*)out, w, nvec, stream); break;
             case OP_QS: e = launch_QS<float>(g, tables, nullptr, (const cx<float>*)in, (cx<float>*)out, w, nvec,
                                              stream); break;
             case OP_EIGVEC: e = launch_QS<float>(g, tables, (const float*)inv_eps32, (const cx<float>*)in,

@@ -12,7 +12,8 @@ int hip_fail(hipError_t e, const char* what);
 bool make_fft_plan(int n, FftPlan* fp);
 
 struct Plan {
-    enum { OP_AR = 0, OP_QS = 1, OP_QSADJ = 2, OP_EIGVEC = 3 };
+    // OP_AR_EPS: Sigma_r Q_r^* B Q_r Sigma_r, the operator with eps in place of 1/eps
+    enum { OP_AR = 0, OP_QS = 1, OP_QSADJ = 2, OP_EIGVEC = 3, OP_AR_EPS = 4 };
 
     pcx_geom geom;
     FftPlan fx, fy, fz;
@@ -24,13 +25,17 @@ struct Plan {
     void* tables_mem = nullptr;
     DeviceTables tables;
 
-    // 1/eps (FP64), 1/(n eps) (FP64), 1/eps (FP32), 1/(n eps) (FP32): 3n each, one allocation
+    // 1/eps (FP64), 1/(n eps) (FP64), 1/eps (FP32), 1/(n eps) (FP32), eps/n (FP64), eps/n (FP32):
+    // 3n each, one allocation
     void* eps_mem = nullptr;
     size_t eps_cap = 0;
+    static size_t eps_bytes(long n) { return 3 * (size_t)n * (3 * sizeof(double) + 3 * sizeof(float)); }
     void* inv_eps64 = nullptr;
     void* inv_epsn64 = nullptr;
     void* inv_eps32 = nullptr;
     void* inv_epsn32 = nullptr;
+    void* epsn64 = nullptr;          // eps / n: the approximate-inverse preconditioner
+    void* epsn32 = nullptr;
     bool eps_set = false;
     double eps_min = 0, eps_max = 0;
 
@@ -71,7 +76,7 @@ struct Plan {
     bool mcodes_valid = false;
 
     int grow(void** buf, size_t* have, size_t need);
-    // inv_eps64 / inv_epsn64 / inv_eps32 / inv_epsn32 inside eps_mem (3n values each)
+    // inv_eps64 / inv_epsn64 / inv_eps32 / inv_epsn32 / epsn64 / epsn32 inside eps_mem (3n values each)
     void set_eps_pointers();
     // grid description for kappa (computes the mode codes on the plan stream when kappa is new)
     int grid_for(const double kappa[3], Grid* g);

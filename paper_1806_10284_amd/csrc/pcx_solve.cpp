@@ -2,9 +2,12 @@
 //
 // The paper solves A_r y = lambda y by inverse Lanczos with CG inner solves; here the same
 // operator drives a block LOBPCG (Knyazev) with
-//   * the preconditioner Lambda_q^{-1} on both y-blocks (the Sigma_r^{-2} scaling: by the
-//     bound kappa(Q_r* B^{-1} Q_r) <= kappa(B^{-1}) of Section 5.2 the preconditioned operator
-//     has condition number at most eps_max / eps_min),
+//   * a preconditioner: Lambda_q^{-1} on both y-blocks (the Sigma_r^{-2} scaling: by the bound
+//     kappa(Q_r* B^{-1} Q_r) <= kappa(B^{-1}) of Section 5.2 the preconditioned operator has
+//     condition number at most eps_max / eps_min), or by default the approximate inverse
+//     Sigma_r^{-1} Q_r* B Q_r Sigma_r^{-1} (the same FFT operator with eps for 1/eps between two
+//     Lambda_q^{-1} scalings), whose preconditioned spectrum lies in [1, (eps_max + eps_min)^2 /
+//     (4 eps_max eps_min)],
 //   * Gram matrices accumulated in FP64 on the device and the Rayleigh-Ritz step solved in
 //     FP64 on the host (Cholesky of the basis Gram matrix, Householder tridiagonalisation and
 //     implicit QL),
@@ -37,6 +40,13 @@ constexpr int kFp32Stall = PCX_FP32_STALL;
 constexpr int kFp64Stall = 40;
 // FP64 absolute residual floor in units of eps ||A_r||
 constexpr double kFloor = PCX_FLOOR_FACTOR;
+// Rayleigh-Ritz: smallest accepted Cholesky pivot of the unit-scaled basis Gram matrix (relative to
+// its largest), else the step is retried without P.  FP32 columns carry ~6e-8 relative rounding,
+// amplified in the Ritz coefficients by 1 / sqrt(pivot); a 1e-9 bound let a nearly dependent P
+// through and the implicitly updated A S drift until Ritz values went negative (FCC 64^3, the
+// approximate-inverse preconditioner); 1e-6 keeps the amplification below 1e3.
+constexpr double kCholTol32 = 1e-6;
+constexpr double kCholTol64 = 1e-13;
 
 // ---------------------------------------------------------------- the solver
 
@@ -185,6 +195,16 @@ struct Solver {
         e = launch_residual<R>(colset(B.X, b), colset(B.AX, b), dev_theta, o.precondition ? prec : nullptr, n,
                                colset(B.W, b), res_part, gram_chunks, res_out, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual");
+        if (o.precondition == PCX_PRECOND_INVERSE) {
+            // W <- D A_r(eps) D r with D = Lambda_q^{-1} (the residual kernel applied the inner D);
+            // AW is free until the next matvec
+            if (int rc = p->apply(Plan::OP_AR_EPS, kappa, sizeof(R) == 8 ? PCX_FP64 : PCX_FP32, B.W, B.AW, b))
+                return rc;
+            st.precond_applies += b;
+            if (sizeof(R) == 4) st.precond_applies_fp32 += b;
+            e = launch_scale_modes<R>(B.AW, B.W, prec, n, b, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner scaling");
+        }
         e = hipMemcpyAsync(host_res, res_out, sizeof(double) * b, hipMemcpyDeviceToHost, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual copy");
         int rc = wg ? gram_async<R>(colset(B.X, b, B.W, b), colset(B.W, b), false) : PCX_OK;
@@ -231,7 +251,7 @@ struct Solver {
         if ((rc = matvec<R>(B.X, B.AX, b))) return rc;
         if ((rc = rr_block<R>(B))) return rc;
         int np = 0;                       // columns of P (the previous active set)
-        const double chol_tol = sizeof(R) == 8 ? 1e-13 : 1e-9;
+        const double chol_tol = sizeof(R) == 8 ? kCholTol64 : kCholTol32;
         double best = 1e300;
         int stall = 0;
         std::vector<zc> G;                       // [X | W]^H W, (2b) x b
@@ -248,9 +268,12 @@ struct Solver {
                     jw = j;
                 }
             }
-            if (o.verbose)
-                fprintf(stderr, "pcx lobpcg %s it %d: theta0 %.12g worst residual %.3e (band %d)\n",
-                        sizeof(R) == 8 ? "fp64" : "fp32", iters, theta[0], worst, jw);
+            if (o.verbose) {
+                int open = 0;
+                for (int j = 0; j < b; ++j) open += !converged<R>(j, tol);
+                fprintf(stderr, "pcx lobpcg %s it %d: theta0 %.12g worst residual %.3e (band %d), %d of %d columns open\n",
+                        sizeof(R) == 8 ? "fp64" : "fp32", iters, theta[0], worst, jw, open, b);
+            }
             if (all || iters >= max_iter) return PCX_OK;
             // a reduced-precision phase ends when its residual stops improving (rounding floor)
             // and leaves at least half of the iterations to the refinement
@@ -314,7 +337,9 @@ struct Solver {
                         GB[(size_t)r * k + c] = G[(size_t)r * 2 * k + c];
                         GA[(size_t)r * k + c] = G[(size_t)r * 2 * k + k + c];
                     }
-                if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C)) break;
+                // A_r is positive semi-definite: a negative Ritz value means the pencil is no longer
+                // consistent (nearly dependent basis), handled like a failed factorisation
+                if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C) && th[0] > -1e-8 * std::fabs(th[b - 1])) break;
                 if (!withP) return fail(PCX_E_NOCONV, "pcx_solve: Rayleigh-Ritz basis became singular");
                 withP = false;
             }
@@ -363,7 +388,7 @@ extern "C" void pcx_opts_default(pcx_opts* o) {
     o->tol = 1e-9;
     o->tol_fp32 = 1e-3;
     o->seed = 12345;
-    o->precondition = 1;
+    o->precondition = PCX_PRECOND_INVERSE;
     o->verbose = 0;
     o->y0 = nullptr;
     o->n_y0 = 0;
@@ -418,6 +443,8 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (b < nev) return fail(PCX_E_ARG, "pcx_solve: block (%d) smaller than nev (%d)", b, nev);
     if (b > PCX_MAX_BLOCK || 3L * b > N - 2) return fail(PCX_E_ARG, "pcx_solve: block %d too large for this grid", b);
     if (S.o.mode < PCX_MODE_FP64 || S.o.mode > PCX_MODE_FP32) return fail(PCX_E_ARG, "pcx_solve: bad mode");
+    if (S.o.precondition < PCX_PRECOND_NONE || S.o.precondition > PCX_PRECOND_INVERSE)
+        return fail(PCX_E_ARG, "pcx_solve: bad preconditioner %d", S.o.precondition);
     if (!(S.o.tol > 0) || S.o.max_iter < 1) return fail(PCX_E_ARG, "pcx_solve: bad tolerance or max_iter");
     if (b > p->max_vectors) return fail(PCX_E_ARG, "pcx_solve: block %d exceeds the plan's max_vectors", b);
     if (S.o.n_y0 < 0 || S.o.n_y0 > b || (S.o.n_y0 > 0 && !S.o.y0))

@@ -147,6 +147,12 @@ int pcx_eigvec(pcx_plan *p, const double kappa[3], int precision, const void *y,
  *                        inner CG solves run without a preconditioner. */
 enum { PCX_PRECOND_NONE = 0, PCX_PRECOND_DIAG = 1, PCX_PRECOND_INVERSE = 2 };
 
+/* z = T y with T the PCX_PRECOND_INVERSE preconditioner D Sigma_r Q_r^* B Q_r Sigma_r D,
+ * D = Lambda_q^{-1} per mode (0 on a masked mode): the three A_r kernels with eps in place of
+ * 1/eps between two mode scalings.  y, z: device, nvec vectors of 2n complex (complex128 for
+ * PCX_FP64, complex64 for PCX_FP32); z may equal y.  Same errors as pcx_apply_Ar. */
+int pcx_apply_precond(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z, int nvec);
+
 typedef struct pcx_opts {
     int mode;            /* PCX_MODE_FP64 | PCX_MODE_FP32_REFINE | PCX_MODE_FP32 */
     int block;           /* LOBPCG block size >= nev (0: nev + max(2, (nev+4)/5)) */

@@ -64,6 +64,8 @@ _SIGS = [
     ("pcx_plan_set_variant", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("pcx_apply_Ar", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int]),
+    ("pcx_apply_precond", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int]),
     ("pcx_apply_Ar_multi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     ("pcx_solve_batch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,

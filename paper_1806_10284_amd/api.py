@@ -135,6 +135,12 @@ class Plan:
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_apply_Ar, kappa, precision, y, z, 2 * self.n, 2 * self.n)
 
+    def pcx_apply_precond(self, kappa, y, z, precision=None):
+        """z = D Sigma_r Q_r^* B Q_r Sigma_r D y, D = Lambda_q^{-1}: the approximate-inverse
+        preconditioner of the solver (z may be y)."""
+        precision = self._prec_of(y) if precision is None else precision
+        return self._apply(self._lib.pcx_apply_precond, kappa, precision, y, z, 2 * self.n, 2 * self.n)
+
     def pcx_apply_Ar_multi(self, kappas, y, z, precision=None):
         """z = A_r(kappa_k) y for every wave vector in one launch per kernel; y, z hold
         len(kappas) equal groups of vectors, ordered [k][v]."""

@@ -503,6 +503,38 @@ extern "C" int pcx_apply_Ar(pcx_plan* p, const double kappa[3], int precision, c
     if (!p) return fail(PCX_E_ARG, "pcx_apply_Ar: null plan");
     return ((Plan*)p)->apply(Plan::OP_AR, kappa, precision, y, z, nvec);
 }
+extern "C" int pcx_apply_precond(pcx_plan* pp, const double kappa[3], int precision, const void* y, void* z,
+                                 int nvec) {
+    Plan* p = (Plan*)pp;
+    if (!p || !kappa || !y || !z) return fail(PCX_E_ARG, "pcx_apply_precond: null pointer");
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "pcx_apply_precond: bad precision");
+    if (nvec < 1 || nvec > p->max_vectors)
+        return fail(PCX_E_ARG, "pcx_apply_precond: nvec %d outside [1, %d]", nvec, p->max_vectors);
+    if (!p->eps_set) return fail(PCX_E_ARG, "pcx_apply_precond: permittivity not set");
+    for (int l = 0; l < 3; ++l)
+        if (!std::isfinite(kappa[l])) return fail(PCX_E_ARG, "pcx_apply_precond: non-finite kappa");
+    int rc = p->check_fits(precision);
+    if (rc) return rc;
+    if ((rc = p->grow(&p->prec, &p->prec_cap, p->n * sizeof(double)))) return rc;
+    Grid g;
+    if ((rc = p->grid_for(kappa, &g))) return rc;
+    hipError_t e = launch_precond_diag(g, p->tables, (double*)p->prec, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_apply_precond: Lambda_q^{-1}");
+    const double* d = (const double*)p->prec;
+    if (precision == PCX_FP64)
+        e = launch_scale_modes<double>((const cx<double>*)y, (cx<double>*)z, d, p->n, nvec, p->stream);
+    else
+        e = launch_scale_modes<float>((const cx<float>*)y, (cx<float>*)z, d, p->n, nvec, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_apply_precond: scaling");
+    if ((rc = p->apply(Plan::OP_AR_EPS, kappa, precision, z, z, nvec))) return rc;
+    if (precision == PCX_FP64)
+        e = launch_scale_modes<double>((const cx<double>*)z, (cx<double>*)z, d, p->n, nvec, p->stream);
+    else
+        e = launch_scale_modes<float>((const cx<float>*)z, (cx<float>*)z, d, p->n, nvec, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_apply_precond: scaling");
+    return PCX_OK;
+}
+
 extern "C" int pcx_apply_Ar_multi(pcx_plan* pp, int nk, const double* kappas, int precision, const void* y,
                                   void* z, int nvec_per_k) {
     Plan* p = (Plan*)pp;

@@ -94,3 +94,11 @@ def test_geometry_errors():
     with pytest.raises(_lib.PcxError) as e:
         api.pcx_geometry(np.array([[1, 2.5, 0], [0, 1, 0], [0, 0, 1.0]]), 4, 4, 4)
     assert e.value.code == _lib.PCX_E_LATTICE
+
+
+def test_preconditioner_codes():
+    from paper_1806_10284_amd import PCX_PRECOND_DIAG, PCX_PRECOND_INVERSE, PCX_PRECOND_NONE, api
+    assert api._precond(True) == PCX_PRECOND_INVERSE and api._precond(False) == PCX_PRECOND_NONE
+    assert api._precond(PCX_PRECOND_DIAG) == 1
+    with pytest.raises(ValueError):
+        api._precond(3)

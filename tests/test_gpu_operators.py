@@ -100,6 +100,31 @@ def test_apply_Ar_parity(name, avec, n, kappa, prec, variant):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,avec,n,kappa", [CASES[1], CASES[4], CASES[7], CASES[9], CASES[11], CASES[13]])
+def test_apply_precond_parity(name, avec, n, kappa, prec):
+    """pcx_apply_precond = D A_r(eps -> 1/eps) D with D = Lambda_q^{-1} (0 on the Gamma mask), in
+    place and out of place."""
+    import torch
+    from oracle.nfsep import preconditioner_diag
+    rng = np.random.default_rng(sum(map(ord, name)) + 1)
+    npts = n[0] * n[1] * n[2]
+    eps = rng.uniform(1.0, 13.0, (3, npts))
+    plan, og, spec, y = _setup(avec, n, kappa, eps, nvec=2, seed=11)
+    say("apply_precond", name, n, prec)
+    d = preconditioner_diag(spec)
+    yd = _to_dev(y, prec)
+    z = torch.empty_like(yd)
+    plan.pcx_apply_precond(kappa, yd, z)
+    plan.pcx_apply_precond(kappa, yd, yd)
+    torch.cuda.synchronize()
+    got, got2 = z.cpu().numpy().T, yd.cpu().numpy().T
+    for v in range(2):
+        ref = d * Ar_apply(spec, 1.0 / eps, d * y[:, v])
+        _cmp(got[:, v], ref, prec, f"{name} vec {v}")
+        _cmp(got2[:, v], ref, prec, f"{name} vec {v} in place")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name,avec,n,kappa", [CASES[1], CASES[3], CASES[7], CASES[8]])
 def test_QS_and_adjoint_and_eigvec(name, avec, n, kappa, prec):
     import torch

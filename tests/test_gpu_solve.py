@@ -55,6 +55,23 @@ def test_config1_eigenvalues(mode, tol):
     assert rel.max() <= tol, rel
 
 
+@pytest.mark.parametrize("pre", [0, 1, 2])
+def test_config1_preconditioners_agree(pre):
+    """No preconditioner, Lambda_q^{-1} and the approximate inverse give the same eigenvalues; the
+    approximate inverse takes fewer iterations than the diagonal one."""
+    plan, kappa, eps, ref = _config1()
+    say("solve config1 preconditioner", pre)
+    lam, _, _, st = plan.pcx_solve(kappa, 10, mode=0, tol=1e-9, precondition=pre, want_y=False)
+    rel = np.abs(lam - ref) / ref
+    say("config1 preconditioner", pre, "iters", st.iterations, "applications", st.precond_applies,
+        "max rel err", rel.max())
+    assert rel.max() <= 1e-10, rel
+    assert (st.precond_applies > 0) == (pre == 2)
+    if pre == 2:
+        _, _, _, st1 = plan.pcx_solve(kappa, 10, mode=0, tol=1e-9, precondition=1, want_y=False)
+        assert st.iterations < st1.iterations
+
+
 def test_config1_eigenvectors_solve_the_gep():
     """x = B^{-1} Q_r Sigma_r y returned by pcx_solve satisfies C*C x = lambda B x with the explicit C."""
     plan, kappa, eps, ref = _config1()

@@ -288,6 +288,31 @@ def test_conditioning_bound():
     assert ev.min() >= 1 / eps.max() - 1e-12 and ev.max() <= 1 / eps.min() + 1e-12
 
 
+def test_approximate_inverse_preconditioner_spectrum():
+    """T = D Sigma_r Q_r^* B Q_r Sigma_r D (D = Lambda_q^{-1}; A_r with eps in place of 1/eps):
+    T A_r is similar to (Q_r^* B Q_r)(Q_r^* B^{-1} Q_r), whose eigenvalues lie in
+    [1, (M + m)^2 / (4 M m)] for eps in [m, M] (the matrix Kantorovich inequality: for an isometry
+    Q, (Q^* B Q)^{-1} <= Q^* B^{-1} Q <= (M + m)^2 / (4 M m) (Q^* B Q)^{-1}); constant eps: T = A_r^{-1}."""
+    rng = np.random.default_rng(21)
+    A, g = random_geometry(rng, 3, 5)
+    kap = rng.uniform(-0.5, 0.5, 3)
+    spec = spectrum(g, kap)
+    d = preconditioner_diag(spec)
+    for eps in (rng.uniform(1.0, 13.0, (3, g.npts)), np.full((3, g.npts), 4.0)):
+        Ar = Ar_dense(spec, eps)
+        T = d[:, None] * Ar_dense(spec, 1.0 / eps) * d[None, :]
+        ev = np.linalg.eigvals(T @ Ar)
+        assert np.abs(ev.imag).max() < 1e-9 * np.abs(ev).max()
+        ev = np.sort(ev.real)
+        m, M = eps.min(), eps.max()
+        kant = (M + m) ** 2 / (4 * M * m)
+        assert ev.min() >= 1 - 1e-10 and ev.max() <= kant + 1e-10, (ev.min(), ev.max(), kant)
+        if m == M:
+            np.testing.assert_allclose(ev, 1.0, atol=1e-10)
+    # the bound is attained up to the grid's freedom: for contrast 13 it is far below 13
+    assert (14.0 ** 2) / (4 * 13.0) < 3.8
+
+
 @pytest.mark.parametrize("lat,n", [("fcc", (8, 8, 8)), ("bcc", (6, 8, 5)), ("hex", (8, 8, 10))])
 def test_nfsep_identity_with_explicit_curl(lat, n):
     """Q_r Sigma_r (A_r y) = C*C B^{-1} Q_r Sigma_r y with the explicit sparse C (Theorem 5.2's proof)."""

@@ -207,10 +207,20 @@ struct Solver {
         }
         e = hipMemcpyAsync(host_res, res_out, sizeof(double) * b, hipMemcpyDeviceToHost, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual copy");
-        int rc = wg ? gram_async<R>(colset(B.X, b, B.W, b), colset(B.W, b), false) : PCX_OK;
+        // [X | W]^H W as the right half of the Hermitian [X | W]^H [X | W]: the 2b columns are staged
+        // once (the plain product would stage W twice)
+        const ColSet XW = colset(B.X, b, B.W, b);
+        int rc = wg ? gram_async<R>(XW, XW, true) : PCX_OK;
         if (!rc) rc = sync();
         if (rc) return rc;
-        if (wg) gram_read(2 * b, b, *wg, false);
+        if (wg) {
+            std::vector<zc> full;
+            gram_read(2 * b, 2 * b, full, true);
+            wg->resize((size_t)2 * b * b);
+            for (int r = 0; r < 2 * b; ++r)
+                std::copy(full.begin() + (size_t)r * 2 * b + b, full.begin() + (size_t)(r + 1) * 2 * b,
+                          wg->begin() + (size_t)r * b);
+        }
         resid.resize(b);
         rabs.resize(b);
         for (int j = 0; j < b; ++j) {

@@ -84,6 +84,10 @@ struct Solver {
     std::vector<double> resid;           // host, relative residuals of the current block
     std::vector<double> rabs;            // host, absolute residual norms ||A_r x - theta x||
     double anorm = 0;                    // ||A_r|| <= max Lambda_q / min eps
+    // columns [pre_lo, pre_hi) get the approximate-inverse preconditioner: the span of the
+    // columns open at the previous convergence check (the others have converged; should one
+    // reopen, its W is still the Lambda_q^{-1}-preconditioned residual)
+    int pre_lo = 0, pre_hi = 0;
 
     // Band j has converged when its relative residual is below tol or, for eigenvalues so close
     // to zero (next to Gamma) that tol |theta| is below what the arithmetic can resolve, when its
@@ -195,14 +199,17 @@ struct Solver {
         e = launch_residual<R>(colset(B.X, b), colset(B.AX, b), dev_theta, o.precondition ? prec : nullptr, n,
                                colset(B.W, b), res_part, gram_chunks, res_out, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual");
-        if (o.precondition == PCX_PRECOND_INVERSE) {
+        const int npre = pre_hi - pre_lo;
+        if (o.precondition == PCX_PRECOND_INVERSE && npre > 0) {
             // W <- D A_r(eps) D r with D = Lambda_q^{-1} (the residual kernel applied the inner D);
             // AW is free until the next matvec
-            if (int rc = p->apply(Plan::OP_AR_EPS, kappa, sizeof(R) == 8 ? PCX_FP64 : PCX_FP32, B.W, B.AW, b))
+            cx<R>* w0 = B.W + (size_t)pre_lo * N;
+            cx<R>* t0 = B.AW + (size_t)pre_lo * N;
+            if (int rc = p->apply(Plan::OP_AR_EPS, kappa, sizeof(R) == 8 ? PCX_FP64 : PCX_FP32, w0, t0, npre))
                 return rc;
-            st.precond_applies += b;
-            if (sizeof(R) == 4) st.precond_applies_fp32 += b;
-            e = launch_scale_modes<R>(B.AW, B.W, prec, n, b, p->stream);
+            st.precond_applies += npre;
+            if (sizeof(R) == 4) st.precond_applies_fp32 += npre;
+            e = launch_scale_modes<R>(t0, w0, prec, n, npre, p->stream);
             if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner scaling");
         }
         e = hipMemcpyAsync(host_res, res_out, sizeof(double) * b, hipMemcpyDeviceToHost, p->stream);
@@ -260,6 +267,8 @@ struct Solver {
             if ((rc = orthonormalize<R>(B.X, B.T1, b))) return rc;
         if ((rc = matvec<R>(B.X, B.AX, b))) return rc;
         if ((rc = rr_block<R>(B))) return rc;
+        pre_lo = 0;
+        pre_hi = b;
         int np = 0;                       // columns of P (the previous active set)
         const double chol_tol = sizeof(R) == 8 ? kCholTol64 : kCholTol32;
         double best = 1e300;
@@ -306,6 +315,8 @@ struct Solver {
             for (int j = 0; j < b; ++j)
                 if (!converged<R>(j, tol)) act.push_back(j);
             const int na = (int)act.size();
+            pre_lo = na ? act.front() : 0;
+            pre_hi = na ? act.back() + 1 : 0;
             // W_act <- (W_act - X G) R^{-1} with one Gram product and one combination:
             // [X | W]^H W (taken with the residuals) gives G = X^H W_act and W_act^H W_act, and the
             // projected Gram matrix W_act^H W_act - G^H G (X has orthonormal columns) gives R

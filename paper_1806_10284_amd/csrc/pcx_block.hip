@@ -488,14 +488,14 @@ hipError_t launch_mask(cx<R>* y, const double* prec, long n, int nvec, hipStream
     return hipGetLastError();
 }
 
-template <typename R>
-__global__ void k_scale_modes(const cx<R>* in, cx<R>* out, const double* __restrict__ prec, long n, long count) {
+template <typename RI, typename RO>
+__global__ void k_scale_modes(const cx<RI>* in, cx<RO>* out, const double* __restrict__ prec, long n, long count) {
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
         const double d = prec[e % n];
-        const cx<R> v = in[e];
-        cx<R> o;
-        o.x = (R)(d * v.x);
-        o.y = (R)(d * v.y);
+        const cx<RI> v = in[e];
+        cx<RO> o;
+        o.x = (RO)(d * (double)v.x);
+        o.y = (RO)(d * (double)v.y);
         out[e] = o;
     }
 }
@@ -503,7 +503,15 @@ __global__ void k_scale_modes(const cx<R>* in, cx<R>* out, const double* __restr
 template <typename R>
 hipError_t launch_scale_modes(const cx<R>* in, cx<R>* out, const double* prec, long n, int nvec, hipStream_t st) {
     const long count = 2 * n * (long)nvec;
-    hipLaunchKernelGGL((k_scale_modes<R>), dim3(grid_for(count)), dim3(256), 0, st, in, out, prec, n, count);
+    hipLaunchKernelGGL((k_scale_modes<R, R>), dim3(grid_for(count)), dim3(256), 0, st, in, out, prec, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_modes(const cx<float>* in, cx<double>* out, const double* prec, long n, int nvec,
+                              hipStream_t st) {
+    const long count = 2 * n * (long)nvec;
+    hipLaunchKernelGGL((k_scale_modes<float, double>), dim3(grid_for(count)), dim3(256), 0, st, in, out, prec, n,
+                       count);
     return hipGetLastError();
 }
 

@@ -162,6 +162,9 @@ hipError_t launch_mask(cx<R>* y, const double* prec, long n, int nvec, hipStream
 // out = prec * in per mode on both y-blocks of nvec vectors (out may equal in)
 template <typename R>
 hipError_t launch_scale_modes(const cx<R>* in, cx<R>* out, const double* prec, long n, int nvec, hipStream_t st);
+// the same from FP32 into FP64
+hipError_t launch_scale_modes(const cx<float>* in, cx<double>* out, const double* prec, long n, int nvec,
+                              hipStream_t st);
 // grad[p] = -sum_t w_t |x_t(p)|^2 ; voxel: summed over the 3 components.  w: device, nvec doubles.
 hipError_t launch_grad(const cx<double>* x, const double* w, int nvec, long n, double* grad, int voxel,
                        hipStream_t st);

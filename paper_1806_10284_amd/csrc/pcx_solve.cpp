@@ -88,6 +88,10 @@ struct Solver {
     // columns open at the previous convergence check (the others have converged; should one
     // reopen, its W is still the Lambda_q^{-1}-preconditioned residual)
     int pre_lo = 0, pre_hi = 0;
+    // one plane wave with Lambda_q far below the others (next to Gamma): its bands go to zero and
+    // the FP64 phase applies the preconditioner in FP64 (FP32 rounding of the preconditioned
+    // residual, dominated by that mode, stalls and then upsets those bands near 1e-9)
+    bool near_gamma = false;
 
     // Band j has converged when its relative residual is below tol or, for eigenvalues so close
     // to zero (next to Gamma) that tol |theta| is below what the arithmetic can resolve, when its
@@ -189,6 +193,40 @@ struct Solver {
         return PCX_OK;
     }
 
+    // W[pre_lo, pre_lo + npre) <- D A_r(eps) D r with D = Lambda_q^{-1} (the residual kernel has
+    // applied the inner D), in FP32 also in the FP64 phase away from Gamma: the preconditioner only
+    // shapes the search direction (the Rayleigh-Ritz step and the residuals stay in the phase's
+    // precision), and the FP32 kernels take about half the time of the FP64 ones.  AW is free
+    // until the next matvec and holds the intermediate vectors.
+    template <typename R>
+    int precondition_inverse(Blocks<R>& B, int npre) {
+        hipError_t e;
+        cx<R>* w0 = B.W + (size_t)pre_lo * N;
+        if (sizeof(R) == 8 && near_gamma) {
+            cx<R>* t0 = B.AW + (size_t)pre_lo * N;
+            if (int rc = p->apply(Plan::OP_AR_EPS, kappa, PCX_FP64, w0, t0, npre)) return rc;
+            st.precond_applies += npre;
+            e = launch_scale_modes<R>(t0, w0, prec, n, npre, p->stream);
+            return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_solve: preconditioner scaling");
+        }
+        // FP64 phase: AW (b columns of complex128) holds the FP32 input and output side by side;
+        // FP32 phase: W itself is the input and AW the output
+        cx<float>* tin = sizeof(R) == 8 ? (cx<float>*)(void*)B.AW : (cx<float>*)(void*)w0;
+        cx<float>* tout = sizeof(R) == 8 ? tin + (size_t)npre * N : (cx<float>*)(void*)B.AW;
+        if (sizeof(R) == 8) {
+            e = launch_convert((const cx<double>*)(const void*)w0, tin, (long)npre * N, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner input");
+        }
+        if (int rc = p->apply(Plan::OP_AR_EPS, kappa, PCX_FP32, tin, tout, npre)) return rc;
+        st.precond_applies += npre;
+        st.precond_applies_fp32 += npre;
+        if (sizeof(R) == 8)
+            e = launch_scale_modes(tout, (cx<double>*)(void*)w0, prec, n, npre, p->stream);
+        else
+            e = launch_scale_modes<float>(tout, (cx<float>*)(void*)w0, prec, n, npre, p->stream);
+        return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_solve: preconditioner scaling");
+    }
+
     // residual norms of the b Ritz pairs, W <- prec (AX - X theta); with wg, also the Gram matrix
     // [X | W]^H W (2b x b) of the new W, under the same stream synchronisation
     template <typename R>
@@ -201,16 +239,7 @@ struct Solver {
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual");
         const int npre = pre_hi - pre_lo;
         if (o.precondition == PCX_PRECOND_INVERSE && npre > 0) {
-            // W <- D A_r(eps) D r with D = Lambda_q^{-1} (the residual kernel applied the inner D);
-            // AW is free until the next matvec
-            cx<R>* w0 = B.W + (size_t)pre_lo * N;
-            cx<R>* t0 = B.AW + (size_t)pre_lo * N;
-            if (int rc = p->apply(Plan::OP_AR_EPS, kappa, sizeof(R) == 8 ? PCX_FP64 : PCX_FP32, w0, t0, npre))
-                return rc;
-            st.precond_applies += npre;
-            if (sizeof(R) == 4) st.precond_applies_fp32 += npre;
-            e = launch_scale_modes<R>(t0, w0, prec, n, npre, p->stream);
-            if (e != hipSuccess) return hip_fail(e, "pcx_solve: preconditioner scaling");
+            if (int rc = precondition_inverse<R>(B, npre)) return rc;
         }
         e = hipMemcpyAsync(host_res, res_out, sizeof(double) * b, hipMemcpyDeviceToHost, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual copy");
@@ -457,8 +486,10 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     int guard = std::max(2, (nev + 4) / 5);
     {
         const long ref = std::min<long>(nsort - 1, std::max<long>(1, (nev + 1) / 2));
-        if (hp[modes[0]] > 0 && hp[modes[ref]] > 0 && hp[modes[0]] > 10.0 * hp[modes[ref]])
+        if (hp[modes[0]] > 0 && hp[modes[ref]] > 0 && hp[modes[0]] > 10.0 * hp[modes[ref]]) {
             guard = std::max(4, (nev + 1) / 2);
+            S.near_gamma = true;
+        }
     }
     int b = S.o.block > 0 ? S.o.block : nev + guard;
     if (b < nev) return fail(PCX_E_ARG, "pcx_solve: block (%d) smaller than nev (%d)", b, nev);

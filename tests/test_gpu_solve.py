@@ -118,6 +118,31 @@ def test_small_grids_vs_dense(case):
     np.testing.assert_allclose(lam, ref, rtol=1e-10)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_next_to_gamma_vs_dense(mode):
+    """A wave vector next to Gamma (one plane wave with Lambda_q far below the others, its two bands
+    near zero): the solver's near-Gamma rules (larger block, FP64 preconditioner in the FP64 phase,
+    the absolute floor for bands that cannot reach tol) against the dense oracle: 1e-10 relative
+    plus the Rayleigh-quotient rounding bound for the near-zero bands."""
+    from paper_1806_10284_amd import Plan, pcx_geometry
+    from oracle.spectral import spectrum
+    avec, n, kappa = S.FCC, (8, 8, 8), (0.01, -0.004, 0.007)
+    og = lattice_geometry(avec, *n)
+    rng = np.random.default_rng(31)
+    eps = rng.uniform(1.0, 13.0, (3, og.npts))
+    nev = 6
+    ref, _ = dense_gep(og, kappa, eps, nev)
+    assert ref[0] < 1e-3 * ref[2]                        # the two bands that go to zero
+    plan = Plan(pcx_geometry(avec, *n), max_vectors=16)
+    plan.pcx_plan_set_eps(eps)
+    say("solve next to Gamma, mode", mode)
+    lam, _, _, st = plan.pcx_solve(kappa, nev, mode=mode, tol=1e-10, want_y=False)
+    lq_max = np.sum(np.abs(spectrum(og, kappa).lam) ** 2, axis=0).max()
+    atol = 1e-13 * lq_max / eps.min()
+    say("next to Gamma: iterations", st.iterations, "lambda", lam, "ref", ref)
+    assert np.all(np.abs(lam - ref) <= 1e-10 * ref + atol), (lam - ref) / ref
+
+
 def test_gradient_matches_oracle_formula():
     """pcx_grad_eps on the solver's x equals -lambda |x|^2 / x*Bx evaluated by the oracle on the dense
     eigenvector of a simple eigenvalue."""

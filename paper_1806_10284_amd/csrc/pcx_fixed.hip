@@ -201,9 +201,27 @@ DEV cx<R> p3_ztw(const LT& L, const cx<R>* __restrict__ rot, int c, int j, int s
     return cmul(L.twc[c], rot[(c * j * s3m) % M]);
 }
 
+// W of mode e of plane i: from the grid's table (layout [2l + c][n], zero on the masked mode) when
+// there is one, else formed here (zero on the masked mode).
+template <typename R, int N2, int N3, bool WT, typename LT>
+DEV void mode_w(const cx<R>* __restrict__ wt, long n, long m, const LT& L, cx<double> L0, int j, int k, int code,
+                double idz, cx<R> w[3][2]) {
+    if constexpr (WT) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) w[q >> 1][q & 1] = wt[(long)q * n + m];
+        return;
+    }
+    if (code == kMasked) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) w[q >> 1][q & 1] = mk<R>((R)0, (R)0);
+        return;
+    }
+    p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
+}
+
 // ------------------------------------------------------------------ plane kernels
 // y: [v][2][n1][N2][N3]  ->  t: [v][3][n1][N3][N2];   grid (n1, nvec)
-template <typename R, int N2, int N3, int NT>
+template <typename R, int N2, int N3, int NT, bool WT>
 __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
                                                 cx<R>* __restrict__ t) {
     const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
@@ -216,6 +234,7 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
     const long n = (long)g.n1 * NP;
     const cx<R>* yb = y + (long)v * 2 * n + (long)i * NP;
     const unsigned char* codes = ks.codes + (long)i * NP;
+    const cx<R>* wt = WT ? (const cx<R>*)g.wtab[sizeof(R) == 8] : nullptr;
     cx<R> y1[EPT], y2[EPT];
     int code[EPT];
 #pragma unroll
@@ -224,7 +243,7 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
         if (NP % NT == 0 || e < NP) {
             y1[s] = yb[e];
             y2[s] = yb[n + e];
-            code[s] = codes[e];
+            code[s] = WT ? 0 : codes[e];
         }
     }
     const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
@@ -242,7 +261,12 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
             const int j = e / N3, k = e % N3;
             tw[s] = p3_ztw<R, N2, N3>(L, rot, k, j, s3m);
             cx<R> u[3];
-            if (code[s] == kMasked) {
+            if constexpr (WT) {
+                cx<R> w[3][2];
+                mode_w<R, N2, N3, true>(wt, n, (long)i * NP + e, L, L0, j, k, 0, idz, w);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) u[l] = cmul(w[l][0], y1[s]) + cmul(w[l][1], y2[s]);
+            } else if (code[s] == kMasked) {
                 u[0] = u[1] = u[2] = mk<R>((R)0, (R)0);
             } else {
                 cx<R> w[3][2];
@@ -285,7 +309,7 @@ __global__ void __launch_bounds__(NT) k_p3_fwd(Grid g, DeviceTables tb, const cx
 }
 
 // t: [v][3][n1][N3][N2]  ->  z: [v][2][n1][N2][N3]
-template <typename R, int N2, int N3, int NT>
+template <typename R, int N2, int N3, int NT, bool WT>
 __global__ void __launch_bounds__(NT) k_p3_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
                                                 cx<R>* __restrict__ z) {
     const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
@@ -337,17 +361,19 @@ __global__ void __launch_bounds__(NT) k_p3_adj(Grid g, DeviceTables tb, const cx
     __syncthreads();
     ffft<R, N3, 3 * N2, 3 * N2, 0, LD, 1, NT, -1>(L.pl, L.twz);   // c -> k along rows j
     const unsigned char* codes = ks.codes + (long)i * NP;
+    const cx<R>* wt = WT ? (const cx<R>*)g.wtab[sizeof(R) == 8] : nullptr;
     cx<R>* zb = z + (long)v * 2 * n + (long)i * NP;
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
         const int e = threadIdx.x + s * NT;
         if (NP % NT == 0 || e < NP) {
             const int j = e / N3, k = e % N3;
-            const int code = codes[e];
+            const int code = WT ? 0 : (int)codes[e];
             cx<R> a1 = mk<R>((R)0, (R)0), a2 = a1;
-            if (code != kMasked) {
+            if (WT || code != kMasked) {
                 cx<R> w[3][2];
-                p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
+                if constexpr (WT) mode_w<R, N2, N3, true>(wt, n, (long)i * NP + e, L, L0, j, k, 0, idz, w);
+                else p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
 #pragma unroll
                 for (int l = 0; l < 3; ++l) {
                     const cx<R> u = L.pl[l * PS + j * LD + k];
@@ -402,6 +428,28 @@ struct P2 {
     }
 };
 
+// the table itself: one work-group per plane i, W of its N2 N3 modes in precision R
+template <typename R, int N2, int N3, int NT>
+__global__ void __launch_bounds__(NT) k_wtable(Grid g, DeviceTables tb, cx<R>* __restrict__ out) {
+    using LT = P2<R, N2, N3>;
+    constexpr int NP = LT::NP;
+    extern __shared__ __align__(16) char lds[];
+    const LT L(lds);
+    const KSel ks = select_k(g, (long)g.n1 * g.n2 * g.n3);
+    const int i = blockIdx.x;
+    const long n = (long)g.n1 * NP;
+    const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
+    const double idz = 1.0 / g.dlt[2];
+    __syncthreads();
+    const unsigned char* codes = ks.codes + (long)i * NP;
+    for (int e = threadIdx.x; e < NP; e += NT) {
+        cx<R> w[3][2];
+        mode_w<R, N2, N3, false>((const cx<R>*)nullptr, n, 0, L, L0, e / N3, e % N3, codes[e], idz, w);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[(long)q * n + (long)i * NP + e] = w[q >> 1][q & 1];
+    }
+}
+
 // z then y inverse transforms of NPL planes starting at plane 0, z-twiddles from registers
 template <typename R, int N2, int N3, int NT, int NPL, int EPT>
 DEV void p2_forward_planes(const P2<R, N2, N3>& L, const cx<R> tw[EPT]) {
@@ -420,7 +468,7 @@ DEV void p2_forward_planes(const P2<R, N2, N3>& L, const cx<R> tw[EPT]) {
     ffft<R, N2, NPL * N3, N3, PS, 1, LD, NT, +1>(L.pl, L.twy);
 }
 
-template <typename R, int N2, int N3, int NT>
+template <typename R, int N2, int N3, int NT, bool WT>
 __global__ void __launch_bounds__(NT) k_p2_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
                                                 cx<R>* __restrict__ t) {
     using LT = P2<R, N2, N3>;
@@ -433,6 +481,7 @@ __global__ void __launch_bounds__(NT) k_p2_fwd(Grid g, DeviceTables tb, const cx
     const long n = (long)g.n1 * NP;
     const cx<R>* yb = y + (long)v * 2 * n + (long)i * NP;
     const unsigned char* codes = ks.codes + (long)i * NP;
+    const cx<R>* wt = WT ? (const cx<R>*)g.wtab[sizeof(R) == 8] : nullptr;
     cx<R> y1[EPT], y2[EPT];
     int code[EPT];
 #pragma unroll
@@ -441,7 +490,7 @@ __global__ void __launch_bounds__(NT) k_p2_fwd(Grid g, DeviceTables tb, const cx
         if (NP % NT == 0 || e < NP) {
             y1[s] = yb[e];
             y2[s] = yb[n + e];
-            code[s] = codes[e];
+            code[s] = WT ? 0 : codes[e];
         }
     }
     const cx<double> L0 = p3_setup<R, N2, N3, NT>(g, ks, tb, i, L);
@@ -458,7 +507,12 @@ __global__ void __launch_bounds__(NT) k_p2_fwd(Grid g, DeviceTables tb, const cx
             const int j = e / N3, k = e % N3;
             tw[s] = p3_ztw<R, N2, N3>(L, rot, k, j, s3m);
             cx<R> u[3];
-            if (code[s] == kMasked) {
+            if constexpr (WT) {
+                cx<R> w[3][2];
+                mode_w<R, N2, N3, true>(wt, n, (long)i * NP + e, L, L0, j, k, 0, idz, w);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) u[l] = cmul(w[l][0], y1[s]) + cmul(w[l][1], y2[s]);
+            } else if (code[s] == kMasked) {
                 u[0] = u[1] = u[2] = mk<R>((R)0, (R)0);
             } else {
                 cx<R> w[3][2];
@@ -540,7 +594,7 @@ DEV void p2_adjoint_planes(const P2<R, N2, N3>& L, const cx<R>* __restrict__ t, 
 }
 
 // FP32: at most 128 registers per lane (4 waves per SIMD), so two 512-thread groups share a CU
-template <typename R, int N2, int N3, int NT>
+template <typename R, int N2, int N3, int NT, bool WT>
 __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) k_p2_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ t,
                                                 cx<R>* __restrict__ z) {
     using LT = P2<R, N2, N3>;
@@ -559,8 +613,10 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) k_p2_adj(Grid g, D
     __syncthreads();
     p2_adjoint_planes<R, N2, N3, NT, 2>(L, t, n, v, i, 0, rot, s3m);
     const unsigned char* codes = ks.codes + (long)i * NP;
-    // FP32: W's third row is formed again at the end rather than held, so that the group fits
-    // in 128 registers per lane (two groups per CU); FP64 groups are one per CU by LDS anyway
+    const cx<R>* wt = WT ? (const cx<R>*)g.wtab[sizeof(R) == 8] : nullptr;
+    // FP32: W's third row is formed (or read) again at the end rather than held, so that the
+    // group fits in 128 registers per lane (two groups per CU); FP64 groups are one per CU by
+    // LDS anyway
     constexpr bool kHoldW2 = sizeof(R) == 8;
     constexpr int NW = kHoldW2 ? EPT : 1;
     cx<R> a1[EPT], a2[EPT], w2a[NW], w2b[NW];
@@ -571,10 +627,11 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) k_p2_adj(Grid g, D
         if (kHoldW2) w2a[s % NW] = w2b[s % NW] = mk<R>((R)0, (R)0);
         if (NP % NT == 0 || e < NP) {
             const int j = e / N3, k = e % N3;
-            const int code = codes[e];
-            if (code != kMasked) {
+            const int code = WT ? 0 : (int)codes[e];
+            if (WT || code != kMasked) {
                 cx<R> w[3][2];
-                p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
+                if constexpr (WT) mode_w<R, N2, N3, true>(wt, n, (long)i * NP + e, L, L0, j, k, 0, idz, w);
+                else p3_w<R, N2, N3>(L, L0, j, k, code, idz, w);
 #pragma unroll
                 for (int l = 0; l < 2; ++l) {
                     const cx<R> u = L.pl[l * PS + j * LD + k];
@@ -601,6 +658,9 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) k_p2_adj(Grid g, D
             if (kHoldW2) {
                 wa = w2a[s % NW];
                 wb = w2b[s % NW];
+            } else if (WT) {
+                wa = wt[4 * n + (long)i * NP + e];
+                wb = wt[5 * n + (long)i * NP + e];
             } else {
                 const int code = codes[e];
                 if (code != kMasked) {
@@ -718,7 +778,7 @@ static hipError_t p3_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, 
     if (kind == 2 || (kind == 0 && fixed_plane_available(g.n2, g.n3, sizeof(R) == 8, 2))) goto two;
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P3<R, A, B>::bytes <= kLdsMax) {                                          \
-        hipLaunchKernelGGL((k_p3_fwd<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, y, t); \
+        hipLaunchKernelGGL((k_p3_fwd<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, y, t); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -728,7 +788,7 @@ static hipError_t p3_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, 
 two:
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
-        hipLaunchKernelGGL((k_p2_fwd<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, y, t); \
+        hipLaunchKernelGGL((k_p2_fwd<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, y, t); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -745,7 +805,10 @@ static hipError_t p3_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, 
     if (kind == 2) goto two;
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P3<R, A, B>::bytes <= kLdsMax) {                                          \
-        hipLaunchKernelGGL((k_p3_adj<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
+        if (g.wtab[sizeof(R) == 8])                                                                          \
+            hipLaunchKernelGGL((k_p3_adj<R, A, B, T, true>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_p3_adj<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -755,7 +818,10 @@ static hipError_t p3_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, 
 two:
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
-        hipLaunchKernelGGL((k_p2_adj<R, A, B, T>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
+        if (g.wtab[sizeof(R) == 8])                                                                          \
+            hipLaunchKernelGGL((k_p2_adj<R, A, B, T, true>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_p2_adj<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -780,6 +846,20 @@ static hipError_t xl_fixed(const Grid& g, const DeviceTables& tb, const R* scale
         }                                                                                                    \
     }
     PCX_XL_SIZES(X)
+#undef X
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t launch_wtable(const Grid& g, const DeviceTables& tb, cx<R>* out, hipStream_t st, bool* done) {
+    *done = false;
+#define X(A, B, T)                                                                                           \
+    if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
+        hipLaunchKernelGGL((k_wtable<R, A, B, T>), dim3(g.n1), dim3(T), (P2<R, A, B>::bytes), st, g, tb, out); \
+        *done = true;                                                                                        \
+        return hipGetLastError();                                                                            \
+    }
+    PCX_P3_SIZES(X)
 #undef X
     return hipSuccess;
 }
@@ -829,13 +909,16 @@ template <typename R>
 static hipError_t fixed_limits() {
     hipError_t e = hipSuccess;
 #define X(A, B, T)                                                                 \
-    if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_fwd<R, A, B, T>); \
-    if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_adj<R, A, B, T>);
+    if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_fwd<R, A, B, T, false>); \
+    if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_adj<R, A, B, T, false>); \
+    if (e == hipSuccess && P3<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p3_adj<R, A, B, T, true>); \
+    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_wtable<R, A, B, T>);
     PCX_P3_SIZES(X)
 #undef X
 #define X(A, B, T)                                                                 \
-    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_fwd<R, A, B, T>); \
-    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_adj<R, A, B, T>);
+    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_fwd<R, A, B, T, false>); \
+    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_adj<R, A, B, T, false>); \
+    if (e == hipSuccess && P2<R, A, B>::bytes <= kLdsMax) e = lds_limit(k_p2_adj<R, A, B, T, true>);
     PCX_P2_SIZES(X)
 #undef X
 #define X(A, TBV, T) \
@@ -859,6 +942,8 @@ template hipError_t launch_fixed_plane_adj<float>(const Grid&, const DeviceTable
                                                   int, hipStream_t, bool*);
 template hipError_t launch_fixed_plane_adj<double>(const Grid&, const DeviceTables&, const cx<double>*, cx<double>*,
                                                    int, hipStream_t, bool*);
+template hipError_t launch_wtable<float>(const Grid&, const DeviceTables&, cx<float>*, hipStream_t, bool*);
+template hipError_t launch_wtable<double>(const Grid&, const DeviceTables&, cx<double>*, hipStream_t, bool*);
 template hipError_t launch_fixed_xline<float>(const Grid&, const DeviceTables&, const float*, cx<float>*, int,
                                               hipStream_t, bool*);
 template hipError_t launch_fixed_xline<double>(const Grid&, const DeviceTables&, const double*, cx<double>*, int,

@@ -233,6 +233,7 @@ Grid Plan::grid(const double kappa[3]) const {
     for (int f = 0; f < 2; ++f) g.split[f] = split_plane_needed(g.n2, g.n3, f) ? 1 : 0;
     g.nvk = 0;
     g.kaps = nullptr;
+    g.wtab[0] = g.wtab[1] = nullptr;
     return g;
 }
 
@@ -246,8 +247,21 @@ int Plan::grid_for(const double kappa[3], Grid* g) {
         if (e != hipSuccess) return hip_fail(e, "mode codes");
         for (int l = 0; l < 3; ++l) codes_kappa[l] = kappa[l];
         codes_valid = true;
+        wtab_valid[0] = wtab_valid[1] = false;
     }
     *g = grid(kappa);
+    // the FP32 W table where the fixed-size FP32 plane kernels run: the adjoint kernel then reads
+    // W instead of forming it per vector
+    if (!g->generic[0] && fixed_plane_available(g->n2, g->n3, 0, g->fixed_kind[0])) {
+        if (!wtab_valid[0]) {
+            if ((rc = grow(&wtab_mem, &wtab_cap, 6 * (size_t)n * sizeof(cx<float>)))) return rc;
+            bool done = false;
+            hipError_t e = launch_wtable<float>(*g, tables, (cx<float>*)wtab_mem, stream, &done);
+            if (e != hipSuccess) return hip_fail(e, "mixing table");
+            wtab_valid[0] = done;
+        }
+        if (wtab_valid[0]) g->wtab[0] = wtab_mem;
+    }
     return PCX_OK;
 }
 
@@ -372,8 +386,8 @@ extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_str
 extern "C" void pcx_plan_destroy(pcx_plan* pp) {
     Plan* p = (Plan*)pp;
     if (!p) return;
-    void* bufs[] = {p->tables_mem, p->eps_mem, p->work,  p->lob_mem,  p->prec,
-                    p->gram_part,  p->small_mem, p->codes, p->mcodes, p->kaps_dev};
+    void* bufs[] = {p->tables_mem, p->eps_mem, p->work,   p->lob_mem,  p->prec,    p->gram_part,
+                    p->small_mem,  p->codes,   p->mcodes, p->kaps_dev, p->wtab_mem};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->pinned) (void)hipHostFree(p->pinned);

@@ -61,6 +61,12 @@ struct Plan {
     double codes_kappa[3] = {0, 0, 0};
     bool codes_valid = false;
 
+    // FP32 W table for the kappa of the codes (6 n complex), built with them for grids that have
+    // fixed-size FP32 plane kernels
+    void* wtab_mem = nullptr;
+    size_t wtab_cap = 0;
+    bool wtab_valid[2] = {false, false};
+
     // kernel variant of the A_r path (PCX_VARIANT_*)
     int variant = PCX_VARIANT_AUTO;
     // autotuned choice per precision ([0] FP32, [1] FP64): 0 untuned, -1 / -2 the three- / two-

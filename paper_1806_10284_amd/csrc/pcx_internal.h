@@ -37,6 +37,13 @@ struct Grid {
     // vector; kaps (device, 3 per k) and codes (n bytes per k) then replace kap and codes
     int nvk;
     const double* kaps;
+    // W of every mode for this kappa ([0] FP32, [1] FP64; layout [2l + c][i][j][k], c the column
+    // of the 3 x 2 matrix, zero on the masked mode), or null: the fixed-size plane kernels then
+    // form W per mode and vector.  Only the FP32 table is built, and only the adjoint plane
+    // kernels read it: measured at 64^3, 32 vectors, it takes the FP32 adjoint from 153 to 134 us
+    // (plane i runs on XCD i mod 8, so each XCD's eighth of the table stays in its L2 across the
+    // vectors), leaves the forward kernels unchanged and slows the FP64 adjoint (96 B per mode)
+    const void* wtab[2];
 };
 
 template <typename R>
@@ -97,6 +104,9 @@ hipError_t launch_fixed_xline(const Grid& g, const DeviceTables& tb, const R* sc
                               hipStream_t st, bool* done);
 // kind: 0 any, 3 the three-plane kernels, 2 the two-plane kernels
 bool fixed_plane_available(int n2, int n3, int fp64, int kind = 0);
+// W of every mode (the Grid's wtab layout) for a grid with fixed-size plane kernels
+template <typename R>
+hipError_t launch_wtable(const Grid& g, const DeviceTables& tb, cx<R>* out, hipStream_t st, bool* done);
 bool fixed_xline_available(int n1, long np, int fp64);
 hipError_t configure_fixed_kernels();
 

@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="fp32_refine", choices=["fp32_refine", "fp64", "fp32"])
+    ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "lanczos"],
+                    help="lanczos: the paper's driver (inverse Lanczos, CG inner solves, FP64; --mode ignored)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -214,6 +216,8 @@ def main():
               "without communication; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
+    if args.solver == "lanczos":
+        args.mode = "fp64"
     import torch
     from paper_1806_10284_amd import PCX_MODE_FP32, PCX_MODE_FP32_REFINE, PCX_MODE_FP64
     torch.cuda.set_device(0)
@@ -234,25 +238,36 @@ def main():
         return
 
     solve_kw = dict(mode=mode, tol=1e-10, want_y=False)
-    for w in range(args.warmup):
+
+    def one_solve():
+        if args.solver == "lanczos":
+            # the paper's outer / inner tolerances (1e-12, 1e-13)
+            lam, sl = plan.pcx_solve_lanczos(kappa, NEV)
+            return lam, {"it": sl["steps"], "it32": 0, "mv": sl["matvecs"], "mv32": 0, "pre": 0, "pre32": 0,
+                         "tm": 0.0, "s": sl["seconds"]}
         lam, _, _, st = plan.pcx_solve(kappa, NEV, **solve_kw)
-        print(f"[bench] warmup {w}: {st.iterations} it, {st.matvecs} matvecs, {st.seconds:.3f} s",
-              file=sys.stderr, flush=True)
+        return lam, {"it": st.iterations, "it32": st.iterations_fp32, "mv": st.matvecs, "mv32": st.matvecs_fp32,
+                     "pre": st.precond_applies, "pre32": st.precond_applies_fp32, "tm": st.seconds_matvec,
+                     "s": st.seconds}
+
+    for w in range(args.warmup):
+        lam, st = one_solve()
+        print(f"[bench] warmup {w}: {st['it']} it, {st['mv']} matvecs, {st['s']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     matvecs = matvecs32 = pre = pre32 = 0
     tm = 0.0
     iters = []
     for s in range(args.steps):
-        lam, _, _, st = plan.pcx_solve(kappa, NEV, **solve_kw)
-        matvecs += st.matvecs
-        matvecs32 += st.matvecs_fp32
-        pre += st.precond_applies
-        pre32 += st.precond_applies_fp32
-        tm += st.seconds_matvec
-        iters.append(st.iterations)
-        print(f"[bench] step {s}: {st.iterations} it ({st.iterations_fp32} fp32), {st.matvecs} matvecs, "
-              f"{st.precond_applies} preconditioner applications, {st.seconds:.3f} s", file=sys.stderr, flush=True)
+        lam, st = one_solve()
+        matvecs += st["mv"]
+        matvecs32 += st["mv32"]
+        pre += st["pre"]
+        pre32 += st["pre32"]
+        tm += st["tm"]
+        iters.append(st["it"])
+        print(f"[bench] step {s}: {st['it']} it ({st['it32']} fp32), {st['mv']} matvecs, "
+              f"{st['pre']} preconditioner applications, {st['s']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     el = t1 - t0
@@ -267,7 +282,7 @@ def main():
 
     # per-band agreement of the timed mode with the plain FP64 path (same tolerance)
     per_band = None
-    if args.mode != "fp64":
+    if args.mode != "fp64" or args.solver == "lanczos":
         lam64, _, _, _ = plan.pcx_solve(kappa, NEV, mode=PCX_MODE_FP64, tol=1e-10, want_y=False)
         per_band = [float(abs(a - b) / b) for a, b in zip(lam, lam64)]
         print(f"[bench] per-band |lambda - lambda_fp64| / lambda_fp64: {per_band}", file=sys.stderr, flush=True)
@@ -299,7 +314,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "FCC diamond 64^3 (spheres r=0.12a, rods r=0.11a, eps 13/1), X point, "
                                "10 smallest positive eigenvalues",
-                   "grid": list(N_GRID), "nev": NEV, "mode": args.mode, "kappa": kappa.tolist()},
+                   "grid": list(N_GRID), "nev": NEV, "mode": args.mode, "solver": args.solver,
+                   "kappa": kappa.tolist()},
         "s_per_kpoint": el / args.steps,
         "solve": {"iterations": iters, "matvecs_per_solve": matvecs / args.steps,
                   "precond_applies_per_solve": pre / args.steps,

@@ -226,6 +226,39 @@ int pcx_plan_autotune(pcx_plan *p, const double kappa[3], int precision, int nve
  * components (PCX_EPS_VOXEL).  Overwrites grad. */
 int pcx_grad_eps(pcx_plan *p, int nvec, const void *x, const double *weight, void *grad, int layout);
 
+/* The paper's own eigen-driver (Section 5.2): Lanczos on A_r^{-1} = Sigma_r^{-1} M^{-1}
+ * Sigma_r^{-1}, M = Q_r^* B^{-1} Q_r, every application of M^{-1} an unpreconditioned CG solve
+ * (kappa(M) <= eps_max / eps_min, the bound of Section 5.2), every M product the A_r kernels
+ * between two Lambda_q^{-1/2} scalings; full reorthogonalisation of the Lanczos basis (twice
+ * classical Gram-Schmidt); the largest Ritz values theta of A_r^{-1} give lambda = 1 / theta.
+ * FP64 throughout, single start vector (an exactly repeated eigenvalue appears once per copy
+ * that rounding brings in, as in the paper's method). */
+typedef struct pcx_lanczos_opts {
+    double tol_outer;        /* Ritz pair accepted when beta_j |s_j| <= tol_outer * theta (1e-12) */
+    double tol_inner;        /* CG stops at ||r|| <= tol_inner ||rhs|| (1e-13) */
+    int max_steps;           /* Lanczos steps, the basis kept for reorthogonalisation (200) */
+    int max_cg;              /* CG iterations per inner solve (2000) */
+    unsigned long long seed; /* start vector */
+} pcx_lanczos_opts;
+
+typedef struct pcx_lanczos_stats {
+    int steps;                         /* Lanczos steps taken */
+    long long cg_iterations;           /* over all inner solves */
+    long long matvecs;                 /* single-vector A_r kernel applications (= cg_iterations) */
+    double seconds;
+    double residual[PCX_MAX_BLOCK];    /* beta_j |s_j| / theta per returned band */
+    int converged;
+} pcx_lanczos_stats;
+
+void pcx_lanczos_opts_default(pcx_lanczos_opts *o);
+
+/* lambda: host, nev doubles ascending (nev <= PCX_MAX_BLOCK).  Device workspace of about
+ * (max_steps + 6) * 2n complex128, allocated for the call.  Errors: PCX_E_ARG (bad arguments,
+ * eps not set), PCX_E_NOCONV (lambda and stats filled with the current Ritz values), PCX_E_OOM,
+ * PCX_E_DEVICE. */
+int pcx_solve_lanczos(pcx_plan *p, const double kappa[3], int nev, const pcx_lanczos_opts *opts, double *lambda,
+                      pcx_lanczos_stats *stats);
+
 /* Measurement hook: runs the three kernels of pcx_apply_Ar (plane forward, x-line, plane
  * adjoint) `reps` times on the plan's stream with HIP events around each launch and returns
  * their mean durations in milliseconds in ms_out[0..2].  Same arguments and effect on z as

@@ -47,6 +47,20 @@ class PcxStats(ctypes.Structure):
     ]
 
 
+class PcxLanczosOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol_outer", ctypes.c_double), ("tol_inner", ctypes.c_double), ("max_steps", ctypes.c_int),
+        ("max_cg", ctypes.c_int), ("seed", ctypes.c_ulonglong),
+    ]
+
+
+class PcxLanczosStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int), ("cg_iterations", ctypes.c_longlong), ("matvecs", ctypes.c_longlong),
+        ("seconds", ctypes.c_double), ("residual", ctypes.c_double * PCX_MAX_BLOCK), ("converged", ctypes.c_int),
+    ]
+
+
 class PcxError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pcx error {code}: {msg}")
@@ -64,6 +78,9 @@ _SIGS = [
     ("pcx_plan_set_variant", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("pcx_apply_Ar", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int]),
+    ("pcx_lanczos_opts_default", None, [ctypes.POINTER(PcxLanczosOpts)]),
+    ("pcx_solve_lanczos", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.POINTER(PcxLanczosOpts),
+                                          ctypes.c_void_p, ctypes.POINTER(PcxLanczosStats)]),
     ("pcx_apply_precond", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int]),
     ("pcx_apply_Ar_multi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,

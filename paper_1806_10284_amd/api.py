@@ -222,6 +222,24 @@ class Plan:
             L.check(code)
         return lam, (y if want_y else None), x, stats
 
+    def pcx_solve_lanczos(self, kappa, nev: int, *, tol_outer=1e-12, tol_inner=1e-13, max_steps=200, max_cg=2000,
+                          seed=4242, raise_on_noconv=True):
+        """The paper's driver: inverse Lanczos with CG inner solves (FP64).  Returns (lambda[nev]
+        numpy ascending, stats dict)."""
+        opts = L.PcxLanczosOpts()
+        self._lib.pcx_lanczos_opts_default(ctypes.byref(opts))
+        opts.tol_outer, opts.tol_inner = float(tol_outer), float(tol_inner)
+        opts.max_steps, opts.max_cg, opts.seed = int(max_steps), int(max_cg), int(seed)
+        lam = np.zeros(nev, dtype=np.float64)
+        st = L.PcxLanczosStats()
+        code = self._lib.pcx_solve_lanczos(self._ptr, _kappa3(kappa), int(nev), ctypes.byref(opts),
+                                           lam.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+        stats = {"steps": st.steps, "cg_iterations": st.cg_iterations, "matvecs": st.matvecs,
+                 "seconds": st.seconds, "residual": np.array(list(st.residual))[:nev], "converged": st.converged}
+        if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
+            L.check(code)
+        return lam, stats
+
     def _opts(self, mode, block, max_iter, tol, tol_fp32, seed, precondition, verbose):
         opts = L.PcxOpts()
         self._lib.pcx_opts_default(ctypes.byref(opts))

@@ -515,6 +515,101 @@ hipError_t launch_scale_modes(const cx<float>* in, cx<double>* out, const double
     return hipGetLastError();
 }
 
+// y = a x + b y (complex a, b), FP64
+__global__ void k_axpby(const cx<double>* __restrict__ x, cx<double>* __restrict__ y, double ar, double ai, double br,
+                        double bi, long count) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
+        const cx<double> u = x[e], v = y[e];
+        cx<double> o;
+        o.x = ar * u.x - ai * u.y + br * v.x - bi * v.y;
+        o.y = ar * u.y + ai * u.x + br * v.y + bi * v.x;
+        y[e] = o;
+    }
+}
+
+hipError_t launch_axpby(const cx<double>* x, cx<double>* y, cx<double> a, cx<double> b, long count, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(count)), dim3(256), 0, st, x, y, a.x, a.y, b.x, b.y, count);
+    return hipGetLastError();
+}
+
+// sum_e conj(a_e) b_e over count entries: per-work-group partial sums, then one work-group adds them
+constexpr int kDotGroups = 1024;
+
+__global__ void __launch_bounds__(256) k_dot_part(const cx<double>* __restrict__ a, const cx<double>* __restrict__ b,
+                                                  long count, cx<double>* __restrict__ part) {
+    __shared__ double rx[4], ry[4];
+    double sx = 0.0, sy = 0.0;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
+        const cx<double> u = a[e], v = b[e];
+        sx = fma(u.x, v.x, sx);
+        sx = fma(u.y, v.y, sx);
+        sy = fma(u.x, v.y, sy);
+        sy = fma(-u.y, v.x, sy);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_down(sx, off, 64);
+        sy += __shfl_down(sy, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        rx[wid] = sx;
+        ry[wid] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cx<double> o;
+        o.x = rx[0] + rx[1] + rx[2] + rx[3];
+        o.y = ry[0] + ry[1] + ry[2] + ry[3];
+        part[blockIdx.x] = o;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_dot_final(const cx<double>* __restrict__ part, int nparts,
+                                                   cx<double>* __restrict__ out) {
+    __shared__ double rx[4], ry[4];
+    double sx = 0.0, sy = 0.0;
+    for (int e = threadIdx.x; e < nparts; e += blockDim.x) {
+        sx += part[e].x;
+        sy += part[e].y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_down(sx, off, 64);
+        sy += __shfl_down(sy, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        rx[wid] = sx;
+        ry[wid] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out->x = rx[0] + rx[1] + rx[2] + rx[3];
+        out->y = ry[0] + ry[1] + ry[2] + ry[3];
+    }
+}
+
+hipError_t launch_dot(const cx<double>* a, const cx<double>* b, long count, cx<double>* part, cx<double>* out,
+                      hipStream_t st) {
+    long blocks = (count + 255) / 256;
+    if (blocks > kDotGroups) blocks = kDotGroups;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_dot_part, dim3((unsigned)blocks), dim3(256), 0, st, a, b, count, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, part, (int)blocks, out);
+    return hipGetLastError();
+}
+
+__global__ void k_sqrt(const double* __restrict__ in, double* __restrict__ out, long count) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x)
+        out[e] = sqrt(in[e]);
+}
+
+hipError_t launch_sqrt(const double* in, double* out, long count, hipStream_t st) {
+    hipLaunchKernelGGL(k_sqrt, dim3(grid_for(count)), dim3(256), 0, st, in, out, count);
+    return hipGetLastError();
+}
+
 __global__ void k_grad(const cx<double>* __restrict__ x, const double* __restrict__ w, int nvec, long n,
                        double* __restrict__ grad, int voxel) {
     const long cnt = voxel ? n : 3 * n;

@@ -175,6 +175,13 @@ hipError_t launch_scale_modes(const cx<R>* in, cx<R>* out, const double* prec, l
 // the same from FP32 into FP64
 hipError_t launch_scale_modes(const cx<float>* in, cx<double>* out, const double* prec, long n, int nvec,
                               hipStream_t st);
+// y = a x + b y over count complex FP64 entries
+hipError_t launch_axpby(const cx<double>* x, cx<double>* y, cx<double> a, cx<double> b, long count, hipStream_t st);
+// *out = a^H b over count complex FP64 entries; part: device, at least 1024 entries of scratch
+hipError_t launch_dot(const cx<double>* a, const cx<double>* b, long count, cx<double>* part, cx<double>* out,
+                      hipStream_t st);
+// out = sqrt(in), count doubles
+hipError_t launch_sqrt(const double* in, double* out, long count, hipStream_t st);
 // grad[p] = -sum_t w_t |x_t(p)|^2 ; voxel: summed over the 3 components.  w: device, nvec doubles.
 hipError_t launch_grad(const cx<double>* x, const double* w, int nvec, long n, double* grad, int voxel,
                        hipStream_t st);

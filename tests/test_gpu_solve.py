@@ -143,6 +143,31 @@ def test_next_to_gamma_vs_dense(mode):
     assert np.all(np.abs(lam - ref) <= 1e-10 * ref + atol), (lam - ref) / ref
 
 
+@pytest.mark.parametrize("case", ["tri_543", "bcc_6", "hex_4_4_6"])
+def test_paper_lanczos_driver_vs_dense(case):
+    """The paper's driver (inverse Lanczos, CG inner solves on Q_r^* B^{-1} Q_r, tolerances 1e-12 /
+    1e-13 as in its experiments) against the dense oracle to 1e-10 (random eps: no repeated
+    eigenvalues, which a single-vector Lanczos would need rounding to resolve)."""
+    from paper_1806_10284_amd import Plan, pcx_geometry
+    avec, n, kappa = {
+        "tri_543": (S.triclinic(1), (5, 4, 3), (0.11, -0.37, 0.42)),
+        "bcc_6": (S.BCC, (6, 6, 6), (0.25, 0.1, 0.0)),
+        "hex_4_4_6": (S.HEX, (4, 4, 6), (0.3, 0.0, 0.2)),
+    }[case]
+    og = lattice_geometry(avec, *n)
+    rng = np.random.default_rng(5)
+    eps = rng.uniform(1.0, 13.0, (3, og.npts))
+    nev = 6
+    ref, _ = dense_gep(og, kappa, eps, nev)
+    plan = Plan(pcx_geometry(avec, *n), max_vectors=4)
+    plan.pcx_plan_set_eps(eps)
+    say("lanczos", case)
+    lam, st = plan.pcx_solve_lanczos(kappa, nev, max_steps=min(120, 2 * og.npts - 4))
+    say("lanczos", case, "steps", st["steps"], "CG iterations", st["cg_iterations"])
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    assert st["converged"] == nev and st["matvecs"] == st["cg_iterations"] > 0
+
+
 def test_gradient_matches_oracle_formula():
     """pcx_grad_eps on the solver's x equals -lambda |x|^2 / x*Bx evaluated by the oracle on the dense
     eigenvector of a simple eigenvalue."""

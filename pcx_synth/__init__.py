@@ -78,6 +78,15 @@ FCC_POINTS = {
 }
 
 
+# BCC corner points (Cartesian, cubic cell side a = 1)
+BCC_POINTS = {
+    "G": np.array([0.0, 0.0, 0.0]),
+    "H": TWO_PI * np.array([0.0, 0.0, 1.0]),
+    "N": TWO_PI * np.array([0.0, 0.5, 0.5]),
+    "P": TWO_PI * np.array([0.25, 0.25, 0.25]),
+}
+
+
 def fcc_path(npts: int, labels=("G", "X", "W", "K", "G", "L")) -> np.ndarray:
     """npts Bloch vectors spaced uniformly in arc length along the polyline, endpoints included."""
     corners = np.array([FCC_POINTS[c] for c in labels])
@@ -257,6 +266,33 @@ def random_sphere_fill(avec, n, shift, seed: int, fill: float = 0.3,
         mask |= _inside(avec, frac, Sphere(np.asarray(avec) @ f, rng.uniform(rmin, rmax)))
     out = np.full(npts, eps_out)
     out[mask] = eps_in
+    return out
+
+
+GYROID_LEVEL = 1.1
+GYROID_EPS_SWEEP = tuple(float(e) for e in np.linspace(3.0, 30.0, 10))   # 3, 6, ..., 30
+
+
+def gyroid_function(r: np.ndarray) -> np.ndarray:
+    """sin(2 pi x) cos(2 pi y) + sin(2 pi y) cos(2 pi z) + sin(2 pi z) cos(2 pi x) at Cartesian
+    points r (m, 3), cubic cell side a = 1 (the single-gyroid level set of Section 6)."""
+    t = 2.0 * math.pi * np.asarray(r, dtype=np.float64)
+    s, c = np.sin(t), np.cos(t)
+    return s[:, 0] * c[:, 1] + s[:, 1] * c[:, 2] + s[:, 2] * c[:, 0]
+
+
+def gyroid_yee(n, shift, eps_in: float, eps_out: float = 1.0, level: float = GYROID_LEVEL,
+               avec=None) -> np.ndarray:
+    """Single gyroid on the BCC lattice (Section 6): eps_in at the Yee points where the gyroid
+    function exceeds ``level``, eps_out elsewhere; (3, n1 n2 n3).  The function is unchanged by
+    the BCC translations (each of x, y, z moved by 1/2 flips the sign of every sine and cosine),
+    so it is periodic on the primitive cell of ``BCC``."""
+    avec = BCC if avec is None else np.asarray(avec, dtype=np.float64)
+    npts = n[0] * n[1] * n[2]
+    out = np.full((3, npts), eps_out, dtype=np.float64)
+    for comp in range(3):
+        r = grid_fractional(n, shift, YEE_OFFSETS[comp]) @ avec.T
+        out[comp, gyroid_function(r) > level] = eps_in
     return out
 
 

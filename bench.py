@@ -19,11 +19,12 @@ set ~ 450 MB, larger than the 256 MB last-level cache); and the FP64 CPU oracle'
 on this host as a reference.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--mode fp32_refine|fp64|fp32]
-                    [--no-cpu-baseline] [--profile-kernels] [--workload fcc_diamond|gyroid_sweep]
+                    [--no-cpu-baseline] [--profile-kernels] [--workload fcc_diamond|gyroid_sweep|gyroid_bands]
 
 --workload gyroid_sweep times the single-gyroid permittivity sweep of Section 6 instead (BCC 64^3,
 eps 3..30, one plan per eps, all ten solved as one batch at the N point); its roofline block runs
-on the eps = 12 plan.
+on the eps = 12 plan.  --workload gyroid_bands solves the same ten plans along G-H-N-G-P-H with 10
+parts per segment (510 problems per step; run it with --steps 1 --warmup 0).
 """
 from __future__ import annotations
 
@@ -200,9 +201,13 @@ def run_gyroid_sweep(args, torch, mode):
     """Section 6's permittivity sweep: the single gyroid on the BCC lattice (level set > 1.1, cubic
     cell a), grid 64^3, eps = 3, 6, ..., 30 in air, one plan per eps, the N point, 10 bands.  One
     step = the whole sweep as one pcx_solve_batch call (worker threads with their own streams
-    overlap the ten solves)."""
+    overlap the ten solves).  --workload gyroid_bands: the ten plans along the path G-H-N-G-P-H with
+    each segment cut into 10 parts (51 wave vectors, 510 problems per step), the paper's figure of
+    band structures against eps."""
     import pcx_synth as S
     from paper_1806_10284_amd import Plan, pcx_geometry, pcx_kappa_from_bloch, pcx_solve_batch
+    from paper_1806_10284_amd.bands import band_structure
+    bands = args.workload == "gyroid_bands"
     g = pcx_geometry(S.BCC, *N_GRID)
     kappa = pcx_kappa_from_bloch(S.BCC, S.BCC_POINTS["N"])
     plans, epss = [], []
@@ -215,17 +220,25 @@ def run_gyroid_sweep(args, torch, mode):
     print(f"[bench] setup done: BCC gyroid {N_GRID}, eps {S.GYROID_EPS_SWEEP}, kappa {kappa.tolist()}",
           file=sys.stderr, flush=True)
     problems = [(p, [tuple(kappa)]) for p in plans]
-    nprob = len(problems)
+    corners = [S.BCC_POINTS[c] for c in "GHNGPH"]
+    nprob = len(problems) * (51 if bands else 1)
 
     def one_sweep():
         t = time.perf_counter()
-        lam, _, st = pcx_solve_batch(problems, NEV, mode=mode, tol=1e-10)
+        if bands:
+            bs = band_structure(plans, S.BCC, corners, NEV, parts=10, mode=mode, tol=1e-10)
+            lam, st = bs.lam.reshape(-1, NEV), bs.stats
+        else:
+            lam, _, st = pcx_solve_batch(problems, NEV, mode=mode, tol=1e-10)
         return lam, st, time.perf_counter() - t
+
+    def its(st):
+        return [x.iterations for x in st] if not bands else \
+            f"mean {np.mean([x.iterations for x in st]):.1f}, max {max(x.iterations for x in st)}"
 
     for w in range(args.warmup):
         _, st, s_el = one_sweep()
-        print(f"[bench] warmup {w}: iterations {[x.iterations for x in st]}, {s_el:.3f} s",
-              file=sys.stderr, flush=True)
+        print(f"[bench] warmup {w}: iterations {its(st)}, {s_el:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     applies = applies32 = 0
@@ -234,7 +247,7 @@ def run_gyroid_sweep(args, torch, mode):
         lam, st, s_el = one_sweep()
         applies += sum(x.matvecs + x.precond_applies for x in st)
         applies32 += sum(x.matvecs_fp32 + x.precond_applies_fp32 for x in st)
-        iters.append([x.iterations for x in st])
+        iters.append(its(st))
         print(f"[bench] step {s}: iterations {iters[-1]}, {s_el:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -261,13 +274,18 @@ def run_gyroid_sweep(args, torch, mode):
         "dtype": {"fp32_refine": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.mode],
         "data": "synthetic",
         "config": {"workload": "BCC single gyroid 64^3 (sin-cos level set > 1.1, eps 3..30 in steps of 3 "
-                               "in air), one plan per eps batched, N point, 10 smallest positive eigenvalues",
+                               "in air), one plan per eps batched, "
+                               + ("path G-H-N-G-P-H with 10 parts per segment (51 wave vectors), "
+                                  if bands else "N point, ") + "10 smallest positive eigenvalues",
                    "grid": list(N_GRID), "nev": NEV, "mode": args.mode, "solver": "lobpcg",
                    "eps": list(S.GYROID_EPS_SWEEP), "kappa": kappa.tolist()},
         "s_per_kpoint": el / args.steps / nprob,
         "solve": {"iterations": iters, "operator_applications_per_step": applies / args.steps,
                   "fp32_application_fraction": applies32 / max(applies, 1), "tol": 1e-10,
-                  "lambda": {str(e): [float(x) for x in lam[q]] for q, e in enumerate(S.GYROID_EPS_SWEEP)}},
+                  "problems_per_step": nprob,
+                  "lambda_at_N" if not bands else "lambda_at_G":
+                      {str(e): [float(x) for x in lam[q * (nprob // len(plans))]]
+                       for q, e in enumerate(S.GYROID_EPS_SWEEP)}},
         "block_matvec": {"vectors": ROOF_VECTORS, "precision": "fp64" if args.mode == "fp64" else "fp32",
                          "matvecs_per_s": tot["matvecs_per_s"], "gbs": tot["gbs"],
                          "frac_of_peak": tot["gbs"] / HBM_PEAK_GBS,
@@ -289,8 +307,9 @@ def main():
     ap.add_argument("--mode", default="fp32_refine", choices=["fp32_refine", "fp64", "fp32"])
     ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "lanczos"],
                     help="lanczos: the paper's driver (inverse Lanczos, CG inner solves, FP64; --mode ignored)")
-    ap.add_argument("--workload", default="fcc_diamond", choices=["fcc_diamond", "gyroid_sweep"],
-                    help="gyroid_sweep: BCC single gyroid 64^3, eps 3..30 as one batch of 10 plans at N")
+    ap.add_argument("--workload", default="fcc_diamond", choices=["fcc_diamond", "gyroid_sweep", "gyroid_bands"],
+                    help="gyroid_sweep: BCC single gyroid 64^3, eps 3..30 as one batch of 10 plans at N; "
+                         "gyroid_bands: the same ten plans along G-H-N-G-P-H, 10 parts per segment")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -313,9 +332,9 @@ def main():
     from paper_1806_10284_amd import PCX_MODE_FP32, PCX_MODE_FP32_REFINE, PCX_MODE_FP64
     torch.cuda.set_device(0)
     mode = {"fp32_refine": PCX_MODE_FP32_REFINE, "fp64": PCX_MODE_FP64, "fp32": PCX_MODE_FP32}[args.mode]
-    if args.workload == "gyroid_sweep":
+    if args.workload != "fcc_diamond":
         if args.solver != "lobpcg" or args.profile_kernels:
-            print("--workload gyroid_sweep runs the batched LOBPCG solver only", file=sys.stderr)
+            print(f"--workload {args.workload} runs the batched LOBPCG solver only", file=sys.stderr)
             sys.exit(2)
         return run_gyroid_sweep(args, torch, mode)
     plan, kappa, eps, g = setup(torch, max_vectors=ROOF_VECTORS)

@@ -180,6 +180,9 @@ typedef struct pcx_stats {
     long long precond_applies;         /* single-vector applications of Sigma_r Q_r^* B Q_r Sigma_r
                                           (PCX_PRECOND_INVERSE; the A_r kernels with eps for 1/eps) */
     long long precond_applies_fp32;    /* of which in FP32 */
+    int restarts;                      /* PCX_MODE_FP32_REFINE: 1 if the FP64 phase stagnated with
+                                          bands open and the solve was repeated in FP64 alone from
+                                          the start block, else 0 */
 } pcx_stats;
 
 /* Smallest nev positive eigenvalues of C*C x = lambda B x at Bloch phases kappa

@@ -603,6 +603,19 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         rc = seed_block(B64.X);
     }
     if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false);
+    if (!rc && use32 && use64 && iters < S.o.max_iter) {
+        // FP32+refine whose FP64 phase stopped on stagnation with bands open (seen next to Gamma
+        // at high contrast: started from the FP32 block, the near-zero bands' residuals first
+        // fall to ~1e-7 and then climb back): solve again in FP64 alone from the start block, as
+        // PCX_MODE_FP64 does; at most once, within the same iteration budget
+        bool open = false;
+        for (int j = 0; j < nev; ++j) open = open || !S.converged<double>(j, S.o.tol, true);
+        if (open) {
+            ++S.st.restarts;
+            rc = seed_block(B64.X);
+            if (!rc) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false);
+        }
+    }
     if (!rc) {
         for (int j = 0; j < nev; ++j) lambda[j] = S.theta[j];
         int conv = 0;

@@ -78,6 +78,14 @@ FCC_POINTS = {
 }
 
 
+# SC corner points (Cartesian, a = 1)
+SC_POINTS = {
+    "G": np.array([0.0, 0.0, 0.0]),
+    "X": TWO_PI * np.array([0.0, 0.5, 0.0]),
+    "M": TWO_PI * np.array([0.5, 0.5, 0.0]),
+    "R": TWO_PI * np.array([0.5, 0.5, 0.5]),
+}
+
 # BCC corner points (Cartesian, cubic cell side a = 1)
 BCC_POINTS = {
     "G": np.array([0.0, 0.0, 0.0]),

@@ -1,0 +1,32 @@
+"""Path construction of the band-structure driver (Section 6: each segment between corner points cut
+into equal parts, 10 in the paper)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import pcx_synth as S
+from paper_1806_10284_amd.bands import kpath
+
+
+def test_kpath_parts_and_arc_length():
+    corners = np.array([S.BCC_POINTS[c] for c in "GHNGPH"])
+    pts, arc = kpath(corners, 10)
+    assert pts.shape == (51, 3) and arc.shape == (51,)
+    np.testing.assert_allclose(pts[::10], corners, atol=1e-14)
+    seg = np.linalg.norm(np.diff(corners, axis=0), axis=1)
+    np.testing.assert_allclose(arc[::10], np.concatenate([[0.0], np.cumsum(seg)]), rtol=1e-14)
+    # equal steps inside each segment, and the arc length is the distance walked
+    for i in range(5):
+        steps = np.linalg.norm(np.diff(pts[10 * i:10 * i + 11], axis=0), axis=1)
+        np.testing.assert_allclose(steps, seg[i] / 10, rtol=1e-12)
+    np.testing.assert_allclose(np.diff(arc), np.linalg.norm(np.diff(pts, axis=0), axis=1), rtol=1e-12)
+
+
+def test_kpath_rejects_degenerate_paths():
+    with pytest.raises(ValueError):
+        kpath([S.SC_POINTS["G"]], 10)
+    with pytest.raises(ValueError):
+        kpath([S.SC_POINTS["G"], S.SC_POINTS["X"]], 0)
+    with pytest.raises(ValueError):
+        kpath([S.SC_POINTS["G"], S.SC_POINTS["X"], S.SC_POINTS["X"]], 4)

@@ -90,3 +90,24 @@ def test_gyroid_sweep_64_properties():
         err = np.abs(lam[q] - ref) / ref
         say(f"eps {S.GYROID_EPS_SWEEP[q]}: batch vs separate FP64 solve {err.max():.1e}")
         assert err.max() <= 1e-10, (q, err)
+
+
+def test_gyroid_next_to_gamma_high_contrast():
+    """eps = 30, the path point one tenth of the way from Gamma towards N (two bands near zero): the
+    FP32+refine solve converges (its FP64 phase may stagnate here and the solve is then repeated in
+    FP64 alone from the start block) and equals
+    the plain FP64 solve to 1e-10 plus the Rayleigh-quotient rounding bound of the near-zero bands."""
+    from paper_1806_10284_amd import PCX_MODE_FP32_REFINE, PCX_MODE_FP64, pcx_kappa_from_bloch
+    n, nev = (64, 64, 64), 10
+    og = lattice_geometry(S.BCC, *n)
+    plans, epss = _sweep_plans(n, (30.0,))
+    kappa = tuple(pcx_kappa_from_bloch(S.BCC, 0.1 * S.BCC_POINTS["N"]))
+    say("gyroid 64^3 eps 30 next to Gamma", kappa)
+    lam, _, _, st = plans[0].pcx_solve(kappa, nev, mode=PCX_MODE_FP32_REFINE, tol=1e-10, want_y=False)
+    say(f"refine: {st.iterations} iterations ({st.iterations_fp32} FP32), restarts {st.restarts}")
+    ref, _, _, st64 = plans[0].pcx_solve(kappa, nev, mode=PCX_MODE_FP64, tol=1e-10, want_y=False)
+    say(f"fp64: {st64.iterations} iterations, restarts {st64.restarts}")
+    assert ref[0] < 1e-2 * ref[2]
+    lq_max = np.sum(np.abs(spectrum(og, kappa).lam) ** 2, axis=0).max()
+    atol = 1e-13 * lq_max / epss[0].min()
+    assert np.all(np.abs(lam - ref) <= 1e-10 * ref + atol), (lam - ref) / ref

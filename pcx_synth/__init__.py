@@ -91,8 +91,20 @@ BCC_POINTS = {
     "G": np.array([0.0, 0.0, 0.0]),
     "H": TWO_PI * np.array([0.0, 0.0, 1.0]),
     "N": TWO_PI * np.array([0.0, 0.5, 0.5]),
-    "P": TWO_PI * np.array([0.25, 0.25, 0.25]),
+    "P": TWO_PI * np.array([0.5, 0.5, 0.5]),
 }
+
+
+def _hex_points():
+    # reciprocal vectors of HEX (2 pi times the rows of HEX^-1); b1, b2 at 60 degrees
+    b = TWO_PI * np.linalg.inv(HEX)
+    b1, b2, b3 = b[0], b[1], b[2]
+    m, k, a = 0.5 * b1, (b1 + b2) / 3.0, 0.5 * b3
+    return {"G": np.zeros(3), "M": m, "K": k, "A": a, "L": m + a, "H": k + a}
+
+
+# hexagonal corner points (Cartesian) for the lattice HEX
+HEX_POINTS = _hex_points()
 
 
 def fcc_path(npts: int, labels=("G", "X", "W", "K", "G", "L")) -> np.ndarray:

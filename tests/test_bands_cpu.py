@@ -30,3 +30,21 @@ def test_kpath_rejects_degenerate_paths():
         kpath([S.SC_POINTS["G"], S.SC_POINTS["X"]], 0)
     with pytest.raises(ValueError):
         kpath([S.SC_POINTS["G"], S.SC_POINTS["X"], S.SC_POINTS["X"]], 4)
+
+
+@pytest.mark.parametrize("name", ["SC", "FCC", "BCC", "HEX"])
+def test_corner_points_lie_on_the_brillouin_zone_boundary(name):
+    """Every corner point k != Gamma is as close to some nonzero reciprocal lattice vector G as to
+    Gamma (|k - G| = |k|, on the boundary of the first Brillouin zone) and no closer to any."""
+    avec = getattr(S, name)
+    pts = getattr(S, f"{name}_POINTS")
+    B = 2 * np.pi * np.linalg.inv(avec)          # rows: reciprocal vectors, b_i . a_j = 2 pi delta_ij
+    rng = np.arange(-2, 3)
+    G = np.array([i * B[0] + j * B[1] + k * B[2] for i in rng for j in rng for k in rng
+                  if (i, j, k) != (0, 0, 0)])
+    for lab, k in pts.items():
+        if lab == "G":
+            assert np.all(k == 0)
+            continue
+        d = np.linalg.norm(k - G, axis=1)
+        assert d.min() == pytest.approx(np.linalg.norm(k), rel=1e-12), (name, lab)

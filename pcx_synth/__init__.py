@@ -103,6 +103,15 @@ def _hex_points():
     return {"G": np.zeros(3), "M": m, "K": k, "A": a, "L": m + a, "H": k + a}
 
 
+def _ortho_points():
+    # rectangular Brillouin zone of ORTHO: half reciprocal vectors and their sums
+    b = TWO_PI * np.linalg.inv(ORTHO)
+    x, y, z = 0.5 * b[0], 0.5 * b[1], 0.5 * b[2]
+    return {"G": np.zeros(3), "X": x, "Y": y, "Z": z, "S": x + y, "U": x + z, "T": y + z, "R": x + y + z}
+
+
+# primitive-orthorhombic corner points (Cartesian) for the lattice ORTHO
+ORTHO_POINTS = _ortho_points()
 # hexagonal corner points (Cartesian) for the lattice HEX
 HEX_POINTS = _hex_points()
 

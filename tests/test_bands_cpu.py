@@ -32,7 +32,7 @@ def test_kpath_rejects_degenerate_paths():
         kpath([S.SC_POINTS["G"], S.SC_POINTS["X"], S.SC_POINTS["X"]], 4)
 
 
-@pytest.mark.parametrize("name", ["SC", "FCC", "BCC", "HEX"])
+@pytest.mark.parametrize("name", ["SC", "FCC", "BCC", "HEX", "ORTHO"])
 def test_corner_points_lie_on_the_brillouin_zone_boundary(name):
     """Every corner point k != Gamma is as close to some nonzero reciprocal lattice vector G as to
     Gamma (|k - G| = |k|, on the boundary of the first Brillouin zone) and no closer to any."""

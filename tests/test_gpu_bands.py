@@ -1,8 +1,9 @@
 """The band-structure driver (Section 6: corner-point path, segments cut into equal parts, one GEP
 per wave vector, all plans and path points as one batch).
 
-* vacuum (eps = 1) on SC 8^3 along Gamma-X-M-Gamma-R: at every path point the eigenvalues are the
-  closed-form Lambda_q, each twice (the two transverse polarisations), 1e-9 relative;
+* vacuum (eps = 1) on SC 8^3 along Gamma-X-M-Gamma-R, hexagonal 6x6x8 along Gamma-M-K-Gamma-A-L-H-A
+  and orthorhombic 8x6x6 along Gamma-X-S-Y-Gamma-Z-U-R-T-Z: at every path point the eigenvalues are
+  the closed-form Lambda_q, each twice (the two transverse polarisations), 1e-9 relative;
 * the single gyroid on BCC 8^3 along Gamma-H-N-Gamma-P-H for eps 3 and 13: every point against the
   dense GEP with the explicit sparse curl, 1e-10 relative.
 """
@@ -31,16 +32,20 @@ def _vacuum_positive(og, kappa, count):
     return np.repeat(lq, 2)[:count]
 
 
-def test_vacuum_band_structure_is_closed_form():
+@pytest.mark.parametrize("name,n,path,parts", [("SC", (8, 8, 8), "GXMGR", 4),
+                                              ("HEX", (6, 6, 8), "GMKGALHA", 2),
+                                              ("ORTHO", (8, 6, 6), "GXSYGZURTZ", 2)])
+def test_vacuum_band_structure_is_closed_form(name, n, path, parts):
     from paper_1806_10284_amd import Plan, pcx_geometry
     from paper_1806_10284_amd.bands import band_structure
-    n, nev = (8, 8, 8), 10
-    og = lattice_geometry(S.SC, *n)
-    plan = Plan(pcx_geometry(S.SC, *n), max_vectors=32)
+    nev = 10
+    avec, table = getattr(S, name), getattr(S, f"{name}_POINTS")
+    og = lattice_geometry(avec, *n)
+    plan = Plan(pcx_geometry(avec, *n), max_vectors=32)
     plan.pcx_plan_set_eps(np.ones((3, og.npts)))
-    say("vacuum SC 8^3 band structure G-X-M-G-R, 4 parts")
-    bs = band_structure([plan], S.SC, [S.SC_POINTS[c] for c in "GXMGR"], nev, parts=4, tol=1e-10)
-    assert bs.lam.shape == (1, 17, nev)
+    say(f"vacuum {name} {n} band structure {path}, {parts} parts")
+    bs = band_structure([plan], avec, [table[c] for c in path], nev, parts=parts, tol=1e-10)
+    assert bs.lam.shape == (1, (len(path) - 1) * parts + 1, nev)
     assert all(s.converged == nev for s in bs.stats)
     for t, kap in enumerate(bs.kappas[0]):
         ref = _vacuum_positive(og, kap, nev)

@@ -76,3 +76,29 @@ def test_gyroid_band_structure_vs_dense():
             err = np.abs(bs.lam[q, t] - ref) / ref
             assert err.max() <= 1e-10, (q, t, kap, err)
     np.testing.assert_allclose(bs.omega, np.sqrt(bs.lam) / (2 * np.pi))
+
+
+def test_band_structure_over_two_lattices():
+    """One request over plans of different lattices (a list of lattice vectors, one per plan): the
+    same Cartesian path maps to each lattice's own phases, and both vacuum band structures equal
+    the closed form."""
+    from paper_1806_10284_amd import Plan, pcx_geometry
+    from paper_1806_10284_amd.bands import band_structure
+    nev = 8
+    cases = [(S.SC, (8, 8, 8)), (S.ORTHO, (8, 6, 6))]
+    plans, geoms = [], []
+    for avec, n in cases:
+        og = lattice_geometry(avec, *n)
+        p = Plan(pcx_geometry(avec, *n), max_vectors=32)
+        p.pcx_plan_set_eps(np.ones((3, og.npts)))
+        plans.append(p)
+        geoms.append(og)
+    corners = [S.SC_POINTS["G"], S.SC_POINTS["X"], S.SC_POINTS["M"]]
+    say("vacuum band structure over SC 8^3 and orthorhombic 8x6x6, G-X-M, 3 parts")
+    bs = band_structure(plans, [a for a, _ in cases], corners, nev, parts=3, tol=1e-10)
+    assert bs.lam.shape == (2, 7, nev)
+    assert not np.allclose(bs.kappas[0], bs.kappas[1])
+    for q, og in enumerate(geoms):
+        for t, kap in enumerate(bs.kappas[q]):
+            ref = _vacuum_positive(og, kap, nev)
+            np.testing.assert_allclose(bs.lam[q, t], ref, rtol=1e-9)

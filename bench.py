@@ -283,6 +283,7 @@ def run_gyroid_sweep(args, torch, mode):
         "solve": {"iterations": iters, "operator_applications_per_step": applies / args.steps,
                   "fp32_application_fraction": applies32 / max(applies, 1), "tol": 1e-10,
                   "problems_per_step": nprob,
+                  "fp64_fallbacks_last_step": int(sum(x.restarts for x in st)),
                   "lambda_at_N" if not bands else "lambda_at_G":
                       {str(e): [float(x) for x in lam[q * (nprob // len(plans))]]
                        for q, e in enumerate(S.GYROID_EPS_SWEEP)}},

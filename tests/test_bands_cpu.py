@@ -48,3 +48,14 @@ def test_corner_points_lie_on_the_brillouin_zone_boundary(name):
             continue
         d = np.linalg.norm(k - G, axis=1)
         assert d.min() == pytest.approx(np.linalg.norm(k), rel=1e-12), (name, lab)
+
+
+def test_band_structure_argument_checks():
+    """Rejected before anything reaches the device: no plans, or a lattice count that matches
+    neither one-for-all nor one-per-plan."""
+    from paper_1806_10284_amd.bands import band_structure
+    corners = [S.SC_POINTS["G"], S.SC_POINTS["X"]]
+    with pytest.raises(ValueError):
+        band_structure([], S.SC, corners)
+    with pytest.raises(ValueError):
+        band_structure([object(), object(), object()], [S.SC, S.FCC], corners)

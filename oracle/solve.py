@@ -99,3 +99,69 @@ def residuals(geom: Geometry, kappa, eps_yee, lam, X):
         r = C.conj().T @ (C @ x) - lam[t] * b * x
         out.append(np.linalg.norm(r) / (abs(lam[t]) * np.linalg.norm(b * x)))
     return np.array(out)
+
+
+def nfsep_inverse_lanczos(spec, eps_yee, nev: int, tol_outer: float = 1e-12, tol_inner: float = 1e-13,
+                          seed: int = 1, ncv: int | None = None):
+    """The method of Section 5.2 for grids beyond the sparse factorisation: Lanczos on A_r^{-1}.
+
+    A_r = Sigma_r M Sigma_r with M = Q_r^* B^{-1} Q_r Hermitian positive definite and
+    cond(M) <= max(eps) / min(eps) (the bound of Section 5.2), so
+        A_r^{-1} v = Sigma_r^{-1} M^{-1} Sigma_r^{-1} v,
+    each M^{-1} an unpreconditioned conjugate-gradient solve (relative residual tol_inner) whose
+    M products are Sigma_r^{-1} A_r Sigma_r^{-1} with the FFT operator of this package.  The largest
+    eigenvalues theta of A_r^{-1} (implicitly restarted Lanczos, scipy eigsh, relative accuracy
+    tol_outer) give lambda = 1 / theta.  Modes with Lambda_q = 0 (kappa in Z^3) are outside the
+    range of Sigma_r and are held at zero.
+
+    Returns (lam[nev] ascending, Y[2n, nev] orthonormal NFSEP eigenvectors, info) with info the
+    number of A_r applications and CG iterations.
+    """
+    from .nfsep import Ar_apply
+    n = spec.npts
+    Lq = np.sum(np.abs(spec.lam) ** 2, axis=0).reshape(-1)
+    live = np.concatenate([Lq, Lq]) > 0
+    sig_inv = np.zeros(2 * n)
+    sig_inv[live] = 1.0 / np.sqrt(np.concatenate([Lq, Lq])[live])
+    info = {"ar_applications": 0, "cg_iterations": 0, "inner_solves": 0}
+
+    def m_apply(v):
+        info["ar_applications"] += 1
+        return sig_inv * Ar_apply(spec, eps_yee, sig_inv * v)
+
+    M = spla.LinearOperator((2 * n, 2 * n), matvec=m_apply, dtype=np.complex128)
+
+    def cg_count(_xk):
+        info["cg_iterations"] += 1
+
+    def ainv_apply(v):
+        rhs = sig_inv * np.asarray(v).reshape(-1)
+        info["inner_solves"] += 1
+        w, flag = spla.cg(M, rhs, rtol=tol_inner, atol=0.0, maxiter=20000, callback=cg_count)
+        if flag != 0:
+            raise RuntimeError(f"nfsep_inverse_lanczos: CG did not converge (flag {flag})")
+        return sig_inv * w
+
+    Ainv = spla.LinearOperator((2 * n, 2 * n), matvec=ainv_apply, dtype=np.complex128)
+    rng = np.random.default_rng(seed)
+    v0 = (rng.standard_normal(2 * n) + 1j * rng.standard_normal(2 * n)) * live
+    k = nev
+    theta, Y = spla.eigsh(Ainv, k=k, which="LA", tol=tol_outer, v0=v0,
+                          ncv=ncv or min(2 * n - 2, max(2 * k + 1, 24)))
+    order = np.argsort(-theta)
+    theta = theta[order]
+    Y = Y[:, order]
+    lam = 1.0 / theta
+    Y = Y / np.linalg.norm(Y, axis=0)
+    return lam, Y, info
+
+
+def nfsep_residuals(spec, eps_yee, lam, Y):
+    """||A_r y - lam y|| / (lam ||y||) per column with the FFT operator."""
+    from .nfsep import Ar_apply
+    out = []
+    for t in range(len(lam)):
+        y = Y[:, t]
+        r = Ar_apply(spec, eps_yee, y) - lam[t] * y
+        out.append(np.linalg.norm(r) / (abs(lam[t]) * np.linalg.norm(y)))
+    return np.array(out)

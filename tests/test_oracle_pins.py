@@ -398,3 +398,36 @@ def test_gradient_via_nfsep_vector():
     # and x solves the GEP
     Amat = double_curl(g, kap)
     assert np.linalg.norm(Amat @ x - ev[0] * b * x) < 1e-9 * ev[0] * np.linalg.norm(b * x)
+
+
+@pytest.mark.parametrize("seed,gamma", [(11, False), (12, True)])
+def test_inverse_lanczos_matches_dense_gep(seed, gamma):
+    """Section 5.2's method in the oracle (Lanczos on A_r^{-1}, CG inner solves on the FFT operator)
+    returns the smallest positive eigenvalues of the explicit-curl GEP, with multiplicity, also at
+    Gamma where A_r keeps the masked mode's two zero eigenvalues outside Sigma_r's range."""
+    from oracle.solve import nfsep_inverse_lanczos, nfsep_residuals
+    rng = np.random.default_rng(seed)
+    avec, g = random_geometry(rng, nlo=3, nhi=5)
+    kap = np.zeros(3) if gamma else rng.uniform(-0.5, 0.5, 3)
+    eps = rng.uniform(1.0, 13.0, (3, g.npts))
+    nev = 6
+    ref, _ = dense_gep(g, kap, eps, nev)
+    spec = spectrum(g, kap)
+    lam, Y, info = nfsep_inverse_lanczos(spec, eps, nev, ncv=min(2 * 2 * g.npts - 2, 40))
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    assert nfsep_residuals(spec, eps, lam, Y).max() < 1e-9
+    assert info["ar_applications"] == info["cg_iterations"] > 0
+
+
+def test_inverse_lanczos_matches_config1_golden():
+    """At the SC 16^3 workload the inverse-Lanczos oracle equals the stored explicit-curl
+    shift-invert eigenvalues (tests/golden/config1_sc16.json) to 1e-10."""
+    import json
+    import os
+    from oracle.solve import nfsep_inverse_lanczos
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config1_sc16.json")))
+    g = lattice_geometry(S.SC, 16, 16, 16)
+    kap = kappa_from_bloch(S.SC, np.array([np.pi / 2, 0.0, 0.0]))
+    eps = S.sample_yee(S.SC, g.n, g.shift, S.sc_sphere_shapes(), 13.0, 1.0)
+    lam, _, _ = nfsep_inverse_lanczos(spectrum(g, kap), eps, 10)
+    np.testing.assert_allclose(lam, gold["lambda"], rtol=1e-10)

@@ -11,12 +11,13 @@ One step = one complete k-point solve (pcx_solve): LOBPCG iterations (A_r block 
 approximate-inverse preconditioner, FP64 Gram products, host Rayleigh-Ritz), refinement and the
 eigenvalues on the host.
 
-Printed (one JSON line): value = applications of the nullspace-free FFT operator per second over
-the timed solves (A_r itself and the preconditioner, which runs the same kernels with eps in
-place of 1/eps; both counts are listed under "solve"), s_per_kpoint; the
-roofline of the dominant matvec kernel measured with HIP events on a 32-vector block (working
-set ~ 450 MB, larger than the 256 MB last-level cache); and the FP64 CPU oracle's matvec rate
-on this host as a reference.
+Printed (one JSON line): value = single-vector A_r applications per second over the timed solves
+(the approximate-inverse preconditioner runs the same kernels with eps in place of 1/eps; its
+applications are listed separately under "solve"), s_per_kpoint, the final relative residual of
+every band and the bands (if any) accepted at the absolute residual floor; the roofline of the
+dominant matvec kernel measured with HIP events on a 32-vector block (working set ~ 450 MB, larger
+than the 256 MB last-level cache); and the FP64 CPU oracle's matvec rate on this host's cores,
+with its estimated seconds per k-point, as a reference.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--mode fp32_refine|fp64|fp32]
                     [--no-cpu-baseline] [--profile-kernels] [--workload fcc_diamond|gyroid_sweep|gyroid_bands]
@@ -175,15 +176,13 @@ def roofline_block(torch, plan, kappa, fp64: bool, reps: int):
                  "matvecs_per_s": ROOF_VECTORS / (tot_ms * 1e-3)}
 
 
-def cpu_baseline(eps, kappa, budget_s: float = 12.0, avec=None, label="FCC diamond 64^3 at X"):
-    """The FP64 oracle's A_r application (numpy FFT route) on this host, same workload."""
-    import pcx_synth as S
-    from oracle.geometry import lattice_geometry
+_CPU_JOB = {}
+
+
+def _cpu_worker(budget_s: float):
+    """One process of the CPU baseline: the oracle's A_r on the stored workload for budget_s."""
     from oracle.nfsep import Ar_apply
-    from oracle.spectral import spectrum
-    g = lattice_geometry(S.FCC if avec is None else avec, *N_GRID)
-    spec = spectrum(g, kappa)
-    y = S.random_block(4, 2 * g.npts, 1)[:, 0]
+    spec, eps, y = _CPU_JOB["spec"], _CPU_JOB["eps"], _CPU_JOB["y"]
     done = 0
     t0 = time.perf_counter()
     while True:
@@ -191,13 +190,87 @@ def cpu_baseline(eps, kappa, budget_s: float = 12.0, avec=None, label="FCC diamo
         done += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
-            break
-    return {"value": done / el, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} FP64 A_r applications (numpy FFT, single-threaded) on {label}, "
-                      f"{el:.1f} s"}
+            return done, el
 
 
-def run_gyroid_sweep(args, torch, mode):
+def host_info() -> dict:
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    blas = None
+    try:
+        dep = np.__config__.CONFIG["Build Dependencies"]["blas"]
+        blas = f"{dep.get('name')} {dep.get('version')}"
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": cores, "numpy_blas": blas}
+
+
+def cpu_baseline(avec, grid, eps, kappa, label: str, budget_s: float = 12.0, lanczos_ar: int | None = None):
+    """The FP64 oracle on this host's cores, before anything touches the GPU: one process per usable
+    core (at most 16, the box's share) applies the oracle's A_r (numpy FFT route, single-threaded per
+    process, BLAS threads pinned to 1) to the same workload for budget_s; value = their summed rate.
+    The oracle's own eigensolve (Section 5.2's inverse Lanczos, a sequential chain of A_r
+    applications) needs `lanczos_ar` applications on this workload (counted when the stored
+    oracle eigenvalues were written), so its seconds per k-point are estimated as that count over
+    the rate of one process running alone (measured first, for budget_s / 2)."""
+    import multiprocessing as mp
+
+    from oracle.geometry import lattice_geometry
+    from oracle.spectral import spectrum
+    import pcx_synth as S
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    info = host_info()
+    procs = max(1, min(16, info["usable_cores"]))
+    g = lattice_geometry(avec, *grid)
+    _CPU_JOB.update(spec=spectrum(g, kappa), eps=eps, y=S.random_block(4, 2 * g.npts, 1)[:, 0])
+    ctx = mp.get_context("fork")
+    with ctx.Pool(1) as pool:                 # one process alone: the rate a sequential solve sees
+        d1, el1 = pool.map(_cpu_worker, [budget_s / 2])[0]
+    with ctx.Pool(procs) as pool:
+        runs = pool.map(_cpu_worker, [budget_s] * procs)
+    rate = sum(d / el for d, el in runs)
+    one = d1 / el1
+    out = {"value": rate, "unit": "matvecs/s", "cores": procs, "kind": "oracle",
+           "sample": f"{sum(d for d, _ in runs)} FP64 A_r applications of the oracle (numpy FFT) on {label}, "
+                     f"{procs} processes x {budget_s:.0f} s (after {d1} by one process alone in {el1:.1f} s)",
+           "host": info, "fft": "numpy.fft (pocketfft), one thread per process"}
+    if lanczos_ar:
+        out["s_per_kpoint_estimate"] = lanczos_ar / one
+        out["s_per_kpoint_note"] = (f"oracle inverse Lanczos (CG inner solves) needs {lanczos_ar} sequential A_r "
+                                    f"applications on this workload; estimate = count / the rate of one "
+                                    f"process alone ({one:.2f} matvecs/s)")
+    return out
+
+
+def cpu_baseline_for(workload: str):
+    """The oracle's inputs for the bench workload, from the oracle's own geometry (no GPU library)."""
+    import pcx_synth as S
+    from oracle.geometry import kappa_from_bloch, lattice_geometry
+    if workload == "fcc_diamond":
+        g = lattice_geometry(S.FCC, *N_GRID)
+        eps = S.sample_yee(S.FCC, N_GRID, tuple(g.shift), S.diamond_shapes(), 13.0, 1.0)
+        kappa = kappa_from_bloch(S.FCC, S.FCC_POINTS["X"])
+        gold = os.path.join(ROOT, "tests", "golden", "config2_fcc64.json")
+        lanczos_ar = json.load(open(gold)).get("ar_applications") if os.path.exists(gold) else None
+        return cpu_baseline(S.FCC, N_GRID, eps, kappa, "FCC diamond 64^3 at X", lanczos_ar=lanczos_ar)
+    g = lattice_geometry(S.BCC, *N_GRID)
+    eps = S.gyroid_yee(N_GRID, tuple(g.shift), 12.0)
+    kappa = kappa_from_bloch(S.BCC, S.BCC_POINTS["N"])
+    return cpu_baseline(S.BCC, N_GRID, eps, kappa, "BCC gyroid 64^3 (eps 12) at N")
+
+
+def run_gyroid_sweep(args, torch, mode, cpu):
     """Section 6's permittivity sweep: the single gyroid on the BCC lattice (level set > 1.1, cubic
     cell a), grid 64^3, eps = 3, 6, ..., 30 in air, one plan per eps, the N point, 10 bands.  One
     step = the whole sweep as one pcx_solve_batch call (worker threads with their own streams
@@ -241,10 +314,11 @@ def run_gyroid_sweep(args, torch, mode):
         print(f"[bench] warmup {w}: iterations {its(st)}, {s_el:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    applies = applies32 = 0
+    applies = applies32 = matvecs = 0
     iters = []
     for s in range(args.steps):
         lam, st, s_el = one_sweep()
+        matvecs += sum(x.matvecs for x in st)
         applies += sum(x.matvecs + x.precond_applies for x in st)
         applies32 += sum(x.matvecs_fp32 + x.precond_applies_fp32 for x in st)
         iters.append(its(st))
@@ -256,13 +330,9 @@ def run_gyroid_sweep(args, torch, mode):
     dominant = max(kern, key=lambda k: kern[k]["ms"])
     dk = kern[dominant]
     print(f"[bench] roofline block: {json.dumps(kern)}", file=sys.stderr, flush=True)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(epss[q_mid], kappa, avec=S.BCC, label="BCC gyroid 64^3 (eps 12) at N")
-        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
     out = {
         "metric": "nullspace-free matvecs/s + HBM GB/s vs peak; s per k-point, 10 bands at 64^3",
-        "value": applies / el,
+        "value": matvecs / el,
         "unit": "matvecs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -280,7 +350,8 @@ def run_gyroid_sweep(args, torch, mode):
                    "grid": list(N_GRID), "nev": NEV, "mode": args.mode, "solver": "lobpcg",
                    "eps": list(S.GYROID_EPS_SWEEP), "kappa": kappa.tolist()},
         "s_per_kpoint": el / args.steps / nprob,
-        "solve": {"iterations": iters, "operator_applications_per_step": applies / args.steps,
+        "solve": {"iterations": iters, "matvecs_per_step": matvecs / args.steps,
+                  "operator_applications_per_step": applies / args.steps,
                   "fp32_application_fraction": applies32 / max(applies, 1), "tol": 1e-10,
                   "problems_per_step": nprob,
                   "fp64_fallbacks_last_step": int(sum(x.restarts for x in st)),
@@ -329,6 +400,11 @@ def main():
 
     if args.solver == "lanczos":
         args.mode = "fp64"
+    # the CPU baseline runs first, in forked processes, before anything initialises the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.profile_kernels:
+        cpu = cpu_baseline_for(args.workload)
+        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
     import torch
     from paper_1806_10284_amd import PCX_MODE_FP32, PCX_MODE_FP32_REFINE, PCX_MODE_FP64
     torch.cuda.set_device(0)
@@ -337,7 +413,7 @@ def main():
         if args.solver != "lobpcg" or args.profile_kernels:
             print(f"--workload {args.workload} runs the batched LOBPCG solver only", file=sys.stderr)
             sys.exit(2)
-        return run_gyroid_sweep(args, torch, mode)
+        return run_gyroid_sweep(args, torch, mode, cpu)
     plan, kappa, eps, g = setup(torch, max_vectors=ROOF_VECTORS)
     print(f"[bench] setup done: FCC diamond {N_GRID}, kappa {kappa.tolist()}", file=sys.stderr, flush=True)
 
@@ -360,11 +436,12 @@ def main():
             # the paper's outer / inner tolerances (1e-12, 1e-13)
             lam, sl = plan.pcx_solve_lanczos(kappa, NEV)
             return lam, {"it": sl["steps"], "it32": 0, "mv": sl["matvecs"], "mv32": 0, "pre": 0, "pre32": 0,
-                         "tm": 0.0, "s": sl["seconds"]}
+                         "tm": 0.0, "s": sl["seconds"], "res": [float(r) for r in sl["residual"]], "floor": []}
         lam, _, _, st = plan.pcx_solve(kappa, NEV, **solve_kw)
         return lam, {"it": st.iterations, "it32": st.iterations_fp32, "mv": st.matvecs, "mv32": st.matvecs_fp32,
                      "pre": st.precond_applies, "pre32": st.precond_applies_fp32, "tm": st.seconds_matvec,
-                     "s": st.seconds}
+                     "s": st.seconds, "res": [float(r) for r in st.residual],
+                     "floor": [j for j in range(NEV) if (st.floor_mask >> j) & 1]}
 
     for w in range(args.warmup):
         lam, st = one_solve()
@@ -387,10 +464,11 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     el = t1 - t0
-    # every application of the nullspace-free FFT operator: A_r, and the approximate-inverse
-    # preconditioner, which runs the same kernels with eps in place of 1/eps
+    # value: applications of A_r itself per second.  The approximate-inverse preconditioner runs the
+    # same three kernels with eps in place of 1/eps; its applications are listed under "solve" and
+    # counted only in the in-solve bandwidth figure
     applies, applies32 = matvecs + pre, matvecs32 + pre32
-    value = applies / el
+    value = matvecs / el
     n = plan.n
     per32 = sum(kernel_bytes_per_vector(n, False).values())
     per64 = sum(kernel_bytes_per_vector(n, True).values())
@@ -410,10 +488,6 @@ def main():
     traffic = load_traffic(dominant, fp64_roof)
     print(f"[bench] roofline block: {json.dumps(kern)}", file=sys.stderr, flush=True)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(eps, kappa)
-        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     out = {
         "metric": "nullspace-free matvecs/s + HBM GB/s vs peak; s per k-point, 10 bands at 64^3",
@@ -439,6 +513,8 @@ def main():
                   "fp32_application_fraction": applies32 / max(applies, 1),
                   "matvec_time_fraction": tm / el, "matvec_gbs_in_solve": solve_gbs,
                   "tol": solve_kw["tol"], "lambda": [float(x) for x in lam],
+                  "final_rel_residual_per_band": st["res"][:NEV],
+                  "bands_accepted_at_floor": st["floor"],
                   "rel_diff_vs_fp64_per_band": per_band,
                   "omega_over_2pi": [math.sqrt(max(x, 0)) / (2 * math.pi) for x in lam]},
         "block_matvec": {"vectors": ROOF_VECTORS, "precision": "fp64" if fp64_roof else "fp32",

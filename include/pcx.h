@@ -183,6 +183,12 @@ typedef struct pcx_stats {
     int restarts;                      /* PCX_MODE_FP32_REFINE: 1 if the FP64 phase stagnated with
                                           bands open and the solve was repeated in FP64 alone from
                                           the start block, else 0 */
+    unsigned long long floor_mask;     /* bit j set: band j counted as converged with a relative
+                                          residual above tol, because its absolute residual reached
+                                          the working-precision floor (1024 eps_64 ||A_r|| in FP64)
+                                          while tol * lambda_j lies four orders below that floor:
+                                          bands that go to zero next to Gamma.  Every other
+                                          converged band has residual[j] <= tol. */
 } pcx_stats;
 
 /* Smallest nev positive eigenvalues of C*C x = lambda B x at Bloch phases kappa

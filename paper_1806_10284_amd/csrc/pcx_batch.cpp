@@ -2,9 +2,10 @@
 //
 // One GEP per wave vector (Section 5.2: the band structure is a sequence of independent
 // problems, one per k), so a request of several lattices x wave vectors is a bag of independent
-// LOBPCG solves.  pcx_solve_batch runs them concurrently: each worker thread owns one HIP stream
-// and, per lattice it meets, a private clone of that lattice's plan (workspaces, mode codes and
-// a device copy of 1/eps), and takes problems from a shared counter.  The GPU then overlaps the
+// LOBPCG solves.  pcx_solve_batch runs them concurrently: each worker thread owns one HIP stream,
+// a private clone of every lattice's plan (mode codes and a device copy of 1/eps) and one set of
+// matvec and eigensolver storage shared by its clones, all created before the workers start,
+// and takes problems from a shared counter.  The GPU then overlaps the
 // kernels of different problems, and one problem's host Rayleigh-Ritz step hides behind the
 // others' device work.  All wave vectors of one lattice can also go through a single launch of
 // each A_r kernel (pcx_apply_Ar_multi).
@@ -57,12 +58,59 @@ int clone_plan(const Plan* src, hipStream_t st, Plan** out) {
     return PCX_OK;
 }
 
+// The matvec and eigensolver storage of a plan.  The plans of one worker never run at the same
+// time, so they share one set: it is moved into a plan for the duration of a solve and back out.
+struct Storage {
+    void* work = nullptr; size_t work_cap = 0;
+    void* lob_mem = nullptr; size_t lob_cap = 0;
+    void* prec = nullptr; size_t prec_cap = 0;
+    void* gram_part = nullptr; size_t gram_part_cap = 0;
+    void* small_mem = nullptr; size_t small_cap = 0;
+    void* pinned = nullptr; size_t pinned_cap = 0;
+};
+
+void swap_storage(Plan* p, Storage& s) {
+    std::swap(p->work, s.work); std::swap(p->work_cap, s.work_cap);
+    std::swap(p->lob_mem, s.lob_mem); std::swap(p->lob_cap, s.lob_cap);
+    std::swap(p->prec, s.prec); std::swap(p->prec_cap, s.prec_cap);
+    std::swap(p->gram_part, s.gram_part); std::swap(p->gram_part_cap, s.gram_part_cap);
+    std::swap(p->small_mem, s.small_mem); std::swap(p->small_cap, s.small_cap);
+    std::swap(p->pinned, s.pinned); std::swap(p->pinned_cap, s.pinned_cap);
+}
+
+// Per-worker resources, all created on the calling thread before any worker starts and released
+// there after every worker has joined and every stream has drained: no allocation or free runs
+// beside another worker's kernels.
+struct Workers {
+    std::vector<hipStream_t> streams;
+    std::vector<std::vector<Plan*>> clones;   // [worker][plan]
+    std::vector<Storage> storage;             // [worker]
+
+    ~Workers() {
+        for (hipStream_t st : streams)
+            if (st) (void)hipStreamSynchronize(st);
+        for (size_t w = 0; w < clones.size(); ++w) {
+            // hand the shared storage to one clone so that its destroy frees it
+            for (Plan* c : clones[w])
+                if (c) {
+                    swap_storage(c, storage[w]);
+                    break;
+                }
+            for (Plan* c : clones[w])
+                if (c) pcx_plan_destroy((pcx_plan*)c);
+        }
+        for (hipStream_t st : streams)
+            if (st) (void)hipStreamDestroy(st);
+    }
+};
+
 }  // namespace
 
 extern "C" int pcx_solve_batch(pcx_plan* const* plans, int nplans, const int* nk, const double* kappas, int nev,
                                const pcx_opts* opts, int nworkers, double* lambda, void* const* y_out,
                                pcx_stats* stats) {
     if (!plans || !nk || !kappas || !lambda || nplans < 1) return fail(PCX_E_ARG, "pcx_solve_batch: null pointer");
+    if (nev < 1) return fail(PCX_E_ARG, "pcx_solve_batch: nev must be >= 1");
     std::vector<int> owner;   // problem -> plan
     for (int p = 0; p < nplans; ++p) {
         const Plan* pl = (const Plan*)plans[p];
@@ -79,52 +127,63 @@ extern "C" int pcx_solve_batch(pcx_plan* const* plans, int nplans, const int* nk
         if (((const Plan*)plans[p])->device != device)
             return fail(PCX_E_ARG, "pcx_solve_batch: plan %d lives on another device", p);
     const int W = std::max(1, std::min(total, nworkers > 0 ? nworkers : 4));
+    pcx_opts o;
+    if (opts) o = *opts;
+    else pcx_opts_default(&o);
+    const bool use32 = o.mode != PCX_MODE_FP64, use64 = o.mode != PCX_MODE_FP32;
+
+    // streams, plan clones and storage for every worker, before any worker starts
+    Workers wk;
+    wk.streams.assign(W, nullptr);
+    wk.clones.assign(W, std::vector<Plan*>(nplans, nullptr));
+    wk.storage.assign(W, Storage());
+    std::vector<bool> used(nplans, false);
+    for (int p : owner) used[p] = true;
+    for (int w = 0; w < W; ++w) {
+        hipError_t e = hipStreamCreate(&wk.streams[w]);
+        if (e != hipSuccess) return hip_fail(e, "pcx_solve_batch: stream");
+        for (int p = 0; p < nplans; ++p) {
+            if (!used[p]) continue;
+            int r = clone_plan((const Plan*)plans[p], wk.streams[w], &wk.clones[w][p]);
+            if (r) return r;
+            // grow the worker's shared storage to what this plan's largest block needs
+            Plan* c = wk.clones[w][p];
+            const int bmax = std::min(solver_max_block(nev, &o), c->max_vectors);
+            swap_storage(c, wk.storage[w]);
+            r = solver_reserve(c, bmax, use32, use64);
+            if (!r) r = c->ensure_work(bmax);
+            swap_storage(c, wk.storage[w]);
+            if (r) return r;
+        }
+    }
 
     std::atomic<int> next(0);
     std::vector<int> rc(total, PCX_OK);
     std::vector<std::string> msg(total);
     std::vector<int> worker_rc(W, PCX_OK);
-    std::vector<std::string> worker_msg(W);
     auto work = [&](int w) {
         if (hipSetDevice(device) != hipSuccess) {
             worker_rc[w] = PCX_E_DEVICE;
-            worker_msg[w] = "hipSetDevice failed";
             return;
         }
-        hipStream_t st = nullptr;
-        if (hipStreamCreate(&st) != hipSuccess) {
-            worker_rc[w] = PCX_E_DEVICE;
-            worker_msg[w] = "hipStreamCreate failed";
-            return;
-        }
-        std::vector<Plan*> mine(nplans, nullptr);
         for (int q = next++; q < total; q = next++) {
-            const int p = owner[q];
-            if (!mine[p]) {
-                int r = clone_plan((const Plan*)plans[p], st, &mine[p]);
-                if (r) {
-                    rc[q] = r;
-                    msg[q] = pcx_last_error();
-                    continue;
-                }
-            }
+            Plan* c = wk.clones[w][owner[q]];
             pcx_stats local;
-            int r = pcx_solve((pcx_plan*)mine[p], kappas + 3 * q, nev, opts, lambda + (size_t)q * nev,
+            swap_storage(c, wk.storage[w]);
+            int r = pcx_solve((pcx_plan*)c, kappas + 3 * q, nev, &o, lambda + (size_t)q * nev,
                               y_out ? y_out[q] : nullptr, nullptr, stats ? &stats[q] : &local);
+            swap_storage(c, wk.storage[w]);
             rc[q] = r;
             if (r) msg[q] = pcx_last_error();
         }
-        for (Plan* c : mine)
-            if (c) pcx_plan_destroy((pcx_plan*)c);
-        (void)hipStreamSynchronize(st);
-        (void)hipStreamDestroy(st);
+        (void)hipStreamSynchronize(wk.streams[w]);
     };
     std::vector<std::thread> th;
     for (int w = 1; w < W; ++w) th.emplace_back(work, w);
     work(0);
     for (auto& t : th) t.join();
     for (int w = 0; w < W; ++w)
-        if (worker_rc[w]) return fail(worker_rc[w], "pcx_solve_batch: worker %d: %s", w, worker_msg[w].c_str());
+        if (worker_rc[w]) return fail(worker_rc[w], "pcx_solve_batch: worker %d: hipSetDevice failed", w);
     // the first hard error, else the first non-convergence
     for (int pass = 0; pass < 2; ++pass)
         for (int q = 0; q < total; ++q)

@@ -667,6 +667,24 @@ hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double s
     return hipGetLastError();
 }
 
+template <typename R>
+__global__ void k_set_units(cx<R>* __restrict__ y, UnitList u) {
+    const int c = threadIdx.x;
+    if (c < u.count) {
+        cx<R> o;
+        o.x = (R)1;
+        o.y = (R)0;
+        y[u.idx[c]] = o;
+    }
+}
+
+template <typename R>
+hipError_t launch_set_units(cx<R>* y, const UnitList& u, hipStream_t st) {
+    if (u.count < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_set_units<R>), dim3(1), dim3(PCX_MAX_BLOCK), 0, st, y, u);
+    return hipGetLastError();
+}
+
 template <typename R, int BLK, bool HERM>
 static hipError_t set_gram_lds() {
     hipError_t e = hipFuncSetAttribute((const void*)k_gram<R, BLK, HERM, 1>,
@@ -696,6 +714,8 @@ hipError_t configure_block_kernels() {
 
 template hipError_t launch_random<float>(cx<float>*, long, unsigned long long, double, hipStream_t);
 template hipError_t launch_random<double>(cx<double>*, long, unsigned long long, double, hipStream_t);
+template hipError_t launch_set_units<float>(cx<float>*, const UnitList&, hipStream_t);
+template hipError_t launch_set_units<double>(cx<double>*, const UnitList&, hipStream_t);
 template hipError_t launch_gram<float>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t,
                                        bool);
 template hipError_t launch_gram<double>(const ColSet&, const ColSet&, long, cx<double>*, int, cx<double>*, hipStream_t,

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "pcx_host.h"
@@ -173,13 +174,17 @@ static void host_twiddles(int n, std::vector<cx<double>>& out) {
     }
 }
 
+// kernel attributes (dynamic LDS limits) are set once per process, whichever thread creates the
+// first plan (batch workers may create plans concurrently)
+static std::once_flag g_config_once;
 static hipError_t g_config_status = hipErrorNotReady;
 
 static int ensure_configured() {
-    if (g_config_status == hipErrorNotReady) {
-        g_config_status = configure_kernels();
-        if (g_config_status == hipSuccess) g_config_status = configure_block_kernels();
-    }
+    std::call_once(g_config_once, [] {
+        hipError_t e = configure_kernels();
+        if (e == hipSuccess) e = configure_block_kernels();
+        g_config_status = e;
+    });
     if (g_config_status != hipSuccess) return hip_fail(g_config_status, "kernel configuration");
     return PCX_OK;
 }

@@ -94,4 +94,11 @@ struct Plan {
     int apply(int op, const double kappa[3], int precision, const void* in, void* out, int nvec);
 };
 
+// eigensolver storage of a plan for a block of b columns (pcx_solve grows it on demand; batches
+// reserve it before their worker threads start)
+int solver_reserve(Plan* p, int b, bool use32, bool use64);
+// the largest block pcx_solve picks for nev bands under these options
+int solver_max_block(int nev, const pcx_opts* o);
+int gram_chunks_for(long N);
+
 }  // namespace pcx

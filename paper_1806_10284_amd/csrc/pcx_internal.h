@@ -189,6 +189,13 @@ hipError_t launch_grad(const cx<double>* x, const double* w, int nvec, long n, d
 // seeded complex normal deviates times `scale` (counter-based: element e of stream `seed`)
 template <typename R>
 hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double scale, hipStream_t st);
+// y[idx[c]] = 1 for c < count (count <= PCX_MAX_BLOCK); the indices travel as a kernel argument
+struct UnitList {
+    long long idx[PCX_MAX_BLOCK];
+    int count;
+};
+template <typename R>
+hipError_t launch_set_units(cx<R>* y, const UnitList& u, hipStream_t st);
 hipError_t configure_block_kernels();
 
 // sizes used by the plan to reserve LDS and workspaces

@@ -98,18 +98,23 @@ struct Solver {
     // absolute residual is at the working-precision floor c eps ||A_r||: c = 1024 in FP64 (the
     // level where LOBPCG's basis stops improving next to Gamma, ~1e-13 ||A_r||), c = 1 in FP32
     // (the matvec's own rounding).  The eigenvalue error of such a band is ~ residual^2 / gap.
-    // In the FP64 phase the floor decides the final verdict, and inside the iteration only next to
-    // Gamma for bands whose tol |theta| lies four orders below it (the bands that go to zero,
-    // which cannot reach tol; point 30 of the FCC path then takes 44 iterations instead of 136):
-    // the others run on towards tol until it stops improving (kFp64Stall), so that bands which
-    // can reach tol do (accepting ordinary bands at the floor made eigenvalue differences at the
-    // 1e-9 level, the gradient check's finite differences, measurably noisier).
+    // In the FP64 phase the floor applies only to bands whose tol |theta| lies four orders below it
+    // (the bands that go to zero next to Gamma, which cannot reach tol; point 30 of the FCC path
+    // then takes 44 iterations instead of 136), inside the iteration only next to Gamma and in the
+    // final verdict everywhere: every other band must reach tol itself (at 64^3 the FP64 floor,
+    // ~1.4e-8, lies above tol |theta| ~ 1e-9 of ordinary bands, which do reach tol).  The FP32
+    // phase accepts any band at its floor (refinement follows).
+    template <typename R>
+    bool at_floor(int j, double tol) const {
+        const double floor = (sizeof(R) == 8 ? kFloor * 1.1102230246251565e-16 : 5.9604644775390625e-08) * anorm;
+        if (rabs[j] > floor) return false;
+        return sizeof(R) == 4 || tol * std::fabs(theta[j]) < 1e-4 * floor;
+    }
     template <typename R>
     bool converged(int j, double tol, bool final_verdict = false) const {
-        const double floor = (sizeof(R) == 8 ? kFloor * 1.1102230246251565e-16 : 5.9604644775390625e-08) * anorm;
         if (resid[j] <= tol) return true;
-        if (rabs[j] > floor) return false;
-        return sizeof(R) == 4 || final_verdict || (near_gamma && tol * std::fabs(theta[j]) < 1e-4 * floor);
+        if (!at_floor<R>(j, tol)) return false;
+        return sizeof(R) == 4 || final_verdict || near_gamma;
     }
 
     int sync() {
@@ -434,6 +439,48 @@ static Blocks<R> carve(void* base, int b, long N) {
 
 using namespace pcx;
 
+namespace pcx {
+
+int gram_chunks_for(long N) { return (int)std::min<long>(1024, std::max<long>(1, N / 512)); }
+
+// Grows the plan's eigensolver storage for a block of b columns: the LOBPCG blocks (ten b-column
+// blocks per precision), the Gram partial sums and residual partials, the small device area (Gram
+// output, coefficient slots, theta, residuals), the pinned host staging and Lambda_q^{-1}.
+int solver_reserve(Plan* p, int b, bool use32, bool use64) {
+    const long n = p->n, N = 2 * n;
+    const size_t bytes64 = use64 ? 10 * (size_t)b * N * sizeof(cx<double>) : 0;
+    const size_t bytes32 = use32 ? 10 * (size_t)b * N * sizeof(cx<float>) : 0;
+    int rc;
+    if ((rc = p->grow(&p->lob_mem, &p->lob_cap, bytes64 + bytes32))) return rc;
+    if ((rc = p->grow(&p->prec, &p->prec_cap, n * sizeof(double)))) return rc;
+    const int chunks = gram_chunks_for(N);
+    const size_t gp = (size_t)(chunks + 32) * (3 * b) * (6 * b) * sizeof(cx<double>);
+    const size_t rp = (size_t)chunks * b * sizeof(double);
+    if ((rc = p->grow(&p->gram_part, &p->gram_part_cap, gp + rp))) return rc;
+    const size_t gram_out = (size_t)(3 * b) * (6 * b) * sizeof(cx<double>);
+    const size_t slots = Solver::kSlots * (size_t)(3 * b) * (2 * b) * sizeof(cx<double>);
+    const size_t small = gram_out + slots + 2 * b * sizeof(double) + 1024;
+    if ((rc = p->grow(&p->small_mem, &p->small_cap, std::max<size_t>(small, 1 << 16)))) return rc;
+    const size_t pinned_bytes = slots + gram_out + 2 * b * sizeof(double);
+    if (p->pinned_cap < pinned_bytes) {
+        if (p->pinned) (void)hipHostFree(p->pinned);
+        p->pinned = nullptr;
+        p->pinned_cap = 0;
+        hipError_t e = hipHostMalloc(&p->pinned, pinned_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "pcx_solve: pinned staging");
+        p->pinned_cap = pinned_bytes;
+    }
+    return PCX_OK;
+}
+
+// The block size pcx_solve chooses for nev bands at most (the near-Gamma guard is the larger one).
+int solver_max_block(int nev, const pcx_opts* o) {
+    if (o && o->block > 0) return o->block;
+    return nev + std::max(4, (nev + 1) / 2);
+}
+
+}  // namespace pcx
+
 extern "C" void pcx_opts_default(pcx_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -514,31 +561,13 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (use64 && (rc = p->check_fits(PCX_FP64))) return rc;
     if (use32 && (rc = p->check_fits(PCX_FP32))) return rc;
 
-    // storage: FP64 blocks, then FP32 blocks
-    hipError_t e0;
+    if ((rc = solver_reserve(p, b, use32, use64))) return rc;
     const size_t bytes64 = use64 ? 10 * (size_t)b * N * sizeof(cx<double>) : 0;
-    const size_t bytes32 = use32 ? 10 * (size_t)b * N * sizeof(cx<float>) : 0;
-    if ((rc = p->grow(&p->lob_mem, &p->lob_cap, bytes64 + bytes32))) return rc;
-    if ((rc = p->grow(&p->prec, &p->prec_cap, n * sizeof(double)))) return rc;
-    S.gram_chunks = (int)std::min<long>(1024, std::max<long>(1, N / 512));
+    S.gram_chunks = gram_chunks_for(N);
     const size_t gp = (size_t)(S.gram_chunks + 32) * (3 * b) * (6 * b) * sizeof(cx<double>);
-    const size_t rp = (size_t)S.gram_chunks * b * sizeof(double);
-    if ((rc = p->grow(&p->gram_part, &p->gram_part_cap, gp + rp))) return rc;
     const size_t gram_out = (size_t)(3 * b) * (6 * b) * sizeof(cx<double>);
     S.slot_elems = (size_t)(3 * b) * (2 * b);
     const size_t slots = Solver::kSlots * S.slot_elems * sizeof(cx<double>);
-    const size_t small = gram_out + slots + 2 * b * sizeof(double) + 1024;
-    if ((rc = p->grow(&p->small_mem, &p->small_cap, std::max<size_t>(small, 1 << 16)))) return rc;
-    // pinned host memory: coefficient slots, gram results, theta, residuals
-    const size_t pinned_bytes = slots + gram_out + 2 * b * sizeof(double);
-    if (p->pinned_cap < pinned_bytes) {
-        if (p->pinned) (void)hipHostFree(p->pinned);
-        p->pinned = nullptr;
-        p->pinned_cap = 0;
-        e0 = hipHostMalloc(&p->pinned, pinned_bytes, hipHostMallocDefault);
-        if (e0 != hipSuccess) return hip_fail(e0, "pcx_solve: pinned staging");
-        p->pinned_cap = pinned_bytes;
-    }
     S.pinned = (zc*)p->pinned;
     S.host_gram = (zc*)((char*)p->pinned + slots);
     S.host_theta = (double*)((char*)p->pinned + slots + gram_out);
@@ -571,14 +600,12 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         using C = typename std::remove_pointer<decltype(X)>::type;
         hipError_t e2 = launch_random(X, (long)b * N, S.o.seed, 1e-3, p->stream);
         if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: random start");
-        for (int c = 0; c < b; ++c) {
-            const long mode = modes[(c / 2) % nm];
-            C one;
-            one.x = 1;
-            one.y = 0;
-            e2 = hipMemcpyAsync(X + (size_t)c * N + (c % 2) * n + mode, &one, sizeof(C), hipMemcpyHostToDevice, p->stream);
-            if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: start block");
-        }
+        // unit entries of the plane waves, written by a kernel (indices passed by value)
+        UnitList units;
+        units.count = b;
+        for (int c = 0; c < b; ++c) units.idx[c] = (long long)c * N + (c % 2) * n + modes[(c / 2) % nm];
+        e2 = launch_set_units(X, units, p->stream);
+        if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: start block");
         if (S.o.n_y0 > 0) {
             const long cnt = (long)S.o.n_y0 * N;
             if (std::is_same<C, cx<double>>::value)
@@ -621,7 +648,10 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         int conv = 0;
         for (int j = 0; j < nev; ++j) {
             if (j < PCX_MAX_BLOCK) S.st.residual[j] = S.resid[j];
-            if (use64 ? S.converged<double>(j, S.o.tol, true) : S.converged<float>(j, S.o.tol, true)) ++conv;
+            if (use64 ? S.converged<double>(j, S.o.tol, true) : S.converged<float>(j, S.o.tol, true)) {
+                ++conv;
+                if (S.resid[j] > S.o.tol) S.st.floor_mask |= 1ull << j;
+            }
         }
         S.st.converged = conv;
         // outputs: y (FP64), x = B^{-1} Q_r Sigma_r y

@@ -268,6 +268,21 @@ void pcx_lanczos_opts_default(pcx_lanczos_opts *o);
 int pcx_solve_lanczos(pcx_plan *p, const double kappa[3], int nev, const pcx_lanczos_opts *opts, double *lambda,
                       pcx_lanczos_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): z = A_r y exactly as pcx_apply_Ar computes it (up to
+ * rounding order: the fixed-size FP32 adjoint kernels form the mixing W per mode instead of
+ * reading the plan's table), with every temporary -- the mode codes of kappa (n bytes) and the
+ * matvec workspace (3n complex per vector in `precision`, twice that where the planes take the
+ * two-pass path) -- in a static device array of PCX_NOALLOC_SCRATCH_BYTES per device, held from
+ * library load to process end.  The call allocates nothing; the plan (created earlier, eps set)
+ * supplies the twiddle tables and 1/eps.  nvec is not bounded by max_vectors but by the scratch:
+ * a block that does not fit returns PCX_E_SIZE with the largest nvec that does (64^3: 20 vectors
+ * in FP32, 10 in FP64).  Calls on one device share the array: calls that overlap on one device
+ * (two streams, two threads) race.  The plan's device must be current.  y, z: device, nvec
+ * vectors of 2n complex, may not overlap.  Errors: PCX_E_ARG, PCX_E_SIZE, PCX_E_DEVICE. */
+#define PCX_NOALLOC_SCRATCH_BYTES (128u << 20)
+int pcx_apply_Ar_noalloc(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z, int nvec);
+
 /* Measurement hook: runs the three kernels of pcx_apply_Ar (plane forward, x-line, plane
  * adjoint) `reps` times on the plan's stream with HIP events around each launch and returns
  * their mean durations in milliseconds in ms_out[0..2].  Same arguments and effect on z as

@@ -137,6 +137,12 @@ class Plan:
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_apply_Ar, kappa, precision, y, z, 2 * self.n, 2 * self.n)
 
+    def pcx_apply_Ar_noalloc(self, kappa, y, z, precision=None):
+        """z = A_r y with every temporary in the library's static device scratch (no allocation);
+        at most PCX_NOALLOC_SCRATCH_BYTES of codes and workspace per call."""
+        precision = self._prec_of(y) if precision is None else precision
+        return self._apply(self._lib.pcx_apply_Ar_noalloc, kappa, precision, y, z, 2 * self.n, 2 * self.n)
+
     def pcx_apply_precond(self, kappa, y, z, precision=None):
         """z = D Sigma_r Q_r^* B Q_r Sigma_r D y, D = Lambda_q^{-1}: the approximate-inverse
         preconditioner of the solver (z may be y)."""

@@ -327,6 +327,10 @@ extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_str
         delete p;
         return hip_fail(e, "hipGetDevice");
     }
+    if ((rc = noalloc_setup(p->device))) {
+        delete p;
+        return rc;
+    }
     // twiddle tables
     std::vector<cx<double>> h[3];
     for (int a = 0; a < 3; ++a) host_twiddles(g->n[a], h[a]);

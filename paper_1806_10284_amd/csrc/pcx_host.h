@@ -100,5 +100,8 @@ int solver_reserve(Plan* p, int b, bool use32, bool use64);
 // the largest block pcx_solve picks for nev bands under these options
 int solver_max_block(int nev, const pcx_opts* o);
 int gram_chunks_for(long N);
+// device address of the static scratch array of pcx_apply_Ar_noalloc on `device` (current),
+// looked up once per device
+int noalloc_setup(int device);
 
 }  // namespace pcx

@@ -58,7 +58,7 @@ def kernel_bytes_per_vector(n: int, fp64: bool) -> dict:
     return {"plane_fwd": 5 * c * n, "xline": 6 * c * n + 3 * r * n, "plane_adj": 5 * c * n}
 
 
-KERNEL_SOURCES = ("pcx_fft.hip", "pcx_fixed.hip", "pcx_dev.h", "pcx_internal.h")
+KERNEL_SOURCES = ("pcx_fft.hip", "pcx_fixed.hip", "pcx_wave.hip", "pcx_dev.h", "pcx_internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -72,6 +72,7 @@ def kernel_source_hash() -> str:
 
 # kernel-name prefix in a rocprofv3 trace -> (A_r kernel, precision)
 KERNEL_KEYS = [
+    ("pcx::k_w64_fwd", "plane_fwd_fp32"), ("pcx::k_w64_adj", "plane_adj_fp32"),
     ("pcx::k_p2_fwd<float", "plane_fwd_fp32"), ("pcx::k_p2_fwd<double", "plane_fwd_fp64"),
     ("pcx::k_p2_adj<float", "plane_adj_fp32"), ("pcx::k_p2_adj<double", "plane_adj_fp64"),
     ("pcx::k_p3_fwd<float", "plane_fwd_fp32"), ("pcx::k_p3_fwd<double", "plane_fwd_fp64"),
@@ -299,10 +300,10 @@ def run_gyroid_sweep(args, torch, mode, cpu):
     def one_sweep():
         t = time.perf_counter()
         if bands:
-            bs = band_structure(plans, S.BCC, corners, NEV, parts=10, mode=mode, tol=1e-10)
+            bs = band_structure(plans, S.BCC, corners, NEV, parts=10, mode=mode, tol=1e-10, nworkers=args.workers)
             lam, st = bs.lam.reshape(-1, NEV), bs.stats
         else:
-            lam, _, st = pcx_solve_batch(problems, NEV, mode=mode, tol=1e-10)
+            lam, _, st = pcx_solve_batch(problems, NEV, mode=mode, tol=1e-10, nworkers=args.workers)
         return lam, st, time.perf_counter() - t
 
     def its(st):
@@ -348,7 +349,7 @@ def run_gyroid_sweep(args, torch, mode, cpu):
                                + ("path G-H-N-G-P-H with 10 parts per segment (51 wave vectors), "
                                   if bands else "N point, ") + "10 smallest positive eigenvalues",
                    "grid": list(N_GRID), "nev": NEV, "mode": args.mode, "solver": "lobpcg",
-                   "eps": list(S.GYROID_EPS_SWEEP), "kappa": kappa.tolist()},
+                   "eps": list(S.GYROID_EPS_SWEEP), "kappa": kappa.tolist(), "workers": args.workers or 4},
         "s_per_kpoint": el / args.steps / nprob,
         "solve": {"iterations": iters, "matvecs_per_step": matvecs / args.steps,
                   "operator_applications_per_step": applies / args.steps,
@@ -383,6 +384,8 @@ def main():
                     help="gyroid_sweep: BCC single gyroid 64^3, eps 3..30 as one batch of 10 plans at N; "
                          "gyroid_bands: the same ten plans along G-H-N-G-P-H, 10 parts per segment")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--workers", type=int, default=0,
+                    help="gyroid workloads: batch worker threads (0: the library's default, 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the 32-vector A_r block (and a calibration copy) for rocprofv3 counters")

@@ -57,7 +57,8 @@ enum { PCX_FP64 = 0, PCX_FP32 = 1 };                 /* arithmetic / storage pre
 enum { PCX_EPS_YEE3 = 0, PCX_EPS_VOXEL = 1 };        /* permittivity layouts */
 enum { PCX_MODE_FP64 = 0, PCX_MODE_FP32_REFINE = 1, PCX_MODE_FP32 = 2 };
 /* kernel variants of the A_r path */
-enum { PCX_VARIANT_AUTO = 0, PCX_VARIANT_GENERIC = 1, PCX_VARIANT_THREE_PLANE = 2, PCX_VARIANT_TWO_PLANE = 3 };
+enum { PCX_VARIANT_AUTO = 0, PCX_VARIANT_GENERIC = 1, PCX_VARIANT_THREE_PLANE = 2, PCX_VARIANT_TWO_PLANE = 3,
+       PCX_VARIANT_REGISTER = 4 };
 
 #define PCX_MAX_N 256      /* largest supported n1, n2, n3 */
 #define PCX_MAX_BLOCK 64   /* largest LOBPCG block */
@@ -103,6 +104,11 @@ int pcx_plan_set_eps(pcx_plan *p, const double *eps, int layout);
  * known at compile time; the three field components of a plane staged together
  * in LDS, or two of them with the third held in registers when three planes do
  * not fit) where the grid and precision have them, else the generic kernels.
+ * For FP32 64 x 64 planes (n1 a multiple of 8, one wave vector per launch) AUTO takes the register
+ * kernels: each 64-point line held by 8 lanes with 8 values each, both radix-8 passes on registers
+ * with a wavefront-local LDS exchange between them, one plane component in LDS at a time for the
+ * row/column exchange, W read from the plan's table, work-groups plane-major per XCD.
+ * PCX_VARIANT_REGISTER: those kernels where they apply, else as AUTO.
  * PCX_VARIANT_GENERIC: runtime-sized kernels for every grid.
  * PCX_VARIANT_THREE_PLANE / _TWO_PLANE: that fixed-size kind where compiled,
  * else the generic kernels.  All compute the same A_r (Section 5.1, Algorithms
@@ -218,10 +224,11 @@ int pcx_solve_batch(pcx_plan *const *plans, int nplans, const int *nk, const dou
 
 /* Autotuner: times one A_r application of nvec vectors at kappa in `precision` for every
  * kernel variant the plan's grid has (the three-plane and two-plane fixed-size kernels where
- * compiled for this plane shape and precision; the generic plane kernels with 256, 512 and,
- * in FP32, 1024 threads) with HIP events on the plan's stream, and keeps the fastest for the
- * plan in that precision.  choice_out (may be NULL): -1 three-plane, -2 two-plane fixed-size
- * kernels, else the generic work-group size; ms_out (may be NULL): its time per application
+ * compiled for this plane shape and precision; the register kernels for FP32 64 x 64 planes; the
+ * generic plane kernels with 256, 512 and, in FP32, 1024 threads) with HIP events on the plan's
+ * stream, and keeps the fastest for the plan in that precision.  choice_out (may be NULL): -1
+ * three-plane, -2 two-plane fixed-size kernels, -3 register kernels, else the generic work-group
+ * size; ms_out (may be NULL): its time per application
  * in ms.
  * Allocates and frees two scratch blocks.  Errors: PCX_E_ARG, PCX_E_SIZE, PCX_E_DEVICE. */
 int pcx_plan_autotune(pcx_plan *p, const double kappa[3], int precision, int nvec, int *choice_out,

@@ -12,7 +12,7 @@ PCX_FP64, PCX_FP32 = 0, 1
 PCX_EPS_YEE3, PCX_EPS_VOXEL = 0, 1
 PCX_MODE_FP64, PCX_MODE_FP32_REFINE, PCX_MODE_FP32 = 0, 1, 2
 PCX_PRECOND_NONE, PCX_PRECOND_DIAG, PCX_PRECOND_INVERSE = 0, 1, 2
-PCX_VARIANT_AUTO, PCX_VARIANT_GENERIC, PCX_VARIANT_THREE_PLANE, PCX_VARIANT_TWO_PLANE = 0, 1, 2, 3
+PCX_VARIANT_AUTO, PCX_VARIANT_GENERIC, PCX_VARIANT_THREE_PLANE, PCX_VARIANT_TWO_PLANE, PCX_VARIANT_REGISTER = 0, 1, 2, 3, 4
 PCX_MAX_N = 256
 PCX_MAX_BLOCK = 64
 

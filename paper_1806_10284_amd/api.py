@@ -107,7 +107,8 @@ class Plan:
         L.check(self._lib.pcx_plan_set_eps(self._ptr, e.ctypes.data_as(ctypes.c_void_p), int(layout)))
 
     def pcx_plan_set_variant(self, variant: int):
-        """PCX_VARIANT_AUTO (fixed-size kernels where available), _GENERIC, _THREE_PLANE or _TWO_PLANE."""
+        """PCX_VARIANT_AUTO (fixed-size kernels where available), _GENERIC, _THREE_PLANE, _TWO_PLANE or
+        _REGISTER."""
         L.check(self._lib.pcx_plan_set_variant(self._ptr, int(variant)))
 
     # -- operators

@@ -217,6 +217,8 @@ extern "C" int pcx_plan_autotune(pcx_plan* pp, const double kappa[3], int precis
     std::vector<int> cands;       // tuned_nt values: -1 fixed-size kernels, else generic group size
     if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f, 3)) cands.push_back(-1);
     if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f, 2)) cands.push_back(-2);
+    // the register kernels (FP32 64 x 64 planes, n1 a multiple of 8)
+    if (!f && p->geom.n[1] == 64 && p->geom.n[2] == 64 && p->geom.n[0] % 8 == 0) cands.push_back(-3);
     cands.push_back(256);
     cands.push_back(512);
     if (!f) cands.push_back(1024);

@@ -233,7 +233,9 @@ Grid Plan::grid(const double kappa[3]) const {
         g.plane_nt[f] = tuned_nt[f] > 0 ? tuned_nt[f] : 0;
         g.fixed_kind[f] = (tuned_nt[f] == -1 || variant == PCX_VARIANT_THREE_PLANE)
                               ? 3
-                              : ((tuned_nt[f] == -2 || variant == PCX_VARIANT_TWO_PLANE) ? 2 : 0);
+                              : ((tuned_nt[f] == -2 || variant == PCX_VARIANT_TWO_PLANE)
+                                     ? 2
+                                     : ((tuned_nt[f] == -3 || variant == PCX_VARIANT_REGISTER) ? 4 : 0));
     }
     for (int f = 0; f < 2; ++f) g.split[f] = split_plane_needed(g.n2, g.n3, f) ? 1 : 0;
     g.nvk = 0;
@@ -257,7 +259,8 @@ int Plan::grid_for(const double kappa[3], Grid* g) {
     *g = grid(kappa);
     // the FP32 W table where the fixed-size FP32 plane kernels run: the adjoint kernel then reads
     // W instead of forming it per vector
-    if (!g->generic[0] && fixed_plane_available(g->n2, g->n3, 0, g->fixed_kind[0])) {
+    const bool regs = (g->fixed_kind[0] == 0 || g->fixed_kind[0] == 4) && wave_plane_available(*g, 0);
+    if (!g->generic[0] && !regs && fixed_plane_available(g->n2, g->n3, 0, g->fixed_kind[0])) {
         if (!wtab_valid[0]) {
             if ((rc = grow(&wtab_mem, &wtab_cap, 6 * (size_t)n * sizeof(cx<float>)))) return rc;
             bool done = false;
@@ -514,7 +517,7 @@ int Plan::apply(int op, const double kappa[3], int precision, const void* in, vo
 
 extern "C" int pcx_plan_set_variant(pcx_plan* p, int variant) {
     if (!p) return fail(PCX_E_ARG, "pcx_plan_set_variant: null plan");
-    if (variant < PCX_VARIANT_AUTO || variant > PCX_VARIANT_TWO_PLANE)
+    if (variant < PCX_VARIANT_AUTO || variant > PCX_VARIANT_REGISTER)
         return fail(PCX_E_ARG, "pcx_plan_set_variant: unknown variant %d", variant);
     Plan* pl = (Plan*)p;
     pl->variant = variant;

@@ -29,8 +29,9 @@ struct Grid {
     // per precision [0] FP32, [1] FP64:
     int generic[2];          // 1: runtime-sized kernels only; 0: fixed-size kernels where they exist
     int plane_nt[2];         // generic plane kernels' work-group size: 0 automatic, 256 / 512 / 1024
-    int fixed_kind[2];       // fixed-size plane kernels: 0 three-plane where compiled else two-plane,
-                             // 3 three-plane only, 2 two-plane only
+    int fixed_kind[2];       // fixed-size plane kernels: 0 automatic (register kernels where they
+                             // apply, else three-plane or two-plane), 3 three-plane only, 2 two-plane
+                             // only, 4 register kernels where they apply
     int split[2];            // 1: plane too large for LDS, two passes through a second 3n-per-vector
                              //    workspace that follows the first one
     // several wave vectors in one launch: vectors are ordered [k][v] with nvk vectors per wave
@@ -108,6 +109,13 @@ bool fixed_plane_available(int n2, int n3, int fp64, int kind = 0);
 template <typename R>
 hipError_t launch_wtable(const Grid& g, const DeviceTables& tb, cx<R>* out, hipStream_t st, bool* done);
 bool fixed_xline_available(int n1, long np, int fp64);
+// register-resident plane kernels (pcx_wave.hip): FP32 64 x 64 planes, n1 % 8 == 0, one wave vector,
+// the FP32 W table present
+bool wave_plane_available(const Grid& g, int fp64);
+hipError_t launch_wave_plane_fwd(const Grid& g, const DeviceTables& tb, const cx<float>* y, cx<float>* t, int nvec,
+                                 hipStream_t st);
+hipError_t launch_wave_plane_adj(const Grid& g, const DeviceTables& tb, const cx<float>* t, cx<float>* z, int nvec,
+                                 hipStream_t st);
 hipError_t configure_fixed_kernels();
 
 // ---- block operations (pcx_block.hip) ----

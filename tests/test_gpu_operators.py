@@ -27,7 +27,7 @@ def say(*a):
     print("[gpu-case]", *a, file=sys.stderr, flush=True)
 
 
-VARIANTS = {"auto": 0, "generic": 1, "three_plane": 2, "two_plane": 3}
+VARIANTS = {"auto": 0, "generic": 1, "three_plane": 2, "two_plane": 3, "register": 4}
 
 
 def _setup(avec, n, kappa, eps, nvec=1, seed=0, variant="auto"):
@@ -149,7 +149,7 @@ def test_QS_and_adjoint_and_eigvec(name, avec, n, kappa, prec):
         _cmp(z[:, v], QS_adjoint(spec, ur[:, v]), prec, "QS_adjoint")
 
 
-@pytest.mark.parametrize("variant", ["auto", "generic", "two_plane"])
+@pytest.mark.parametrize("variant", ["auto", "generic", "two_plane", "three_plane", "register"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_apply_Ar_fcc64_full_size(prec, variant):
     """The 64^3 diamond workload: every output entry against the oracle (numpy FFT route)."""
@@ -164,6 +164,42 @@ def test_apply_Ar_fcc64_full_size(prec, variant):
     plan.pcx_apply_Ar(kappa, _to_dev(y, prec), z)
     torch.cuda.synchronize()
     _cmp(z.cpu().numpy().T[:, 0], Ar_apply(spec, eps, y[:, 0]), prec, "fcc64")
+
+
+@pytest.mark.parametrize("case", ["fcc_X", "fcc_generic", "fcc_gamma", "bcc_16", "tri_24"])
+def test_register_plane_kernels_64(case):
+    """The register-resident FP32 kernels for 64 x 64 planes (8 lanes x 8 values per line, plane-major
+    block order per XCD, W from the plan's table) on a 5-vector block: A_r, Q_r Sigma_r and its
+    adjoint against the oracle for every vector, also at Gamma (masked mode) and for n1 = 16 and 24
+    (two and three planes per XCD)."""
+    import torch
+    avec, n, kappa = {
+        "fcc_X": (S.FCC, (64, 64, 64), (0.5, 0.0, 0.5)),
+        "fcc_generic": (S.FCC, (64, 64, 64), (0.13, -0.41, 0.27)),
+        "fcc_gamma": (S.FCC, (64, 64, 64), (0.0, 0.0, 0.0)),
+        "bcc_16": (S.BCC, (16, 64, 64), (0.31, 0.07, -0.22)),
+        "tri_24": (S.triclinic(5), (24, 64, 64), (-0.17, 0.38, 0.44)),
+    }[case]
+    og = lattice_geometry(avec, *n)
+    rng = np.random.default_rng(19)
+    eps = rng.uniform(1.0, 13.0, (3, og.npts))
+    nv = 5
+    plan, og, spec, y = _setup(avec, n, kappa, eps, nvec=nv, seed=21, variant="register")
+    say("register planes", case)
+    yd = _to_dev(y, "fp32")
+    z = torch.empty_like(yd)
+    plan.pcx_apply_Ar(kappa, yd, z)
+    u = torch.empty((nv, 3 * og.npts), dtype=yd.dtype, device="cuda")
+    plan.pcx_apply_QS(kappa, yd, u)
+    ur = S.random_block(22, 3 * og.npts, nv)
+    zq = torch.empty_like(yd)
+    plan.pcx_apply_QS_adjoint(kappa, _to_dev(ur, "fp32"), zq)
+    torch.cuda.synchronize()
+    z, u, zq = z.cpu().numpy().T, u.cpu().numpy().T, zq.cpu().numpy().T
+    for v in range(nv):
+        _cmp(z[:, v], Ar_apply(spec, eps, y[:, v]), "fp32", f"A_r vector {v}")
+        _cmp(u[:, v], QS_apply(spec, y[:, v]), "fp32", f"QS vector {v}")
+        _cmp(zq[:, v], QS_adjoint(spec, ur[:, v]), "fp32", f"QS adjoint vector {v}")
 
 
 def test_nfsep_identity_with_explicit_curl_fcc64():

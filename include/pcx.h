@@ -83,6 +83,14 @@ int pcx_geometry(const double avec[9], int n1, int n2, int n3, pcx_geom *out);
 /* kappa_l = kvec . a~_l / (2 pi), kvec = the Bloch vector 2 pi k (Section 1.2). Host. */
 int pcx_kappa_from_bloch(const double avec[9], const double kvec[3], double kappa[3]);
 
+/* Section 2.3: Omega = [a1 a2 a3]^{-T} [a~1 a~2 a~3]^T, the map from the user's reciprocal
+ * frame to that of the rotated, angle-corrected vectors of g (as computed by pcx_geometry from
+ * the same avec): a Bloch vector 2 pi k of the user's frame (for example a Brillouin-zone corner
+ * point) becomes Omega (2 pi k), and (Omega k) . a_l = k . a~_l, so the phases kappa_l are the
+ * same in both frames.  Omega is a rotation when no angle needed correcting.  omega: row-major
+ * 3x3.  Pure host computation.  Errors: PCX_E_ARG (null pointer), PCX_E_LATTICE (singular). */
+int pcx_omega(const double avec[9], const pcx_geom *g, double omega[9]);
+
 typedef struct pcx_plan pcx_plan;
 
 /* Creates a plan for one grid/lattice.  max_vectors bounds nvec in the apply

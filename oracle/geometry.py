@@ -156,6 +156,15 @@ def kappa_from_bloch(avec, kvec) -> np.ndarray:
     return out
 
 
+def omega_matrix(avec, geom: Geometry) -> np.ndarray:
+    """Section 2.3: Omega = [a1 a2 a3]^{-T} [a~1 a~2 a~3]^T, written as the defining product
+    (B B~^{-1} with B = 2 pi [a]^{-T}, B~ = 2 pi [a~]^{-T}), so that the reciprocal vectors of the
+    corrected lattice are Omega times those of the user's lattice."""
+    B_new = 2.0 * math.pi * np.linalg.inv(np.asarray(geom.avec_rot, dtype=np.float64)).T
+    B_old = 2.0 * math.pi * np.linalg.inv(np.asarray(avec, dtype=np.float64)).T
+    return B_new @ np.linalg.inv(B_old)
+
+
 def lattice_rows_grid_units(geom: Geometry) -> np.ndarray:
     """The corrected lattice vectors in grid units, as rows:
     L1 = (n1, 0, 0), L2 = (s1, n2, 0), L3 = (s2, s3, n3)."""

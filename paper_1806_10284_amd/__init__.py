@@ -6,10 +6,10 @@ and the current stream.  Build with ``python -m paper_1806_10284_amd.build``.
 """
 from ._lib import (PCX_EPS_VOXEL, PCX_EPS_YEE3, PCX_FP32, PCX_FP64, PCX_MODE_FP32, PCX_MODE_FP32_REFINE,
                    PCX_MODE_FP64, PCX_PRECOND_DIAG, PCX_PRECOND_INVERSE, PCX_PRECOND_NONE, PcxError)
-from .api import Plan, geom_dict, pcx_geometry, pcx_kappa_from_bloch, pcx_solve_batch
+from .api import Plan, geom_dict, pcx_geometry, pcx_kappa_from_bloch, pcx_omega, pcx_solve_batch
 
 __all__ = [
-    "Plan", "pcx_geometry", "pcx_kappa_from_bloch", "pcx_solve_batch", "geom_dict", "PcxError",
+    "Plan", "pcx_geometry", "pcx_kappa_from_bloch", "pcx_omega", "pcx_solve_batch", "geom_dict", "PcxError",
     "PCX_FP32", "PCX_FP64", "PCX_EPS_YEE3", "PCX_EPS_VOXEL",
     "PCX_MODE_FP64", "PCX_MODE_FP32_REFINE", "PCX_MODE_FP32",
     "PCX_PRECOND_NONE", "PCX_PRECOND_DIAG", "PCX_PRECOND_INVERSE",

@@ -84,6 +84,7 @@ _SIGS = [
                                           ctypes.c_void_p, ctypes.POINTER(PcxLanczosStats)]),
     ("pcx_apply_precond", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int]),
+    ("pcx_omega", ctypes.c_int, [c_double9, ctypes.POINTER(PcxGeom), c_double9]),
     ("pcx_apply_Ar_noalloc", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_int]),
     ("pcx_apply_Ar_multi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,

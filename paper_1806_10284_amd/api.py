@@ -33,6 +33,15 @@ def pcx_kappa_from_bloch(avec, kvec) -> np.ndarray:
     return np.array(list(out))
 
 
+def pcx_omega(avec, geom: L.PcxGeom) -> np.ndarray:
+    """Section 2.3: Omega (3x3) mapping user-frame Bloch vectors to the frame of the rotated,
+    corrected lattice of ``geom`` (from pcx_geometry with the same ``avec``)."""
+    lib = L.load()
+    out = L.c_double9()
+    L.check(lib.pcx_omega(_avec9(avec), ctypes.byref(geom), out))
+    return np.array(list(out)).reshape(3, 3)
+
+
 def geom_dict(g: L.PcxGeom) -> dict:
     return {"n": tuple(g.n), "m": tuple(g.m), "rho": tuple(g.rho), "shift": tuple(g.shift),
             "delta": tuple(g.delta), "avec_rot": np.array(list(g.avec_rot)).reshape(3, 3),

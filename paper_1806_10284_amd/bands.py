@@ -16,7 +16,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib as L
-from .api import pcx_kappa_from_bloch, pcx_solve_batch
+from .api import pcx_kappa_from_bloch, pcx_omega, pcx_solve_batch
 
 
 def kpath(corners, parts: int = 10):
@@ -54,11 +54,13 @@ class BandStructure:
 
 
 def band_structure(plans, avecs, corners, nev: int = 10, parts: int = 10, *, mode=L.PCX_MODE_FP32_REFINE,
-                   tol: float = 1e-9, nworkers: int = 0, **solve_kw) -> BandStructure:
+                   tol: float = 1e-9, nworkers: int = 0, warm_start: bool = False, **solve_kw) -> BandStructure:
     """The ``nev`` smallest positive eigenvalues at every point of ``kpath(corners, parts)`` for each
     plan (its permittivity already set).  ``avecs``: the lattice vectors (columns) of each plan, or
     one 3x3 array shared by all; the Bloch vectors are mapped to each plan's phases with
-    ``pcx_kappa_from_bloch``.  All problems are solved as one batch."""
+    ``pcx_kappa_from_bloch``.  By default all problems are solved as one batch; with
+    ``warm_start`` each plan's path is walked point by point, every solve starting from the
+    previous point's eigenvectors (neighbouring wave vectors have nearby eigenspaces)."""
     plans = list(plans)
     if not plans:
         raise ValueError("no plans")
@@ -68,6 +70,23 @@ def band_structure(plans, avecs, corners, nev: int = 10, parts: int = 10, *, mod
         raise ValueError("one lattice per plan, or one for all")
     kvecs, arc = kpath(corners, parts)
     kappas = np.array([[pcx_kappa_from_bloch(a, k) for k in kvecs] for a in avs])
+    if warm_start:
+        lam = np.zeros((len(plans), len(kvecs), nev))
+        stats = []
+        for q, (p, kap) in enumerate(zip(plans, kappas)):
+            y = None
+            for t, k in enumerate(kap):
+                lam[q, t], y, _, st = p.pcx_solve(tuple(k), nev, mode=mode, tol=tol, want_y=True, y0=y, **solve_kw)
+                stats.append(st)
+        return BandStructure(kvecs, arc, kappas, lam, stats)
     problems = [(p, [tuple(k) for k in kap]) for p, kap in zip(plans, kappas)]
     lam, _, stats = pcx_solve_batch(problems, nev, mode=mode, tol=tol, nworkers=nworkers, **solve_kw)
     return BandStructure(kvecs, arc, kappas, lam.reshape(len(plans), len(kvecs), nev), stats)
+
+
+def rotated_bloch_vectors(avec, geom, kvecs) -> np.ndarray:
+    """Section 2.3: the Bloch vectors ``kvecs`` (user frame, rows) in the frame of the rotated,
+    angle-corrected lattice ``geom``, Omega k; their phases with the corrected vectors equal
+    those of ``kvecs`` with the user's vectors."""
+    om = pcx_omega(avec, geom)
+    return np.asarray(kvecs, dtype=np.float64).reshape(-1, 3) @ om.T

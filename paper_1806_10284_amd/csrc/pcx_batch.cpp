@@ -149,6 +149,7 @@ extern "C" int pcx_solve_batch(pcx_plan* const* plans, int nplans, const int* nk
             // grow the worker's shared storage to what this plan's largest block needs
             Plan* c = wk.clones[w][p];
             const int bmax = std::min(solver_max_block(nev, &o), c->max_vectors);
+            c->block_cap = bmax;
             swap_storage(c, wk.storage[w]);
             r = solver_reserve(c, bmax, use32, use64);
             if (!r) r = c->ensure_work(bmax);

@@ -149,6 +149,29 @@ extern "C" int pcx_geometry(const double avec[9], int n1, int n2, int n3, pcx_ge
     return PCX_OK;
 }
 
+extern "C" int pcx_omega(const double avec[9], const pcx_geom* g, double omega[9]) {
+    if (!avec || !g || !omega) return fail(PCX_E_ARG, "pcx_omega: null pointer");
+    // [a]^{-T} = cof(A) / det(A) for A = g->avec_rot (row-major, columns the corrected vectors)
+    const double* A = g->avec_rot;
+    auto at = [&](int r, int c) { return A[3 * r + c]; };
+    double cof[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            cof[3 * r + c] = at(r1, c1) * at(r2, c2) - at(r1, c2) * at(r2, c1);
+        }
+    const double det = at(0, 0) * cof[0] + at(0, 1) * cof[1] + at(0, 2) * cof[2];
+    if (!(std::fabs(det) > 0) || !std::isfinite(det)) return fail(PCX_E_LATTICE, "pcx_omega: singular lattice");
+    // Omega[r][c] = sum_m [a]^{-T}[r][m] [a~]^T[m][c] = sum_m cof[r][m] avec[c][m] / det
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m) s += cof[3 * r + m] * avec[3 * c + m];
+            omega[3 * r + c] = s / det;
+        }
+    return PCX_OK;
+}
+
 extern "C" int pcx_kappa_from_bloch(const double avec[9], const double kvec[3], double kappa[3]) {
     if (!avec || !kvec || !kappa) return fail(PCX_E_ARG, "pcx_kappa_from_bloch: null pointer");
     for (int l = 0; l < 3; ++l) {

@@ -67,6 +67,10 @@ struct Plan {
     size_t wtab_cap = 0;
     bool wtab_valid[2] = {false, false};
 
+    // largest automatic LOBPCG block pcx_solve may pick for this plan (0: max_vectors); a batch sets
+    // it to the storage it reserved before its workers started
+    int block_cap = 0;
+
     // kernel variant of the A_r path (PCX_VARIANT_*)
     int variant = PCX_VARIANT_AUTO;
     // autotuned choice per precision ([0] FP32, [1] FP64): 0 untuned, -1 / -2 the three- / two-

@@ -59,3 +59,62 @@ def test_band_structure_argument_checks():
         band_structure([], S.SC, corners)
     with pytest.raises(ValueError):
         band_structure([object(), object(), object()], [S.SC, S.FCC], corners)
+
+
+@pytest.mark.parametrize("name", list(__import__("pcx_synth.bravais", fromlist=["x"]).BRAVAIS_NAMES))
+def test_bravais_corner_points_lie_on_the_brillouin_zone_boundary(name):
+    """All 14 Bravais lattices: every tabulated corner point k != Gamma is exactly as far from some
+    nonzero reciprocal lattice vector as from Gamma and no closer to any (the boundary of the first
+    Brillouin zone).  A wrong coefficient in a shape-dependent point (eta, zeta, psi, ...) moves the
+    point off the boundary."""
+    from pcx_synth.bravais import bravais
+    avec, pts, path = bravais(name)
+    assert set(path) <= set(pts) and "G" in pts
+    B = 2 * np.pi * np.linalg.inv(avec)
+    rng = np.arange(-3, 4)
+    G = np.array([i * B[0] + j * B[1] + k * B[2] for i in rng for j in rng for k in rng
+                  if (i, j, k) != (0, 0, 0)])
+    for lab, k in pts.items():
+        if lab == "G":
+            assert np.all(k == 0)
+            continue
+        d = np.linalg.norm(k - G, axis=1)
+        assert d.min() == pytest.approx(np.linalg.norm(k), rel=1e-12), (name, lab)
+
+
+@pytest.mark.parametrize("name", list(__import__("pcx_synth.bravais", fromlist=["x"]).BRAVAIS_NAMES))
+def test_omega_map_keeps_the_phases(name):
+    """Section 2.3's Omega (C library) equals the oracle's reciprocal-frame product B B~^{-1}; a corner
+    point mapped by Omega has the same phases with the corrected vectors as the original point
+    with the user's vectors; Omega is a rotation when no angle was corrected."""
+    from oracle.geometry import kappa_from_bloch, lattice_geometry, omega_matrix
+    from paper_1806_10284_amd import pcx_geometry, pcx_omega
+    from pcx_synth.bravais import bravais
+    avec, pts, _ = bravais(name)
+    for n in [(6, 6, 6), (64, 64, 64)]:
+        g = pcx_geometry(avec, *n)
+        og = lattice_geometry(avec, *n)
+        om = pcx_omega(avec, g)
+        np.testing.assert_allclose(om, omega_matrix(avec, og), rtol=1e-12, atol=1e-13)
+        rot = np.array(list(g.avec_rot)).reshape(3, 3)
+        for lab, k in pts.items():
+            kap_user = kappa_from_bloch(avec, k)
+            kap_rot = (om @ k) @ rot / (2 * np.pi)
+            np.testing.assert_allclose(kap_rot, kap_user, atol=1e-12)
+        user_cos = [avec[:, a] @ avec[:, b] / np.linalg.norm(avec[:, a]) / np.linalg.norm(avec[:, b])
+                    for a, b in ((0, 1), (0, 2), (1, 2))]
+        if np.allclose(user_cos, g.cos_angles, atol=1e-14) and np.allclose(
+                [np.linalg.norm(avec[:, l]) for l in range(3)], np.linalg.norm(rot, axis=0), rtol=1e-14):
+            np.testing.assert_allclose(om.T @ om, np.eye(3), atol=1e-12)
+            assert np.linalg.det(om) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_omega_of_the_corrected_fcc_lattice():
+    """FCC at 64^3 needs its third angle corrected (m3 = 21.33 -> 21): Omega is then not a rotation,
+    but the X point keeps its phases (1/2, 0, 1/2)."""
+    from paper_1806_10284_amd import pcx_geometry, pcx_omega
+    g = pcx_geometry(S.FCC, 64, 64, 64)
+    om = pcx_omega(S.FCC, g)
+    assert np.abs(om.T @ om - np.eye(3)).max() > 1e-4
+    rot = np.array(list(g.avec_rot)).reshape(3, 3)
+    np.testing.assert_allclose((om @ S.FCC_POINTS["X"]) @ rot / (2 * np.pi), [0.5, 0.0, 0.5], atol=1e-12)

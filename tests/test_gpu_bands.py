@@ -102,3 +102,59 @@ def test_band_structure_over_two_lattices():
         for t, kap in enumerate(bs.kappas[q]):
             ref = _vacuum_positive(og, kap, nev)
             np.testing.assert_allclose(bs.lam[q, t], ref, rtol=1e-9)
+
+
+def test_vacuum_band_structures_of_all_14_bravais_lattices():
+    """Every Bravais lattice of the corner-point tables, 6^3 grid, vacuum, along its default path
+    (2 parts per segment), all lattices and points in one batch: every eigenvalue equals the
+    closed-form Lambda_q (each twice) at that point's phases, 1e-9 relative."""
+    from paper_1806_10284_amd import Plan, pcx_geometry, pcx_solve_batch
+    from paper_1806_10284_amd.bands import kpath
+    from paper_1806_10284_amd.api import pcx_kappa_from_bloch
+    from pcx_synth.bravais import BRAVAIS_NAMES, bravais
+    nev, n = 8, (6, 6, 6)
+    problems, geoms = [], []
+    for name in BRAVAIS_NAMES:
+        avec, pts, path = bravais(name)
+        og = lattice_geometry(avec, *n)
+        plan = Plan(pcx_geometry(avec, *n), max_vectors=32)
+        plan.pcx_plan_set_eps(np.ones((3, og.npts)))
+        kv, _ = kpath([pts[c] for c in path], 2)
+        problems.append((plan, [tuple(pcx_kappa_from_bloch(avec, k)) for k in kv]))
+        geoms.append((name, og))
+    total = sum(len(k) for _, k in problems)
+    say("vacuum band structures of the 14 lattices:", total, "problems")
+    lam, _, stats = pcx_solve_batch(problems, nev, tol=1e-10)
+    assert all(s.converged == nev for s in stats)
+    q = 0
+    for (plan, ks), (name, og) in zip(problems, geoms):
+        for kap in ks:
+            ref = _vacuum_positive(og, kap, nev)
+            err = np.abs(lam[q] - ref) / ref
+            assert err.max() <= 1e-9, (name, kap, err)
+            q += 1
+
+
+def test_warm_started_path_equals_the_batch():
+    """Walking the path point by point from the previous point's eigenvectors (warm start) gives the
+    batch's eigenvalues (1e-10) in fewer iterations: SC 12^3 sphere along Gamma-X-M-Gamma-R."""
+    from paper_1806_10284_amd import Plan, pcx_geometry
+    from paper_1806_10284_amd.bands import band_structure
+    from pcx_synth.bravais import bravais
+    avec, pts, _ = bravais("CUB")
+    n = (12, 12, 12)
+    g = pcx_geometry(avec, *n)
+    eps = S.sample_yee(avec, n, tuple(g.shift), S.sc_sphere_shapes(), 13.0, 1.0)
+    plan = Plan(g, max_vectors=32)
+    plan.pcx_plan_set_eps(eps)
+    corners = [pts[c] for c in "GXMGR"]
+    say("warm-started SC 12^3 path")
+    cold = band_structure([plan], avec, corners, 8, parts=5, mode=0, tol=1e-10)
+    warm = band_structure([plan], avec, corners, 8, parts=5, mode=0, tol=1e-10, warm_start=True)
+    lq = np.sum(np.abs(spectrum(lattice_geometry(avec, *n), (0.3, 0.2, 0.1)).lam) ** 2, axis=0).max()
+    atol = 1e-13 * lq
+    assert np.all(np.abs(warm.lam - cold.lam) <= 1e-10 * cold.lam + atol)
+    it_cold = sum(s.iterations for s in cold.stats)
+    it_warm = sum(s.iterations for s in warm.stats)
+    say("warm start: iterations", it_warm, "against", it_cold)
+    assert it_warm < it_cold

@@ -94,9 +94,10 @@ def test_gyroid_sweep_64_properties():
 
 def test_gyroid_next_to_gamma_high_contrast():
     """eps = 30, the path point one tenth of the way from Gamma towards N (two bands near zero): the
-    FP32+refine solve converges (its FP64 phase may stagnate here and the solve is then repeated in
-    FP64 alone from the start block) and equals
-    the plain FP64 solve to 1e-10 plus the Rayleigh-quotient rounding bound of the near-zero bands."""
+    FP32+refine solve converges without repeating itself in FP64 (with an odd near-Gamma block of 15
+    its FP64 phase stagnated here: the block edge separated the two polarisations of a plane wave)
+    and equals the plain FP64 solve to 1e-10 plus the Rayleigh-quotient rounding bound of the
+    near-zero bands."""
     from paper_1806_10284_amd import PCX_MODE_FP32_REFINE, PCX_MODE_FP64, pcx_kappa_from_bloch
     n, nev = (64, 64, 64), 10
     og = lattice_geometry(S.BCC, *n)
@@ -107,6 +108,7 @@ def test_gyroid_next_to_gamma_high_contrast():
     say(f"refine: {st.iterations} iterations ({st.iterations_fp32} FP32), restarts {st.restarts}")
     ref, _, _, st64 = plans[0].pcx_solve(kappa, nev, mode=PCX_MODE_FP64, tol=1e-10, want_y=False)
     say(f"fp64: {st64.iterations} iterations, restarts {st64.restarts}")
+    assert st.restarts == 0
     assert ref[0] < 1e-2 * ref[2]
     lq_max = np.sum(np.abs(spectrum(og, kappa).lam) ** 2, axis=0).max()
     atol = 1e-13 * lq_max / epss[0].min()

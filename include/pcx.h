@@ -298,6 +298,26 @@ int pcx_solve_lanczos(pcx_plan *p, const double kappa[3], int nev, const pcx_lan
 #define PCX_NOALLOC_SCRATCH_BYTES (128u << 20)
 int pcx_apply_Ar_noalloc(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z, int nvec);
 
+/* The magnetic-field side of the SVD C = P_r Sigma_r Q_r^* (Section 5.1, eq. SVD, Theorem 5.1):
+ *
+ * pcx_apply_curl: v = C u (adjoint = 0) or v = C^* u (adjoint != 0), the discrete curl of Section 3
+ *   as real-space forward (backward) differences with the quasi-periodic wraps of Section 1.2
+ *   (C = [[0, -C3, C2], [C3, 0, -C1], [-C2, C1, 0]]).  u, v: device, nvec vectors of 3n complex in
+ *   the e-layout; they may not overlap.
+ * pcx_hfield: h = P_r y = C Q_r Sigma_r^{-1} y (2n -> 3n): for an NFSEP eigenvector y the
+ *   magnetic-field eigenvector of C B^{-1} C^* h = lambda h (same lambda; ||h|| = ||y||), since
+ *   P_r^* (C B^{-1} C^*) P_r = A_r.  At kappa in Z^3 the one mode with Lambda_q = 0 has no range
+ *   (the Gamma-point SVD: n + 2 zero singular values) and contributes nothing.  y, h: device.
+ * pcx_apply_hfield_operator: z = C B^{-1} C^* h (3n -> 3n), the magnetic-field operator.
+ *
+ * All three use a plan workspace of 5n complex per vector (allocated on growth).  Errors:
+ * PCX_E_ARG (null pointer, nvec outside [1, max_vectors], eps not set for the operator),
+ * PCX_E_DEVICE. */
+int pcx_apply_curl(pcx_plan *p, const double kappa[3], int precision, const void *u, void *v, int nvec,
+                   int adjoint);
+int pcx_hfield(pcx_plan *p, const double kappa[3], int precision, const void *y, void *h, int nvec);
+int pcx_apply_hfield_operator(pcx_plan *p, const double kappa[3], int precision, const void *h, void *z, int nvec);
+
 /* Measurement hook: runs the three kernels of pcx_apply_Ar (plane forward, x-line, plane
  * adjoint) `reps` times on the plan's stream with HIP events around each launch and returns
  * their mean durations in milliseconds in ms_out[0..2].  Same arguments and effect on z as

@@ -109,6 +109,42 @@ def QS_adjoint(spec: Spectrum, u: np.ndarray) -> np.ndarray:
     return np.concatenate([z1.reshape(-1), z2.reshape(-1)])
 
 
+def hfield_mixing(lam: np.ndarray) -> np.ndarray:
+    """V per mode (3, 2, ...): the columns Lambda x W[:, c] / Lambda_q.
+
+    The curl acts per mode as the cross product with Lambda, so C Q_r Sigma_r = (I_3 (x) T)(Lambda x W)
+    and, from C = P_r Sigma_r Q_r^* (Theorem 5.1), P_r = C Q_r Sigma_r^{-1} = (I_3 (x) T) V with
+    V = (Lambda x W) / Lambda_q: the left singular vectors that belong to this package's Q_r (the
+    paper's P_r = [P_2, P_1] for its own basis).  Zero on the masked mode."""
+    W = mixing(lam)
+    Lq = np.sum(np.abs(lam) ** 2, axis=0)
+    inv = np.where(Lq > 0, 1.0 / np.where(Lq > 0, Lq, 1.0), 0.0)
+    V = np.zeros_like(W)
+    for c in range(2):
+        w = W[:, c]
+        V[0, c] = (lam[1] * w[2] - lam[2] * w[1]) * inv
+        V[1, c] = (lam[2] * w[0] - lam[0] * w[2]) * inv
+        V[2, c] = (lam[0] * w[1] - lam[1] * w[0]) * inv
+    return V
+
+
+def P_apply(spec: Spectrum, y: np.ndarray) -> np.ndarray:
+    """h = P_r y = (I_3 (x) T)(V y): 2n -> 3n, the magnetic field of an NFSEP vector."""
+    V = hfield_mixing(spec.lam)
+    y1, y2 = split_y(spec, y)
+    return np.concatenate([T_apply(spec, V[l, 0] * y1 + V[l, 1] * y2) for l in range(3)])
+
+
+def P_adjoint(spec: Spectrum, h: np.ndarray) -> np.ndarray:
+    """P_r^* h = V^H (I_3 (x) T^*) h: 3n -> 2n."""
+    n = spec.npts
+    V = hfield_mixing(spec.lam)
+    v = [Tstar_apply(spec, h[l * n:(l + 1) * n]) for l in range(3)]
+    z1 = sum(np.conj(V[l, 0]) * v[l] for l in range(3))
+    z2 = sum(np.conj(V[l, 1]) * v[l] for l in range(3))
+    return np.concatenate([z1.reshape(-1), z2.reshape(-1)])
+
+
 def Ar_apply(spec: Spectrum, eps_yee: np.ndarray, y: np.ndarray) -> np.ndarray:
     """A_r y (eq. NFSEP) with B = diag(eps_yee) (eps_yee shape (3, n))."""
     u = QS_apply(spec, y)

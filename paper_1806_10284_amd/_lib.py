@@ -84,6 +84,12 @@ _SIGS = [
                                           ctypes.c_void_p, ctypes.POINTER(PcxLanczosStats)]),
     ("pcx_apply_precond", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int]),
+    ("pcx_apply_curl", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_int]),
+    ("pcx_hfield", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int]),
+    ("pcx_apply_hfield_operator", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_int]),
     ("pcx_omega", ctypes.c_int, [c_double9, ctypes.POINTER(PcxGeom), c_double9]),
     ("pcx_apply_Ar_noalloc", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_int]),

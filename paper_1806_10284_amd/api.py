@@ -147,6 +147,26 @@ class Plan:
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_apply_Ar, kappa, precision, y, z, 2 * self.n, 2 * self.n)
 
+    def pcx_apply_curl(self, kappa, u, v, adjoint: bool = False, precision=None):
+        """v = C u (or C^* u): the discrete curl on 3n-vectors (e-layout)."""
+        precision = self._prec_of(u) if precision is None else precision
+        nv = self._check_block(u, 3 * self.n, precision, "u")
+        if self._check_block(v, 3 * self.n, precision, "v") != nv:
+            raise ValueError("u and v hold different numbers of vectors")
+        L.check(self._lib.pcx_apply_curl(self._ptr, _kappa3(kappa), int(precision), ctypes.c_void_p(u.data_ptr()),
+                                         ctypes.c_void_p(v.data_ptr()), nv, int(bool(adjoint))))
+        return v
+
+    def pcx_hfield(self, kappa, y, h, precision=None):
+        """h = P_r y = C Q_r Sigma_r^{-1} y: the magnetic field of an NFSEP vector (2n -> 3n)."""
+        precision = self._prec_of(y) if precision is None else precision
+        return self._apply(self._lib.pcx_hfield, kappa, precision, y, h, 2 * self.n, 3 * self.n)
+
+    def pcx_apply_hfield_operator(self, kappa, h, z, precision=None):
+        """z = C B^{-1} C^* h (3n -> 3n)."""
+        precision = self._prec_of(h) if precision is None else precision
+        return self._apply(self._lib.pcx_apply_hfield_operator, kappa, precision, h, z, 3 * self.n, 3 * self.n)
+
     def pcx_apply_Ar_noalloc(self, kappa, y, z, precision=None):
         """z = A_r y with every temporary in the library's static device scratch (no allocation);
         at most PCX_NOALLOC_SCRATCH_BYTES of codes and workspace per call."""

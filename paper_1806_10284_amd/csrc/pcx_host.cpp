@@ -421,8 +421,8 @@ extern "C" int pcx_plan_create(const pcx_geom* g, int max_vectors, void* hip_str
 extern "C" void pcx_plan_destroy(pcx_plan* pp) {
     Plan* p = (Plan*)pp;
     if (!p) return;
-    void* bufs[] = {p->tables_mem, p->eps_mem, p->work,   p->lob_mem,  p->prec,    p->gram_part,
-                    p->small_mem,  p->codes,   p->mcodes, p->kaps_dev, p->wtab_mem};
+    void* bufs[] = {p->tables_mem, p->eps_mem, p->work,   p->lob_mem,  p->prec,     p->gram_part,
+                    p->small_mem,  p->codes,   p->mcodes, p->kaps_dev, p->wtab_mem, p->aux};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->pinned) (void)hipHostFree(p->pinned);
@@ -546,6 +546,81 @@ extern "C" int pcx_plan_set_variant(pcx_plan* p, int variant) {
     pl->variant = variant;
     pl->tuned_nt[0] = pl->tuned_nt[1] = 0;
     return PCX_OK;
+}
+
+namespace {
+
+int curl_args(Plan* p, const double kappa[3], int precision, const void* in, void* out, int nvec, const char* who) {
+    if (!p || !kappa || !in || !out) return fail(PCX_E_ARG, "%s: null pointer", who);
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "%s: bad precision", who);
+    if (nvec < 1 || nvec > p->max_vectors) return fail(PCX_E_ARG, "%s: nvec %d outside [1, %d]", who, nvec, p->max_vectors);
+    for (int l = 0; l < 3; ++l)
+        if (!std::isfinite(kappa[l])) return fail(PCX_E_ARG, "%s: non-finite kappa", who);
+    return PCX_OK;
+}
+
+template <typename R>
+int hfield_impl(Plan* p, const double kappa[3], const void* y, void* h, int nvec) {
+    const long n = p->n;
+    int rc = p->grow(&p->aux, &p->aux_cap, (size_t)nvec * 5 * n * sizeof(cx<R>));
+    if (!rc) rc = p->grow(&p->prec, &p->prec_cap, n * sizeof(double));
+    if (rc) return rc;
+    Grid g;
+    if ((rc = p->grid_for(kappa, &g))) return rc;
+    cx<R>* tmp = (cx<R>*)p->aux;                       // Lambda_q^{-1} y
+    cx<R>* u = tmp + (size_t)nvec * 2 * n;             // Q_r Sigma_r (Lambda_q^{-1} y)
+    hipError_t e = launch_precond_diag(g, p->tables, (double*)p->prec, p->stream);
+    if (e == hipSuccess) e = launch_scale_modes<R>((const cx<R>*)y, tmp, (const double*)p->prec, n, nvec, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pcx_hfield: scaling");
+    if ((rc = p->apply(Plan::OP_QS, kappa, sizeof(R) == 8 ? PCX_FP64 : PCX_FP32, tmp, u, nvec))) return rc;
+    e = launch_curl<R>(g, u, (cx<R>*)h, nvec, false, p->stream);
+    return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_hfield: curl");
+}
+
+template <typename R>
+int hoperator_impl(Plan* p, const double kappa[3], const void* h, void* z, int nvec) {
+    const long n = p->n;
+    int rc = p->grow(&p->aux, &p->aux_cap, (size_t)nvec * 5 * n * sizeof(cx<R>));
+    if (rc) return rc;
+    Grid g = p->grid(kappa);
+    cx<R>* t = (cx<R>*)p->aux;
+    const R* inv = sizeof(R) == 8 ? (const R*)p->inv_eps64 : (const R*)p->inv_eps32;
+    hipError_t e = launch_curl<R>(g, (const cx<R>*)h, t, nvec, true, p->stream);
+    if (e == hipSuccess) e = launch_scale3<R>(inv, t, 3 * n, nvec, p->stream);
+    if (e == hipSuccess) e = launch_curl<R>(g, t, (cx<R>*)z, nvec, false, p->stream);
+    return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_apply_hfield_operator");
+}
+
+}  // namespace
+
+extern "C" int pcx_apply_curl(pcx_plan* pp, const double kappa[3], int precision, const void* u, void* v, int nvec,
+                              int adjoint) {
+    Plan* p = (Plan*)pp;
+    int rc = curl_args(p, kappa, precision, u, v, nvec, "pcx_apply_curl");
+    if (rc) return rc;
+    Grid g = p->grid(kappa);
+    hipError_t e = precision == PCX_FP64
+                       ? launch_curl<double>(g, (const cx<double>*)u, (cx<double>*)v, nvec, adjoint != 0, p->stream)
+                       : launch_curl<float>(g, (const cx<float>*)u, (cx<float>*)v, nvec, adjoint != 0, p->stream);
+    return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_apply_curl");
+}
+
+extern "C" int pcx_hfield(pcx_plan* pp, const double kappa[3], int precision, const void* y, void* h, int nvec) {
+    Plan* p = (Plan*)pp;
+    int rc = curl_args(p, kappa, precision, y, h, nvec, "pcx_hfield");
+    if (rc) return rc;
+    if ((rc = p->check_fits(precision))) return rc;
+    return precision == PCX_FP64 ? hfield_impl<double>(p, kappa, y, h, nvec) : hfield_impl<float>(p, kappa, y, h, nvec);
+}
+
+extern "C" int pcx_apply_hfield_operator(pcx_plan* pp, const double kappa[3], int precision, const void* h, void* z,
+                                         int nvec) {
+    Plan* p = (Plan*)pp;
+    int rc = curl_args(p, kappa, precision, h, z, nvec, "pcx_apply_hfield_operator");
+    if (rc) return rc;
+    if (!p->eps_set) return fail(PCX_E_ARG, "pcx_apply_hfield_operator: permittivity not set");
+    return precision == PCX_FP64 ? hoperator_impl<double>(p, kappa, h, z, nvec)
+                                 : hoperator_impl<float>(p, kappa, h, z, nvec);
 }
 
 extern "C" int pcx_apply_Ar(pcx_plan* p, const double kappa[3], int precision, const void* y, void* z, int nvec) {

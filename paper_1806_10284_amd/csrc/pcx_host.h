@@ -42,6 +42,9 @@ struct Plan {
     // matvec workspace (3n complex per vector)
     void* work = nullptr;
     size_t work_cap = 0;
+    // magnetic-field maps: 2n + 3n complex per vector
+    void* aux = nullptr;
+    size_t aux_cap = 0;
 
     // eigensolver storage
     void* lob_mem = nullptr;

@@ -194,6 +194,14 @@ hipError_t launch_sqrt(const double* in, double* out, long count, hipStream_t st
 hipError_t launch_grad(const cx<double>* x, const double* w, int nvec, long n, double* grad, int voxel,
                        hipStream_t st);
 
+// the discrete curl C of Section 3 (adjoint: C^*) on nvec 3n-vectors in the e-layout (real-space
+// stencils with the quasi-periodic wraps); in and out must not overlap
+template <typename R>
+hipError_t launch_curl(const Grid& g, const cx<R>* in, cx<R>* out, int nvec, bool adjoint, hipStream_t st);
+// x[v][q] *= s[q] for q < n3 (a 3n-long real scaling such as 1/eps)
+template <typename R>
+hipError_t launch_scale3(const R* s, cx<R>* x, long n3, int nvec, hipStream_t st);
+
 // seeded complex normal deviates times `scale` (counter-based: element e of stream `seed`)
 template <typename R>
 hipError_t launch_random(cx<R>* y, long count, unsigned long long seed, double scale, hipStream_t st);

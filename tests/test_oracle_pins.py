@@ -431,3 +431,63 @@ def test_inverse_lanczos_matches_config1_golden():
     eps = S.sample_yee(S.SC, g.n, g.shift, S.sc_sphere_shapes(), 13.0, 1.0)
     lam, _, _ = nfsep_inverse_lanczos(spectrum(g, kap), eps, 10)
     np.testing.assert_allclose(lam, gold["lambda"], rtol=1e-10)
+
+
+@pytest.mark.parametrize("seed,gamma", [(21, False), (22, True), (23, False)])
+def test_svd_of_the_explicit_curl(seed, gamma):
+    """Theorem 5.1 with the explicit sparse C (dense SVD at small grids): the singular values are
+    sqrt(Lambda_q) of every mode, twice, and n zeros; at kappa in Z^3 (the Gamma-point SVD) the one mode
+    with Lambda_q = 0 adds two more zeros (n + 2).  The oracle's left and right singular vectors
+    P_r = (I_3 (x) T) V and Q_r = (I_3 (x) T) W Sigma_r^{-1} satisfy C Q_r = P_r Sigma_r and
+    C^* P_r = Q_r Sigma_r, and P_r has orthonormal columns."""
+    from oracle.curl import curl_matrix
+    from oracle.nfsep import P_adjoint, P_apply, QS_apply, QS_adjoint
+    rng = np.random.default_rng(seed)
+    avec, g = random_geometry(rng, nlo=3, nhi=5)
+    kap = np.zeros(3) if gamma else rng.uniform(-0.5, 0.5, 3)
+    n = g.npts
+    C = curl_matrix(g, kap).toarray()
+    sv = np.sort(np.linalg.svd(C, compute_uv=False))
+    spec = spectrum(g, kap)
+    lq = np.sort(np.sum(np.abs(spec.lam) ** 2, axis=0).reshape(-1))
+    nz = n + 2 if gamma else n
+    assert np.all(sv[:nz] < 1e-10 * sv[-1])
+    ref = np.sort(np.sqrt(np.repeat(lq[lq > 0], 2)))
+    np.testing.assert_allclose(sv[nz:], ref, rtol=1e-10)
+    # dense P_r and Q_r Sigma_r, column by column
+    P = np.stack([P_apply(spec, e) for e in np.eye(2 * n)], axis=1)
+    QS = np.stack([QS_apply(spec, e) for e in np.eye(2 * n)], axis=1)
+    lq2 = np.concatenate([np.sum(np.abs(spec.lam) ** 2, axis=0).reshape(-1)] * 2)
+    live = lq2 > 0
+    G = P.conj().T @ P
+    np.testing.assert_allclose(G[np.ix_(live, live)], np.eye(live.sum()), atol=1e-12)
+    assert not np.any(P[:, ~live])
+    # C Q_r Sigma_r = P_r Sigma_r^2 and C^* P_r = Q_r Sigma_r
+    np.testing.assert_allclose(C @ QS, P * lq2[None, :], atol=1e-10 * lq2.max())
+    np.testing.assert_allclose(C.conj().T @ P, QS, atol=1e-10 * np.sqrt(lq2.max()))
+    # the adjoint map
+    h = rng.standard_normal(3 * n) + 1j * rng.standard_normal(3 * n)
+    np.testing.assert_allclose(P_adjoint(spec, h), P.conj().T @ h, atol=1e-12 * np.abs(h).max())
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_hfield_operator_and_nfsep(seed):
+    """The magnetic-field operator C B^{-1} C^* (explicit C) has the same positive eigenvalues as the GEP,
+    and P_r^* (C B^{-1} C^*) P_r = A_r (dense, random eps)."""
+    from oracle.curl import curl_matrix
+    from oracle.nfsep import P_apply
+    rng = np.random.default_rng(seed)
+    avec, g = random_geometry(rng, nlo=3, nhi=5)
+    kap = rng.uniform(-0.5, 0.5, 3)
+    eps = rng.uniform(1.0, 13.0, (3, g.npts))
+    C = curl_matrix(g, kap).toarray()
+    H = C @ np.diag(1.0 / eps.reshape(-1)) @ C.conj().T
+    wh = np.linalg.eigvalsh(0.5 * (H + H.conj().T))
+    wh = wh[wh > 1e-9 * wh.max()]
+    ref, _ = dense_gep(g, kap, eps, len(wh))
+    np.testing.assert_allclose(wh, ref, rtol=1e-9)
+    spec = spectrum(g, kap)
+    n2 = 2 * g.npts
+    P = np.stack([P_apply(spec, e) for e in np.eye(n2)], axis=1)
+    Ar = Ar_dense(spec, eps)
+    np.testing.assert_allclose(P.conj().T @ H @ P, Ar, atol=1e-9 * np.abs(Ar).max())

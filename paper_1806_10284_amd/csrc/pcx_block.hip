@@ -3,6 +3,10 @@
 // Vectors are columns of length N stored contiguously; a ColSet lists up to 4 runs of columns.
 #include "pcx_internal.h"
 
+#include <algorithm>
+#include <type_traits>
+#include <utility>
+
 namespace pcx {
 
 #define DEV __device__ __forceinline__
@@ -175,6 +179,381 @@ __global__ void __launch_bounds__(256) k_gram(ColSet A, ColSet B, long N, long r
     }
 }
 
+// ------------------------------------------------------------------ Gram on the matrix cores
+// The Hermitian layouts (B = [A] or [A | A'], every ka x ka half Hermitian) with ka <= kMfmaMaxA go
+// through FP64 4x4x4 MFMA products with four blocks per instruction.  A complex inner product is
+// a real one over a K index that runs over (row, real/imaginary part): with a_k = (Re a, Im a) and
+// b_k = (Re b, Im b), Re(conj(a) b) = sum_k a_k b_k, and with a'_k = (-Im a, Re a),
+// Im(conj(a) b) = sum_k a'_k b_k.  An instruction takes K = 4 (two rows) in each of its blocks,
+// i.e. eight rows of one 4 x 4 tile of G, and the four blocks' partial sums are added at the end.
+// Operand lane l holds element (m, k) of block q, m = l & 3 (the column within the tile),
+// q = (l >> 2) & 3, k = l >> 4; result element (i, j) of block q sits in lane 16 i + 4 q + j.
+// The partner k ^ 1 that a' needs sits in lane l ^ 16: one lane swap (v_permlane16_swap) and a
+// sign flip turn a into a'.
+//
+// Rows reach LDS by direct global-to-LDS loads (16 bytes per lane, lane L written at 16 L of a
+// 1 KB unit), so the number of bytes in flight is bounded by LDS, not by registers.  A unit holds
+// one tile of four columns over 16 rows (FP64) or 32 rows (FP32), with the lanes' rows chosen so
+// that the operand of lane l is
+//   FP64: element 32 g + 16 (l >> 5) + (l & 15) of the unit, half (l >> 4) & 1,
+//   FP32: 16-byte chunk 16 g + (l & 15) (rows 2 q, 2 q + 1 of column m), float l >> 4,
+// for the group g of eight rows: a wave's operand read is 512 contiguous bytes (FP64) or 256
+// (FP32), free of bank conflicts.  A stage is `sub` row blocks of all tiles; `slots` stages rotate
+// through LDS, slots - 1 of them in flight while the waves multiply the oldest, with one barrier
+// per stage.  Rows past the end and padding columns load from a zero block.
+//
+// Work split: 512 threads, eight waves, two per SIMD.  With two halves (NH = 2) waves 0-3 take
+// half 0 and waves 4-7 half 1; within a half, the upper-triangle tile pairs (I, J >= I) are split
+// at a tile row into two sets of about equal size (I < IS and I >= IS), and each set goes to two
+// waves that alternate over the groups of eight rows (with one half, to four waves).  A wave
+// reads the A and B tiles of its set for a group once, into registers, and issues the set's
+// products fully unrolled (NT a template parameter), holding the real and imaginary accumulators
+// of its pairs for the whole row chunk; while they run, the reads of the next group are in
+// flight.  The waves of a set add their accumulators through LDS at the end.
+#ifndef PCX_MFMA_LDS
+#define PCX_MFMA_LDS (76 * 1024)
+#endif
+#ifndef PCX_MFMA_LDS1
+#define PCX_MFMA_LDS1 (150 * 1024)
+#endif
+#ifndef PCX_DMA_UNITS
+#define PCX_DMA_UNITS 16
+#endif
+#ifndef PCX_DMA_SLOTS
+#define PCX_DMA_SLOTS 8
+#endif
+constexpr int kMfmaMaxNT = 12;
+constexpr int kMfmaMaxA = 4 * kMfmaMaxNT;
+constexpr int kMfmaLds = PCX_MFMA_LDS;         // LDS for the stage slots, two work-groups per CU
+constexpr int kMfmaLds1 = PCX_MFMA_LDS1;       // the same, one work-group per CU
+constexpr int kDmaUnits = PCX_DMA_UNITS;       // 1 KB units per stage aimed at
+constexpr int kDmaSlots = PCX_DMA_SLOTS;       // most stage slots
+constexpr int kMfmaThreads = 512;              // eight waves
+constexpr int kMfmaWaves = kMfmaThreads / 64;
+constexpr int kDmaMaxUPW = 3;                  // units per wave and stage (at most 24 per stage)
+
+__device__ __align__(16) double g_dma_zero[2];   // never written: the zero block
+
+// tile counts up to this run two work-groups per CU (the accumulators' registers allow it)
+constexpr int kMfmaTwoGroupsNT = 5;
+
+// first tile row of the second pair set: the smallest IS with at least half of the
+// nt (nt + 1) / 2 pairs in rows I < IS
+__host__ __device__ constexpr int mfma_split(int nt) {
+    int is = 0, c = 0;
+    while (2 * c < nt * (nt + 1) / 2) c += nt - is++;
+    return is;
+}
+__host__ __device__ constexpr int mfma_set_pairs(int nt, int set) {
+    int c = 0;
+    for (int I = set ? mfma_split(nt) : 0; I < (set ? nt : mfma_split(nt)); ++I) c += nt - I;
+    return c;
+}
+
+struct DmaShape {
+    int sub, units, slot_bytes, slots, lds_bytes;
+};
+// nphase: waves that alternate over one half's groups of eight rows
+__host__ __device__ inline int mfma_phases(int nh) { return nh == 2 ? 2 : 4; }
+__host__ __device__ inline DmaShape dma_shape(int ka, int kb, bool f64) {
+    DmaShape d;
+    const int nt = (ka + 3) / 4, nh = kb / ka, ntiles = nh * nt;
+    d.sub = kDmaUnits / ntiles < 1 ? 1 : kDmaUnits / ntiles;
+    // every wave of a half gets the same number of groups: sub * (groups per row block) a
+    // multiple of the phases
+    if (f64 && mfma_phases(nh) == 4 && (d.sub & 1)) ++d.sub;
+    while (d.sub > 1 && d.sub * ntiles > kMfmaWaves * kDmaMaxUPW) d.sub -= f64 && mfma_phases(nh) == 4 ? 2 : 1;
+    if (d.sub < 1) d.sub = 1;
+    d.units = d.sub * ntiles;
+    d.slot_bytes = d.units * 1024;
+    d.slots = (nt <= kMfmaTwoGroupsNT ? kMfmaLds : kMfmaLds1) / d.slot_bytes;
+    if (d.slots > kDmaSlots) d.slots = kDmaSlots;
+    if (d.slots < 2) d.slots = 2;
+    // the final reduction: the other phases' partial sums of every pair of both sets, 16 lanes x
+    // 16 bytes each
+    const int ps = mfma_set_pairs(nt, 0) > mfma_set_pairs(nt, 1) ? mfma_set_pairs(nt, 0) : mfma_set_pairs(nt, 1);
+    const int red = nh * 2 * (mfma_phases(nh) - 1) * ps * 256;
+    d.lds_bytes = d.slots * d.slot_bytes > red ? d.slots * d.slot_bytes : red;
+    return d;
+}
+
+DEV double flip_sign(double x, unsigned hi_mask) {
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    u ^= (unsigned long long)hi_mask << 32;
+    return __longlong_as_double((long long)u);
+}
+
+// the value of lane l ^ 16: v_permlane16_swap of x with itself returns the even 16-lane rows'
+// values in its first result and the odd rows' in its second
+DEV unsigned swap16(unsigned x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+}
+DEV double swap16(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = swap16((unsigned)u), hi = swap16((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One 16-byte-per-lane global-to-LDS load: lane L's 16 bytes land at LDS byte lds_addr + 16 L
+// (lds_addr wave-uniform).  Written as an instruction rather than the builtin so that the compiler
+// does not order every later LDS read after it (it cannot tell which stage slot a read touches);
+// the kernel waits for these loads itself (wait_then_barrier).  The load has no register result.
+DEV void dma16(const void* src, unsigned lds_addr) {
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds_addr) : "memory", "m0");
+}
+
+// wait until at most n of this wave's global loads are outstanding (n wave-uniform; the counter
+// holds at most 63, a larger n waits for 63) and its LDS reads are done, then the work-group barrier
+DEV void wait_then_barrier(int n) {
+#define W(k) \
+    case k: __builtin_amdgcn_s_waitcnt(0x070 | ((k) & 15) | (((k) >> 4) << 14)); break
+#define W8(k) W(k); W(k + 1); W(k + 2); W(k + 3); W(k + 4); W(k + 5); W(k + 6); W(k + 7)
+    switch (n) {
+        W8(0); W8(8); W8(16); W8(24); W8(32); W8(40); W8(48);
+        W(56); W(57); W(58); W(59); W(60); W(61); W(62);
+        default: __builtin_amdgcn_s_waitcnt(0x070 | 15 | (3 << 14)); break;
+    }
+#undef W8
+#undef W
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <typename R, int NT, int NH>
+__global__ void __launch_bounds__(kMfmaThreads) k_gram_mfma(ColSet B, int ka, long N, long rows_per_chunk, int sub,
+                                                             int slots, cx<double>* __restrict__ part) {
+    constexpr bool F64 = sizeof(R) == 8;
+    constexpr int UR = F64 ? 16 : 32;                    // rows per unit
+    constexpr int G = UR / 8;                            // groups of eight rows per unit
+    constexpr int NPH = NH == 2 ? 2 : 4;                 // waves per set
+    constexpr int ntiles = NH * NT;
+    constexpr int PSMAX = mfma_set_pairs(NT, 0) > mfma_set_pairs(NT, 1) ? mfma_set_pairs(NT, 0) : mfma_set_pairs(NT, 1);
+    extern __shared__ __align__(1024) char lds[];
+    const int kb = NH * ka;
+    const int U = sub * ntiles, slot_bytes = U * 1024, SR = sub * UR;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int hw = NH == 2 ? wave >> 2 : 0;
+    const int set = NH == 2 ? (wave >> 1) & 1 : wave >> 2;
+    const int ph = NH == 2 ? wave & 1 : wave & 3;
+    const long r0 = (long)blockIdx.x * rows_per_chunk;
+    const long r1 = min(N, r0 + rows_per_chunk);
+    const int stages = (int)((r1 - r0 + SR - 1) / SR);
+
+    // this wave's units u = wave + 8 i (row block u / ntiles, tile u % ntiles): the column this
+    // lane loads and its row within the stage
+    const int urow = F64 ? 8 * (lane >> 5) + 2 * ((lane >> 2) & 3) + ((lane >> 4) & 1)
+                         : 8 * (lane >> 4) + 2 * ((lane >> 2) & 3);
+    const int cw = (U - wave + kMfmaWaves - 1) / kMfmaWaves;
+    const cx<R>* colp[kDmaMaxUPW];
+    int srow[kDmaMaxUPW];
+#pragma unroll
+    for (int i = 0; i < kDmaMaxUPW; ++i) {
+        const int u = wave + kMfmaWaves * i;
+        colp[i] = nullptr;
+        srow[i] = 0;
+        if (u < U) {
+            const int t = u % ntiles, h = t / NT, q = 4 * (t % NT) + (lane & 3);
+            if (q < ka) colp[i] = col_ptr<const cx<R>>(B, h * ka + q, N);
+            srow[i] = (u / ntiles) * UR + urow;
+        }
+    }
+    const unsigned lds0 = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) char*)lds);
+    const void* zero = (const void*)g_dma_zero;
+    auto issue = [&](int s) {
+        const unsigned dst = lds0 + (unsigned)((s % slots) * slot_bytes) + (unsigned)(wave * 1024);
+        const long rs = r0 + (long)s * SR;
+#pragma unroll
+        for (int i = 0; i < kDmaMaxUPW; ++i) {
+            if (i < cw) {
+                const long row = rs + srow[i];
+                dma16((colp[i] && row < r1) ? (const void*)(colp[i] + row) : zero,
+                      dst + (unsigned)(kMfmaWaves * i * 1024));
+            }
+        }
+    };
+
+    const unsigned neg = ((lane >> 4) & 1) ? 0u : 0x80000000u;   // a' = (-Im a, Re a)
+    const int lo = F64 ? (16 * (lane >> 5) + (lane & 15)) * 16 + ((lane >> 4) & 1) * 8 : (lane & 15) * 16 + (lane >> 4) * 4;
+    const int bofs = hw * NT * 1024;                              // this wave's half of B
+
+    // The wave's groups of eight rows, in order: gps per stage (group ph + NPH j of the stage),
+    // W in all.  A group that opens a stage first waits for that stage's loads and passes the
+    // barrier, then queues the loads of a later stage into the slot every wave has finished with.
+    const int gps = sub * G / NPH, W = stages * gps;
+    auto open_stage = [&](int w) {
+        const int s = w / gps;
+        wait_then_barrier(min(slots - 2, stages - 1 - s) * cw);
+        if (s + slots - 1 < stages) issue(s + slots - 1);
+    };
+    cx<double>* red = (cx<double>*)lds;    // final reduction: [half][set][phase - 1][pair][16 lanes]
+    const int slot16 = (lane >> 4) * 4 + (lane & 3);
+
+    // everything a wave does for the pair set SET: tile rows I in [IB, IE), B tiles J in [IB, NT)
+    auto run = [&](auto set_tag) {
+        constexpr int SET = decltype(set_tag)::value;
+        constexpr int IS = mfma_split(NT);
+        constexpr int IB = SET ? IS : 0, IE = SET ? NT : IS;
+        constexpr int NA = IE - IB > 0 ? IE - IB : 1, NB = NT - IB > 0 ? NT - IB : 1;
+        constexpr int PS = mfma_set_pairs(NT, SET) > 0 ? mfma_set_pairs(NT, SET) : 1;
+        double accR[PS], accI[PS];
+#pragma unroll
+        for (int p = 0; p < PS; ++p) accR[p] = accI[p] = 0.0;
+
+        // raw LDS reads of a group, then, after the products that overlap their latency, a' and b
+        auto load = [&](int w, R* ra, R* rb) {
+            const int s = w / gps, gg = ph + NPH * (w - s * gps);
+            const char* pg = lds + (size_t)(s % slots) * slot_bytes + (size_t)(gg / G) * ntiles * 1024 +
+                             (F64 ? 512 : 256) * (gg % G) + lo;
+            // an empty set (NT = 1) reads the last tile, whose products it never issues
+            constexpr int T0 = IB < NT ? IB : NT - 1;
+#pragma unroll
+            for (int t = 0; t < NA; ++t) ra[t] = *(const R*)(pg + 1024 * (T0 + t));
+#pragma unroll
+            for (int t = 0; t < NB; ++t) rb[t] = *(const R*)(pg + bofs + 1024 * (T0 + t));
+        };
+        auto finish = [&](const R* ra, const R* rb, double* a, double* a2, double* bv) {
+#pragma unroll
+            for (int t = 0; t < NA; ++t) {
+                a[t] = (double)ra[t];
+                if (F64)
+                    a2[t] = flip_sign(swap16(a[t]), neg);
+                else
+                    a2[t] = flip_sign((double)__uint_as_float(swap16(__float_as_uint((float)ra[t]))), neg);
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t) bv[t] = (double)rb[t];
+        };
+        auto product = [&](const double* a, const double* a2, const double* bv) {
+            int p = 0;
+#pragma unroll
+            for (int I = IB; I < IE; ++I)
+#pragma unroll
+                for (int J = I; J < NT; ++J, ++p) {
+                    accR[p] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[I - IB], bv[J - IB], accR[p], 0, 0, 0);
+                    accI[p] = __builtin_amdgcn_mfma_f64_4x4x4f64(a2[I - IB], bv[J - IB], accI[p], 0, 0, 0);
+                }
+        };
+
+        R ra[NA], rb[NB];
+        double a0[NA], b0[NA], c0[NB], a1[NA], b1[NA], c1[NB];   // two sets of (a, a', b)
+        open_stage(0);
+        load(0, ra, rb);
+        finish(ra, rb, a0, b0, c0);
+        // the reads are unconditional (past the last group they read the current one again), so
+        // that no register copies, which would wait for them, join the branches
+        for (int w = 0; w < W; w += 2) {
+            const bool more1 = w + 1 < W;
+            if (more1 && (w + 1) % gps == 0) open_stage(w + 1);
+            load(more1 ? w + 1 : w, ra, rb);
+            __builtin_amdgcn_sched_barrier(0);
+            product(a0, b0, c0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (!more1) break;
+            finish(ra, rb, a1, b1, c1);
+            const bool more2 = w + 2 < W;
+            if (more2 && (w + 2) % gps == 0) open_stage(w + 2);
+            load(more2 ? w + 2 : w + 1, ra, rb);
+            __builtin_amdgcn_sched_barrier(0);
+            product(a1, b1, c1);
+            __builtin_amdgcn_sched_barrier(0);
+            finish(ra, rb, a0, b0, c0);
+        }
+
+        // the four blocks of each accumulator, then the phases of the set through LDS (the stage
+        // slots are free: the last wait had no load outstanding and every wave is past it)
+#pragma unroll
+        for (int p = 0; p < PS; ++p) {
+            accR[p] += __shfl_xor(accR[p], 4, 64);
+            accI[p] += __shfl_xor(accI[p], 4, 64);
+            accR[p] += __shfl_xor(accR[p], 8, 64);
+            accI[p] += __shfl_xor(accI[p], 8, 64);
+        }
+        wait_then_barrier(0);
+        const size_t rbase = (size_t)((hw * 2 + SET) * (NPH - 1)) * PSMAX;
+        if (ph > 0 && (lane & 12) == 0) {
+#pragma unroll
+            for (int p = 0; p < PS; ++p) {
+                cx<double> v;
+                v.x = accR[p];
+                v.y = accI[p];
+                red[(rbase + (size_t)(ph - 1) * PSMAX + p) * 16 + slot16] = v;
+            }
+        }
+        wait_then_barrier(0);
+        if (ph == 0 && (lane & 12) == 0 && mfma_set_pairs(NT, SET) > 0) {
+            cx<double>* out = part + (size_t)blockIdx.x * ka * kb;
+            int p = 0;
+#pragma unroll
+            for (int I = IB; I < IE; ++I)
+#pragma unroll
+                for (int J = I; J < NT; ++J, ++p) {
+                    double re = accR[p], im = accI[p];
+#pragma unroll
+                    for (int f = 1; f < NPH; ++f) {
+                        const cx<double> v = red[(rbase + (size_t)(f - 1) * PSMAX + p) * 16 + slot16];
+                        re += v.x;
+                        im += v.y;
+                    }
+                    const int ia = 4 * I + (lane >> 4), jb = 4 * J + (lane & 3);
+                    if (ia < ka && jb < ka) {
+                        cx<double> o;
+                        o.x = re;
+                        o.y = im;
+                        out[(size_t)ia * kb + hw * ka + jb] = o;
+                    }
+                }
+        }
+    };
+
+    for (int s = 0; s < min(slots - 1, stages); ++s) issue(s);
+    if (set == 0)
+        run(std::integral_constant<int, 0>{});
+    else
+        run(std::integral_constant<int, 1>{});
+}
+
+template <typename R, int NT, int NH>
+static hipError_t gram_mfma_impl(const ColSet& B, int ka, long N, cx<double>* part, int chunks, long rpc,
+                                 hipStream_t st) {
+    const DmaShape d = dma_shape(ka, B.total(), sizeof(R) == 8);
+    hipLaunchKernelGGL((k_gram_mfma<R, NT, NH>), dim3(chunks), dim3(kMfmaThreads), (size_t)d.lds_bytes, st, B, ka, N,
+                       rpc, d.sub, d.slots, part);
+    return hipGetLastError();
+}
+
+template <typename R, int NH>
+static hipError_t gram_mfma_nh(const ColSet& B, int ka, long N, cx<double>* part, int chunks, long rpc,
+                               hipStream_t st) {
+    switch ((ka + 3) / 4) {
+        case 1: return gram_mfma_impl<R, 1, NH>(B, ka, N, part, chunks, rpc, st);
+        case 2: return gram_mfma_impl<R, 2, NH>(B, ka, N, part, chunks, rpc, st);
+        case 3: return gram_mfma_impl<R, 3, NH>(B, ka, N, part, chunks, rpc, st);
+        case 4: return gram_mfma_impl<R, 4, NH>(B, ka, N, part, chunks, rpc, st);
+        case 5: return gram_mfma_impl<R, 5, NH>(B, ka, N, part, chunks, rpc, st);
+        case 6: return gram_mfma_impl<R, 6, NH>(B, ka, N, part, chunks, rpc, st);
+        case 7: return gram_mfma_impl<R, 7, NH>(B, ka, N, part, chunks, rpc, st);
+        case 8: return gram_mfma_impl<R, 8, NH>(B, ka, N, part, chunks, rpc, st);
+        case 9: return gram_mfma_impl<R, 9, NH>(B, ka, N, part, chunks, rpc, st);
+        case 10: return gram_mfma_impl<R, 10, NH>(B, ka, N, part, chunks, rpc, st);
+        case 11: return gram_mfma_impl<R, 11, NH>(B, ka, N, part, chunks, rpc, st);
+        default: return gram_mfma_impl<R, 12, NH>(B, ka, N, part, chunks, rpc, st);
+    }
+}
+
+// row chunks of the matrix-core Gram: one or two work-groups per CU (by the accumulators' registers)
+inline int mfma_groups(int ka) { return (ka + 3) / 4 <= kMfmaTwoGroupsNT ? 512 : 256; }
+
+template <typename R>
+static hipError_t gram_mfma(const ColSet& B, int ka, long N, cx<double>* part, int chunks, long rpc,
+                            hipStream_t st) {
+    return B.total() == 2 * ka ? gram_mfma_nh<R, 2>(B, ka, N, part, chunks, rpc, st)
+                               : gram_mfma_nh<R, 1>(B, ka, N, part, chunks, rpc, st);
+}
+
 // out[e] = sum over chunks of part[c][e]: stage 1 sums chunk groups in parallel, stage 2 the groups
 constexpr int kRedGroups = 32;
 
@@ -206,6 +585,18 @@ __global__ void k_reduce_stage2(const cx<double>* __restrict__ mid, int count, c
     out[e].y = sy;
 }
 
+// out = the sum of the chunks' partial Gram matrices (count entries each); the middle stage's
+// kRedGroups rows sit after the chunks' rows in part
+static hipError_t reduce_chunks(cx<double>* part, int chunks, int count, cx<double>* out, hipStream_t st) {
+    cx<double>* mid = part + (size_t)chunks * count;
+    hipLaunchKernelGGL(k_reduce_stage1, dim3((count + 255) / 256, kRedGroups), dim3(256), 0, st, part, chunks, count,
+                       mid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_stage2, dim3((count + 255) / 256), dim3(256), 0, st, mid, count, out);
+    return hipGetLastError();
+}
+
 template <typename R, int BLK, bool HERM>
 static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>* part, int chunks, long rpc,
                             hipStream_t st) {
@@ -232,9 +623,23 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     const int ka = A.total(), kb = B.total();
     if (ka < 1 || kb < 1 || ka > kMaxCols || kb > kMaxCols) return hipErrorInvalidValue;
     if (herm && kb != ka && kb != 2 * ka) return hipErrorInvalidValue;
+    hipError_t e;
+    int chunks;
+    if (herm && ka <= kMfmaMaxA) {
+        // matrix-core path: at most kMfmaGroups row chunks
+        const long groups = std::min<long>(nchunk, mfma_groups(ka));
+        const DmaShape d = dma_shape(ka, kb, sizeof(R) == 8);
+        const long SR = (long)d.sub * (sizeof(R) == 8 ? 16 : 32);     // rows per stage
+        long rpc = (N + groups - 1) / groups;
+        rpc = (rpc + SR - 1) / SR * SR;
+        chunks = (int)((N + rpc - 1) / rpc);
+        e = gram_mfma<R>(B, ka, N, part, chunks, rpc, st);
+        if (e != hipSuccess) return e;
+        return reduce_chunks(part, chunks, ka * kb, out, st);
+    }
     long rpc = (N + nchunk - 1) / nchunk;
     rpc = (rpc + kGramRows - 1) / kGramRows * kGramRows;
-    const int chunks = (int)((N + rpc - 1) / rpc);
+    chunks = (int)((N + rpc - 1) / rpc);
     // register tile: every thread of the group waits for the busiest, so the cost of a tile size
     // is (rounds of 256 pair-blocks) x BLK^2; the cheapest, larger BLK on ties (fewer LDS reads per
     // product).  A second round (two pair-blocks per thread) counts 2.5: half the group idles
@@ -242,7 +647,6 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     // Rayleigh-Ritz product takes 207 us with BLK 3 in one round, 248 us with BLK 2 in two); beyond
     // 2 rounds the pair-blocks go to several work-groups per row chunk, each of which stages the
     // rows again, so those rounds count double
-    hipError_t e;
     auto pbs = [&](int blk) {
         const int a = (ka + blk - 1) / blk;
         return herm ? (kb / ka) * a * (a + 1) / 2 : a * ((kb + blk - 1) / blk);
@@ -269,14 +673,7 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
         default: e = gram_impl<R, 4, true>(A, B, N, part, chunks, rpc, st); break;
     }
     if (e != hipSuccess) return e;
-    const int count = ka * kb;
-    cx<double>* mid = part + (size_t)chunks * count;
-    hipLaunchKernelGGL(k_reduce_stage1, dim3((count + 255) / 256, kRedGroups), dim3(256), 0, st, part, chunks, count,
-                       mid);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_stage2, dim3((count + 255) / 256), dim3(256), 0, st, mid, count, out);
-    return hipGetLastError();
+    return reduce_chunks(part, chunks, ka * kb, out, st);
 }
 
 // ------------------------------------------------------------------ Y = S C
@@ -694,6 +1091,23 @@ static hipError_t set_gram_lds() {
                                160 * 1024);
 }
 
+template <typename R, int NT, int NH>
+static hipError_t set_mfma_lds_one() {
+    return hipFuncSetAttribute((const void*)k_gram_mfma<R, NT, NH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024);
+}
+template <typename R, int... NT>
+static hipError_t set_mfma_lds_list(std::integer_sequence<int, NT...>) {
+    hipError_t e = hipSuccess;
+    ((e = e == hipSuccess ? set_mfma_lds_one<R, NT + 1, 1>() : e), ...);
+    ((e = e == hipSuccess ? set_mfma_lds_one<R, NT + 1, 2>() : e), ...);
+    return e;
+}
+template <typename R>
+static hipError_t set_mfma_lds() {
+    return set_mfma_lds_list<R>(std::make_integer_sequence<int, kMfmaMaxNT>{});
+}
+
 hipError_t configure_block_kernels() {
     hipError_t e = hipSuccess;
 #define G(R, B, H) \
@@ -703,6 +1117,8 @@ hipError_t configure_block_kernels() {
     G(double, 1, false); G(double, 2, false); G(double, 3, false); G(double, 4, false);
     G(double, 1, true); G(double, 2, true); G(double, 3, true); G(double, 4, true);
 #undef G
+    if (e == hipSuccess) e = set_mfma_lds<float>();
+    if (e == hipSuccess) e = set_mfma_lds<double>();
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)k_combine<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kCombineLds);

@@ -99,64 +99,148 @@ static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, st
     return true;
 }
 
-bool herm_eig(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>& V, int ncols) {
+// Matrices in split form (real and imaginary parts in separate row-major arrays), so that the
+// row operations below are plain real loops the compiler vectorises.
+struct SMat {
+    int rows = 0, cols = 0;
+    std::vector<double> re, im;
+    SMat() = default;
+    SMat(int r, int c) : rows(r), cols(c), re((size_t)r * c, 0.0), im((size_t)r * c, 0.0) {}
+    double* rr(int i) { return re.data() + (size_t)i * cols; }
+    double* ri(int i) { return im.data() + (size_t)i * cols; }
+    const double* rr(int i) const { return re.data() + (size_t)i * cols; }
+    const double* ri(int i) const { return im.data() + (size_t)i * cols; }
+};
+
+static SMat split(int r, int c, const std::vector<zc>& A) {
+    SMat S(r, c);
+    for (size_t e = 0; e < (size_t)r * c; ++e) {
+        S.re[e] = A[e].real();
+        S.im[e] = A[e].imag();
+    }
+    return S;
+}
+
+static std::vector<zc> join(const SMat& S) {
+    std::vector<zc> A((size_t)S.rows * S.cols);
+    for (size_t e = 0; e < A.size(); ++e) A[e] = zc(S.re[e], S.im[e]);
+    return A;
+}
+
+// sum_c a[c] b[c] over n entries (complex, a conjugated when CONJ)
+template <bool CONJ>
+static inline void dotc(int n, const double* ar, const double* ai, const double* br, const double* bi, double& sr,
+                        double& si) {
+    double xr = 0.0, xi = 0.0;
+    {
+        // the order of the additions is free (lets the loop run on vector registers)
+#pragma clang fp reassociate(on)
+        for (int c = 0; c < n; ++c) {
+            if (CONJ) {
+                xr += ar[c] * br[c] + ai[c] * bi[c];
+                xi += ar[c] * bi[c] - ai[c] * br[c];
+            } else {
+                xr += ar[c] * br[c] - ai[c] * bi[c];
+                xi += ar[c] * bi[c] + ai[c] * br[c];
+            }
+        }
+    }
+    sr = xr;
+    si = xi;
+}
+
+// y[c] -= s x[c] over n entries (complex s)
+static inline void axpy_sub(int n, double sr, double si, const double* xr, const double* xi, double* yr, double* yi) {
+    for (int c = 0; c < n; ++c) {
+        const double a = xr[c], b = xi[c];
+        yr[c] -= sr * a - si * b;
+        yi[c] -= sr * b + si * a;
+    }
+}
+
+// Householder reduction and QL on a split Hermitian matrix; V (k x ncols, split) holds the
+// eigenvectors of the ncols lowest eigenvalues
+static bool herm_eig_split(int k, SMat A, std::vector<double>& w, SMat& V, int ncols) {
     if (ncols < 0 || ncols > k) ncols = k;
-    hermitize(k, A);
-    // Householder reduction A = Q T Q^H, Q = H_0 H_1 ... with H_j = I - 2 v_j v_j^H acting on the
-    // indices above j; each step updates only the trailing block A[j+1:, j+1:]
-    std::vector<zc> R((size_t)k * k, zc(0, 0));   // row j: v_j (zero below index j + 1)
+    // hermitize
+    for (int i = 0; i < k; ++i) {
+        A.ri(i)[i] = 0.0;
+        for (int j = i + 1; j < k; ++j) {
+            const double r = 0.5 * (A.rr(i)[j] + A.rr(j)[i]), m = 0.5 * (A.ri(i)[j] - A.ri(j)[i]);
+            A.rr(i)[j] = r;
+            A.ri(i)[j] = m;
+            A.rr(j)[i] = r;
+            A.ri(j)[i] = -m;
+        }
+    }
+    // A = Q T Q^H, Q = H_0 H_1 ... with H_j = I - 2 v_j v_j^H acting on the indices above j; each
+    // step updates only the trailing block A[j+1:, j+1:]
+    SMat R(k, k);                                   // row j: v_j (zero below index j + 1)
     std::vector<char> has(k, 0);
-    std::vector<zc> p(k), q(k);
+    std::vector<double> pr(k), pi(k), qr(k), qi(k);
     for (int j = 0; j + 2 < k; ++j) {
-        zc* aj = &A[(size_t)j * k];                 // row j holds conj of column j
+        const int o = j + 1, n = k - o;
+        // x = A[j+1:, j] = conj of row j's entries
+        const double* ajr = A.rr(j) + o;
+        const double* aji = A.ri(j) + o;
         double xn2 = 0.0;
-        for (int i = j + 1; i < k; ++i) xn2 += std::norm(aj[i]);
+        for (int i = 0; i < n; ++i) xn2 += ajr[i] * ajr[i] + aji[i] * aji[i];
         const double xn = std::sqrt(xn2);
         if (xn == 0.0) continue;
-        const zc x0 = std::conj(aj[j + 1]);          // A[j+1][j]
+        const zc x0(ajr[0], -aji[0]);
         const double ax0 = std::abs(x0);
-        const zc ph = ax0 > 0 ? x0 / ax0 : zc(1, 0);
-        const zc alpha = -ph * xn;                   // reflect x = A[j+1:, j] onto alpha e_1
-        zc* v = &R[(size_t)j * k];
-        for (int i = j + 1; i < k; ++i) v[i] = std::conj(aj[i]);
-        v[j + 1] -= alpha;
+        const zc ph = ax0 > 0 ? zc(x0.real() / ax0, x0.imag() / ax0) : zc(1, 0);
+        const zc alpha = -ph * xn;                  // reflect x onto alpha e_1
+        double* vr = R.rr(j) + o;
+        double* vi = R.ri(j) + o;
+        for (int i = 0; i < n; ++i) {
+            vr[i] = ajr[i];
+            vi[i] = -aji[i];
+        }
+        vr[0] -= alpha.real();
+        vi[0] -= alpha.imag();
         double vn2 = 0.0;
-        for (int i = j + 1; i < k; ++i) vn2 += std::norm(v[i]);
+        for (int i = 0; i < n; ++i) vn2 += vr[i] * vr[i] + vi[i] * vi[i];
         if (vn2 == 0.0) continue;
-        const double vi = 1.0 / std::sqrt(vn2);
-        for (int i = j + 1; i < k; ++i) v[i] *= vi;
+        const double vs = 1.0 / std::sqrt(vn2);
+        for (int i = 0; i < n; ++i) {
+            vr[i] *= vs;
+            vi[i] *= vs;
+        }
         has[j] = 1;
         // H A22 H = A22 - 2 (v q^H + q v^H), p = A22 v, K = v^H p (real), q = p - K v
-        for (int i = j + 1; i < k; ++i) {
-            const zc* ai = &A[(size_t)i * k];
-            double sr = 0.0, si = 0.0;
-            for (int c = j + 1; c < k; ++c) {
-                sr += ai[c].real() * v[c].real() - ai[c].imag() * v[c].imag();
-                si += ai[c].real() * v[c].imag() + ai[c].imag() * v[c].real();
-            }
-            p[i] = zc(sr, si);
-        }
+        for (int i = 0; i < n; ++i) dotc<false>(n, A.rr(o + i) + o, A.ri(o + i) + o, vr, vi, pr[i], pi[i]);
         double K = 0.0;
-        for (int i = j + 1; i < k; ++i) K += cjmul(v[i], p[i]).real();
-        for (int i = j + 1; i < k; ++i) q[i] = p[i] - K * v[i];
-        for (int i = j + 1; i < k; ++i) {
-            zc* ai = &A[(size_t)i * k];
-            const zc vi2 = 2.0 * v[i], qi2 = 2.0 * q[i];
-            for (int c = j + 1; c < k; ++c) ai[c] -= mulcj(vi2, q[c]) + mulcj(qi2, v[c]);
+        for (int i = 0; i < n; ++i) K += vr[i] * pr[i] + vi[i] * pi[i];
+        for (int i = 0; i < n; ++i) {
+            qr[i] = pr[i] - K * vr[i];
+            qi[i] = pi[i] - K * vi[i];
+        }
+        for (int i = 0; i < n; ++i) {
+            double* ar = A.rr(o + i) + o;
+            double* ai = A.ri(o + i) + o;
+            const double v2r = 2.0 * vr[i], v2i = 2.0 * vi[i], q2r = 2.0 * qr[i], q2i = 2.0 * qi[i];
+            // a[c] -= 2 v_i conj(q_c) + 2 q_i conj(v_c)
+            for (int c = 0; c < n; ++c) {
+                ar[c] -= v2r * qr[c] + v2i * qi[c] + q2r * vr[c] + q2i * vi[c];
+                ai[c] -= v2i * qr[c] - v2r * qi[c] + q2i * vr[c] - q2r * vi[c];
+            }
         }
         // the reduced column and row: alpha e_1
-        A[(size_t)(j + 1) * k + j] = alpha;
-        aj[j + 1] = std::conj(alpha);
+        A.rr(o)[j] = alpha.real();
+        A.ri(o)[j] = alpha.imag();
+        A.rr(j)[o] = alpha.real();
+        A.ri(j)[o] = -alpha.imag();
     }
     // phases that make the sub-diagonal real and non-negative
     std::vector<zc> dph(k, zc(1, 0));
     std::vector<double> d(k), e(std::max(k, 1), 0.0);
-    for (int i = 0; i < k; ++i) d[i] = A[(size_t)i * k + i].real();
+    for (int i = 0; i < k; ++i) d[i] = A.rr(i)[i];
     for (int i = 0; i + 1 < k; ++i) {
-        const zc s = A[(size_t)(i + 1) * k + i];
+        const zc s(A.rr(i + 1)[i], A.ri(i + 1)[i]);
         const double as = std::abs(s);
         e[i] = as;
-        dph[i + 1] = as > 0 ? dph[i] * s / as : dph[i];
+        dph[i + 1] = as > 0 ? dph[i] * zc(s.real() / as, s.imag() / as) : dph[i];
     }
     std::vector<Rot> rots;
     rots.reserve((size_t)4 * k * k);
@@ -180,78 +264,115 @@ bool herm_eig(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>&
             zj[c] = g.c * a1 - g.s * a0;
         }
     }
-    // eigenvector c = Q diag(dph) Z[:, idx[c]]: the phases, then H_{k-3}, ..., H_0 in turn
-    std::vector<zc> X((size_t)ncols * k);           // row c: eigenvector c
-    for (int c = 0; c < ncols; ++c) {
-        zc* x = &X[(size_t)c * k];
-        for (int m = 0; m < k; ++m) x[m] = dph[m] * Zw[(size_t)m * ncols + c];
-    }
+    // eigenvector c = Q diag(dph) Z[:, idx[c]]: the phases, then H_{k-3}, ..., H_0 in turn (X:
+    // row c holds eigenvector c)
+    SMat X(ncols, k);
+    for (int c = 0; c < ncols; ++c)
+        for (int m = 0; m < k; ++m) {
+            const double z = Zw[(size_t)m * ncols + c];
+            X.rr(c)[m] = dph[m].real() * z;
+            X.ri(c)[m] = dph[m].imag() * z;
+        }
     for (int j = k - 3; j >= 0; --j) {
         if (!has[j]) continue;
-        const zc* v = &R[(size_t)j * k];
+        const int o = j + 1, n = k - o;
+        const double* vr = R.rr(j) + o;
+        const double* vi = R.ri(j) + o;
         for (int c = 0; c < ncols; ++c) {
-            zc* x = &X[(size_t)c * k];
-            double sr = 0.0, si = 0.0;
-            for (int i = j + 1; i < k; ++i) {
-                sr += v[i].real() * x[i].real() + v[i].imag() * x[i].imag();
-                si += v[i].real() * x[i].imag() - v[i].imag() * x[i].real();
-            }
-            const zc s2(2.0 * sr, 2.0 * si);
-            for (int i = j + 1; i < k; ++i) x[i] -= cmul(s2, v[i]);
+            double* xr = X.rr(c) + o;
+            double* xi = X.ri(c) + o;
+            double sr, si;
+            dotc<true>(n, vr, vi, xr, xi, sr, si);          // v^H x
+            axpy_sub(n, 2.0 * sr, 2.0 * si, vr, vi, xr, xi);  // x -= 2 (v^H x) v
         }
     }
-    V.assign((size_t)k * ncols, zc(0, 0));
+    V = SMat(k, ncols);
     for (int i = 0; i < k; ++i)
-        for (int c = 0; c < ncols; ++c) V[(size_t)i * ncols + c] = X[(size_t)c * k + i];
+        for (int c = 0; c < ncols; ++c) {
+            V.rr(i)[c] = X.rr(c)[i];
+            V.ri(i)[c] = X.ri(c)[i];
+        }
     return true;
+}
+
+bool herm_eig(int k, std::vector<zc> A, std::vector<double>& w, std::vector<zc>& V, int ncols) {
+    if (ncols < 0 || ncols > k) ncols = k;
+    SMat Vs;
+    if (!herm_eig_split(k, split(k, k, A), w, Vs, ncols)) return false;
+    V = join(Vs);
+    return true;
+}
+
+// G = L L^H on split matrices
+static bool cholesky_split(int k, const SMat& G, SMat& L, double rel_tol) {
+    L = SMat(k, k);
+    double dmax = 0.0;
+    for (int i = 0; i < k; ++i) dmax = std::max(dmax, G.rr(i)[i]);
+    if (!(dmax > 0.0)) return false;
+    for (int j = 0; j < k; ++j) {
+        double dj = G.rr(j)[j];
+        for (int m = 0; m < j; ++m) dj -= L.rr(j)[m] * L.rr(j)[m] + L.ri(j)[m] * L.ri(j)[m];
+        if (!(dj > rel_tol * dmax)) return false;
+        const double ljj = std::sqrt(dj), inv = 1.0 / ljj;
+        L.rr(j)[j] = ljj;
+        for (int i = j + 1; i < k; ++i) {
+            // L[i][j] = (G[i][j] - sum_m L[i][m] conj(L[j][m])) / L[j][j]
+            double sr, si;
+            dotc<true>(j, L.rr(j), L.ri(j), L.rr(i), L.ri(i), sr, si);   // sum conj(L[j][m]) L[i][m]
+            L.rr(i)[j] = (G.rr(i)[j] - sr) * inv;
+            L.ri(i)[j] = (G.ri(i)[j] - si) * inv;
+        }
+    }
+    return true;
+}
+
+// X = L^{-1} B (B: k x m), split
+static SMat solve_L_split(int k, const SMat& L, const SMat& B) {
+    SMat X = B;
+    const int m = B.cols;
+    for (int i = 0; i < k; ++i) {
+        double* xr = X.rr(i);
+        double* xi = X.ri(i);
+        for (int j = 0; j < i; ++j) axpy_sub(m, L.rr(i)[j], L.ri(i)[j], X.rr(j), X.ri(j), xr, xi);
+        const double inv = 1.0 / L.rr(i)[i];
+        for (int c = 0; c < m; ++c) {
+            xr[c] *= inv;
+            xi[c] *= inv;
+        }
+    }
+    return X;
+}
+
+// X = L^{-H} B (B: k x m), split
+static SMat solve_LH_split(int k, const SMat& L, const SMat& B) {
+    SMat X = B;
+    const int m = B.cols;
+    for (int i = k - 1; i >= 0; --i) {
+        double* xr = X.rr(i);
+        double* xi = X.ri(i);
+        for (int j = i + 1; j < k; ++j) axpy_sub(m, L.rr(j)[i], -L.ri(j)[i], X.rr(j), X.ri(j), xr, xi);
+        const double inv = 1.0 / L.rr(i)[i];
+        for (int c = 0; c < m; ++c) {
+            xr[c] *= inv;
+            xi[c] *= inv;
+        }
+    }
+    return X;
 }
 
 bool cholesky(int k, const std::vector<zc>& G, std::vector<zc>& L, double rel_tol) {
-    L.assign((size_t)k * k, zc(0, 0));
-    double dmax = 0.0;
-    for (int i = 0; i < k; ++i) dmax = std::max(dmax, G[(size_t)i * k + i].real());
-    if (!(dmax > 0.0)) return false;
-    for (int j = 0; j < k; ++j) {
-        double dj = G[(size_t)j * k + j].real();
-        for (int m = 0; m < j; ++m) dj -= std::norm(L[(size_t)j * k + m]);
-        if (!(dj > rel_tol * dmax)) return false;
-        const double ljj = std::sqrt(dj);
-        L[(size_t)j * k + j] = ljj;
-        for (int i = j + 1; i < k; ++i) {
-            zc s = G[(size_t)i * k + j];
-            for (int m = 0; m < j; ++m) s -= mulcj(L[(size_t)i * k + m], L[(size_t)j * k + m]);
-            L[(size_t)i * k + j] = s / ljj;
-        }
-    }
-    return true;
+    SMat Ls;
+    const bool ok = cholesky_split(k, split(k, k, G), Ls, rel_tol);
+    L = ok ? join(Ls) : std::vector<zc>((size_t)k * k, zc(0, 0));
+    return ok;
 }
 
 void solve_LH(int k, const std::vector<zc>& L, const std::vector<zc>& B, int m, std::vector<zc>& X) {
-    X = B;
-    for (int i = k - 1; i >= 0; --i) {
-        zc* xi = &X[(size_t)i * m];
-        for (int j = i + 1; j < k; ++j) {
-            const zc l = L[(size_t)j * k + i];
-            const zc* xj = &X[(size_t)j * m];
-            for (int c = 0; c < m; ++c) xi[c] -= cjmul(l, xj[c]);
-        }
-        const double inv = L[(size_t)i * k + i].real();
-        for (int c = 0; c < m; ++c) xi[c] /= inv;
-    }
+    X = join(solve_LH_split(k, split(k, k, L), split(k, m, B)));
 }
 
 void solve_L(int k, const std::vector<zc>& L, const std::vector<zc>& B, int m, std::vector<zc>& X) {
-    X = B;
-    for (int i = 0; i < k; ++i) {
-        zc* xi = &X[(size_t)i * m];
-        for (int j = 0; j < i; ++j) {
-            const zc l = L[(size_t)i * k + j];
-            const zc* xj = &X[(size_t)j * m];
-            for (int c = 0; c < m; ++c) xi[c] -= cmul(l, xj[c]);
-        }
-        const double inv = L[(size_t)i * k + i].real();
-        for (int c = 0; c < m; ++c) xi[c] /= inv;
-    }
+    X = join(solve_L_split(k, split(k, k, L), split(k, m, B)));
 }
 
 bool rayleigh_ritz(int k, std::vector<zc> GA, std::vector<zc> GB, int want, double chol_tol,
@@ -270,20 +391,23 @@ bool rayleigh_ritz(int k, std::vector<zc> GA, std::vector<zc> GB, int want, doub
             GA[(size_t)i * k + j] *= sc[i] * sc[j];
             GB[(size_t)i * k + j] *= sc[i] * sc[j];
         }
-    std::vector<zc> L;
-    if (!cholesky(k, GB, L, chol_tol)) return false;
-    std::vector<zc> Y, H;
-    solve_L(k, L, GA, k, Y);                    // Y = L^{-1} GA
-    std::vector<zc> Yh((size_t)k * k);
+    SMat L;
+    if (!cholesky_split(k, split(k, k, GB), L, chol_tol)) return false;
+    const SMat Y = solve_L_split(k, L, split(k, k, GA));      // Y = L^{-1} GA
+    SMat Yh(k, k);
     for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) Yh[(size_t)i * k + j] = std::conj(Y[(size_t)j * k + i]);
-    solve_L(k, L, Yh, k, H);                    // H = L^{-1} Y^H = L^{-1} GA L^{-H}
+        for (int j = 0; j < k; ++j) {
+            Yh.rr(i)[j] = Y.rr(j)[i];
+            Yh.ri(i)[j] = -Y.ri(j)[i];
+        }
+    const SMat H = solve_L_split(k, L, Yh);                  // H = L^{-1} Y^H = L^{-1} GA L^{-H}
     std::vector<double> w;
-    std::vector<zc> V;
-    if (!herm_eig(k, H, w, V, want)) return false;
-    solve_LH(k, L, V, want, C);
+    SMat V;
+    if (!herm_eig_split(k, H, w, V, want)) return false;
+    const SMat Cs = solve_LH_split(k, L, V);
+    C.resize((size_t)k * want);
     for (int i = 0; i < k; ++i)
-        for (int c = 0; c < want; ++c) C[(size_t)i * want + c] *= sc[i];
+        for (int c = 0; c < want; ++c) C[(size_t)i * want + c] = zc(Cs.rr(i)[c], Cs.ri(i)[c]) * sc[i];
     theta.assign(w.begin(), w.begin() + want);
     return true;
 }

@@ -757,9 +757,145 @@ __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __r
     }
 }
 
+// Y = S C on the matrix cores for ks <= kCombMaxK inputs and m <= 2 NTO outputs: the real
+// product [Re S, Im S] C' in FP64 4x4x4 MFMA with four blocks of four rows each, i.e. 16 rows per
+// instruction.  Real outputs are ordered (output column u, real/imaginary part); C' row
+// (c, Re) = (Re C[c][u], Im C[c][u]) and row (c, Im) = (-Im C[c][u], Re C[c][u]).  A K step takes
+// four input columns: operand lane l (block q = (l >> 2) & 3, row 4 q + (l & 3), k = l >> 4) loads
+// the complex entry of column 4 s + k (16 bytes; a wave reads 16 rows of four columns) and feeds
+// its real part to one product (K rows (c, Re)) and its imaginary part to a second one (K rows
+// (c, Im)).  The B side (C' tiles of 4 K x 4 outputs, the same for the four blocks) is staged in
+// LDS once per work-group and read with four lanes on each address.  A wave takes kCombRT row
+// tiles at a time, so each C' tile read serves kCombRT products, with NTO accumulators per row
+// tile, and the S loads run kCombAhead K steps ahead of the products.
+// Result lane l holds row 4 q + (l >> 4)'s output 4 t + (l & 3) of block q.
+#ifndef PCX_COMB_RT
+#define PCX_COMB_RT 2
+#endif
+#ifndef PCX_COMB_AHEAD
+#define PCX_COMB_AHEAD 2
+#endif
+constexpr int kCombMaxK = 48;
+constexpr int kCombRT = PCX_COMB_RT;               // row tiles per wave and pass
+constexpr int kCombAhead = PCX_COMB_AHEAD;         // K steps the S loads run ahead
+
+template <typename R, int NTO>
+__global__ void __launch_bounds__(256) k_combine_mfma(ColSet S, const cx<double>* __restrict__ C, ColSet Y, long N) {
+    constexpr int CR = kCombRT, AH = kCombAhead;
+    __shared__ double cp[(kCombMaxK / 4) * 2 * NTO * 16];   // C' tiles [K step][Re, Im][output tile][k][j]
+    __shared__ const cx<R>* scol[kCombMaxK];
+    __shared__ cx<R>* ycol[2 * NTO];
+    const int ks = S.total(), m = Y.total();
+    const int nks = (ks + 3) / 4;                            // K steps (four complex columns each)
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int c = tid; c < ks; c += blockDim.x) scol[c] = col_ptr<const cx<R>>(S, c, N);
+    for (int c = tid; c < m; c += blockDim.x) ycol[c] = col_ptr<cx<R>>(Y, c, N);
+    for (int e = tid; e < nks * 2 * NTO * 16; e += blockDim.x) {
+        const int s = e / (2 * NTO * 16), rem = e % (2 * NTO * 16);
+        const int p = rem / (NTO * 16), t = (rem / 16) % NTO, k = (rem / 4) % 4, j = rem % 4;
+        const int c = 4 * s + k, o = 4 * t + j, u = o >> 1, pp = o & 1;
+        double v = 0.0;
+        if (c < ks && u < m) {
+            const cx<double> cc = C[(size_t)c * m + u];
+            v = p == 0 ? (pp == 0 ? cc.x : cc.y) : (pp == 0 ? -cc.y : cc.x);
+        }
+        cp[e] = v;
+    }
+    __syncthreads();
+
+    const int q = (lane >> 2) & 3, k = lane >> 4;
+    const int wave = tid >> 6, nwave = blockDim.x >> 6;
+    const double* cpl = cp + (size_t)(k * 4 + (lane & 3));        // B lane (k, j) of a tile
+    const long span = 16L * CR;
+    for (long base = ((long)blockIdx.x * nwave + wave) * span; base < N; base += (long)gridDim.x * nwave * span) {
+        double acc[CR][NTO];
+#pragma unroll
+        for (int r = 0; r < CR; ++r)
+#pragma unroll
+            for (int t = 0; t < NTO; ++t) acc[r][t] = 0.0;
+        long row[CR];
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const long rr = base + 16 * r + 4 * q + (lane & 3);
+            row[r] = rr < N ? rr : N - 1;                          // tail rows read a valid row
+        }
+        // the ring of loaded S entries: slot (s mod (AH + 1)); padding columns read column ks - 1
+        // (their C' rows are zero)
+        cx<R> ring[AH + 1][CR];
+        auto load = [&](int s, cx<R>* v) {
+            const cx<R>* col = scol[min(4 * s + k, ks - 1)];
+#pragma unroll
+            for (int r = 0; r < CR; ++r) v[r] = col[row[r]];
+        };
+#pragma unroll
+        for (int a = 0; a < AH; ++a)
+            if (a < nks) load(a, ring[a]);
+        for (int s0 = 0; s0 < nks; s0 += AH + 1) {
+#pragma unroll
+            for (int d = 0; d <= AH; ++d) {
+                const int s = s0 + d;
+                if (s >= nks) break;
+                if (s + AH < nks) load(s + AH, ring[(d + AH) % (AH + 1)]);
+                const double* cs = cpl + (size_t)s * 2 * NTO * 16;
+#pragma unroll
+                for (int t = 0; t < NTO; ++t) {
+                    const double bre = cs[t * 16], bim = cs[(NTO + t) * 16];
+#pragma unroll
+                    for (int r = 0; r < CR; ++r) {
+                        acc[r][t] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)ring[d][r].x, bre, acc[r][t], 0, 0, 0);
+                        acc[r][t] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)ring[d][r].y, bim, acc[r][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // lane l: row 4 q + (l >> 4) of the tile, real output 4 t + (l & 3)
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const long rr = base + 16 * r + 4 * q + (lane >> 4);
+            if (rr >= N) continue;
+#pragma unroll
+            for (int t = 0; t < NTO; ++t) {
+                const int o = 4 * t + (lane & 3), u = o >> 1;
+                if (u < m) ((R*)ycol[u])[2 * rr + (o & 1)] = (R)acc[r][t];
+            }
+        }
+    }
+}
+
+template <typename R, int NTO>
+static hipError_t combine_mfma_impl(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
+    long blocks = (N + 16L * kCombRT * 4 - 1) / (16L * kCombRT * 4);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL((k_combine_mfma<R, NTO>), dim3((unsigned)blocks), dim3(256), 0, st, S, C, Y, N);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t combine_mfma(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
+    switch ((Y.total() + 1) / 2) {
+        case 1: return combine_mfma_impl<R, 1>(S, C, Y, N, st);
+        case 2: return combine_mfma_impl<R, 2>(S, C, Y, N, st);
+        case 3: return combine_mfma_impl<R, 3>(S, C, Y, N, st);
+        case 4: return combine_mfma_impl<R, 4>(S, C, Y, N, st);
+        case 5: return combine_mfma_impl<R, 5>(S, C, Y, N, st);
+        case 6: return combine_mfma_impl<R, 6>(S, C, Y, N, st);
+        case 7: return combine_mfma_impl<R, 7>(S, C, Y, N, st);
+        case 8: return combine_mfma_impl<R, 8>(S, C, Y, N, st);
+        case 9: return combine_mfma_impl<R, 9>(S, C, Y, N, st);
+        case 10: return combine_mfma_impl<R, 10>(S, C, Y, N, st);
+        case 11: return combine_mfma_impl<R, 11>(S, C, Y, N, st);
+        case 12: return combine_mfma_impl<R, 12>(S, C, Y, N, st);
+        case 13: return combine_mfma_impl<R, 13>(S, C, Y, N, st);
+        case 14: return combine_mfma_impl<R, 14>(S, C, Y, N, st);
+        case 15: return combine_mfma_impl<R, 15>(S, C, Y, N, st);
+        default: return combine_mfma_impl<R, 16>(S, C, Y, N, st);
+    }
+}
+
 template <typename R>
 hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
     if (S.total() < 1 || Y.total() < 1 || S.total() > kMaxCols || Y.total() > kMaxCols) return hipErrorInvalidValue;
+    if (S.total() <= kCombMaxK && Y.total() <= 32) return combine_mfma<R>(S, C, Y, N, st);
     const long span = 256L * kRowsPerThread;
     long blocks = (N + span - 1) / span;
     if (blocks > 8192) blocks = 8192;

@@ -194,9 +194,10 @@ typedef struct pcx_stats {
     long long precond_applies;         /* single-vector applications of Sigma_r Q_r^* B Q_r Sigma_r
                                           (PCX_PRECOND_INVERSE; the A_r kernels with eps for 1/eps) */
     long long precond_applies_fp32;    /* of which in FP32 */
-    int restarts;                      /* PCX_MODE_FP32_REFINE: 1 if the FP64 phase stagnated with
+    int restarts;                      /* 1 if the FP64 phase (after the FP32 phase of
+                                          PCX_MODE_FP32_REFINE, or started from y0) stagnated with
                                           bands open and the solve was repeated in FP64 alone from
-                                          the start block, else 0 */
+                                          the plain start block (without y0), else 0 */
     unsigned long long floor_mask;     /* bit j set: band j counted as converged with a relative
                                           residual above tol, because its absolute residual reached
                                           the working-precision floor (1024 eps_64 ||A_r|| in FP64)
@@ -319,9 +320,10 @@ int pcx_hfield(pcx_plan *p, const double kappa[3], int precision, const void *y,
 int pcx_apply_hfield_operator(pcx_plan *p, const double kappa[3], int precision, const void *h, void *z, int nvec);
 
 /* Measurement hook: runs the three kernels of pcx_apply_Ar (plane forward, x-line, plane
- * adjoint) `reps` times on the plan's stream with HIP events around each launch and returns
- * their mean durations in milliseconds in ms_out[0..2].  Same arguments and effect on z as
- * pcx_apply_Ar.  Synchronises the stream. */
+ * adjoint) `reps` times back to back on the plan's stream, with HIP events around each kernel's
+ * run of launches, and returns their mean durations in milliseconds in ms_out[0..2].  Same
+ * arguments and effect on z as pcx_apply_Ar (one plain application follows the timed runs).
+ * Synchronises the stream. */
 int pcx_time_Ar_kernels(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z,
                         int nvec, int reps, double ms_out[3]);
 

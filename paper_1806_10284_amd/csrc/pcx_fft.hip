@@ -992,28 +992,32 @@ hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_e
 template <typename R>
 hipError_t time_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y, cx<R>* z,
                          cx<R>* t, int nvec, int reps, hipStream_t st, double ms[3]) {
-    hipEvent_t ev[4];
-    for (int q = 0; q < 4; ++q)
+    // each kernel `reps` times back to back between two events (the average interval is then the
+    // kernel's own duration, without the idle gap an event pair around a single launch adds); the
+    // x-line kernel works in place, so its repetitions see changed data, which does not change its
+    // cost; one plain application at the end leaves z = A_r y
+    hipEvent_t ev[2];
+    for (int q = 0; q < 2; ++q)
         if (hipEventCreate(&ev[q]) != hipSuccess) return hipErrorOutOfMemory;
-    double acc[3] = {0, 0, 0};
     hipError_t e = hipSuccess;
-    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
         (void)hipEventRecord(ev[0], st);
-        e = plane_fwd<R>(g, tb, y, t, nvec, st);
-        (void)hipEventRecord(ev[1], st);
-        if (e == hipSuccess) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
-        (void)hipEventRecord(ev[2], st);
-        if (e == hipSuccess) e = plane_adj<R>(g, tb, t, z, nvec, st);
-        (void)hipEventRecord(ev[3], st);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
-        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
-            float f = 0.0f;
-            e = hipEventElapsedTime(&f, ev[q], ev[q + 1]);
-            acc[q] += f;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            if (q == 0) e = plane_fwd<R>(g, tb, y, t, nvec, st);
+            else if (q == 1) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
+            else e = plane_adj<R>(g, tb, t, z, nvec, st);
         }
+        (void)hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
+        ms[q] = reps > 0 ? f / reps : 0.0;
     }
-    for (int q = 0; q < 4; ++q) (void)hipEventDestroy(ev[q]);
-    for (int q = 0; q < 3; ++q) ms[q] = reps > 0 ? acc[q] / reps : 0.0;
+    if (e == hipSuccess) e = plane_fwd<R>(g, tb, y, t, nvec, st);
+    if (e == hipSuccess) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
+    if (e == hipSuccess) e = plane_adj<R>(g, tb, t, z, nvec, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (int q = 0; q < 2; ++q) (void)hipEventDestroy(ev[q]);
     return e;
 }
 

@@ -44,9 +44,13 @@ constexpr double kFloor = PCX_FLOOR_FACTOR;
 // its largest), else the step is retried without P.  FP32 columns carry ~6e-8 relative rounding,
 // amplified in the Ritz coefficients by 1 / sqrt(pivot); a 1e-9 bound let a nearly dependent P
 // through and the implicitly updated A S drift until Ritz values went negative (FCC 64^3, the
-// approximate-inverse preconditioner); 1e-6 keeps the amplification below 1e3.
+// approximate-inverse preconditioner); 1e-6 keeps the amplification below 1e3.  In FP64 a 1e-13
+// bound let a P through that had become nearly dependent once the residuals reached ~1e-10 (SC
+// sphere at Gamma, started from the eigenvectors of the neighbouring path point): the Ritz vectors
+// lost accuracy and the residuals climbed back to 1e-4; 1e-11 drops that P (the cold solves of the
+// same path take the same iterations with either bound).
 constexpr double kCholTol32 = 1e-6;
-constexpr double kCholTol64 = 1e-13;
+constexpr double kCholTol64 = 1e-11;
 
 // ---------------------------------------------------------------- the solver
 
@@ -619,7 +623,8 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
             if (hp[q] > 0 && (dmin == 0 || hp[q] < dmin)) dmin = hp[q];
         S.anorm = dmin > 0 ? 1.0 / (dmin * p->eps_min) : 0.0;
     }
-    auto seed_block = [&](auto* X) -> int {
+    // start block, with the caller's vectors y0 in its first columns when `warm`
+    auto seed_block = [&](auto* X, bool warm) -> int {
         using C = typename std::remove_pointer<decltype(X)>::type;
         hipError_t e2 = launch_random(X, (long)b * N, S.o.seed, 1e-3, p->stream);
         if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: random start");
@@ -629,7 +634,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         for (int c = 0; c < b; ++c) units.idx[c] = (long long)c * N + (c % 2) * n + modes[(c / 2) % nm];
         e2 = launch_set_units(X, units, p->stream);
         if (e2 != hipSuccess) return hip_fail(e2, "pcx_solve: start block");
-        if (S.o.n_y0 > 0) {
+        if (warm && S.o.n_y0 > 0) {
             const long cnt = (long)S.o.n_y0 * N;
             if (std::is_same<C, cx<double>>::value)
                 e2 = hipMemcpyAsync((void*)X, S.o.y0, cnt * sizeof(cx<double>), hipMemcpyDeviceToDevice, p->stream);
@@ -642,7 +647,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     int iters = 0;
     rc = PCX_OK;
     if (use32) {
-        rc = seed_block(B32.X);
+        rc = seed_block(B32.X, true);
         const double tol32 = S.o.mode == PCX_MODE_FP32 ? S.o.tol : std::max(S.o.tol, S.o.tol_fp32);
         if (!rc) rc = S.phase<float>(B32, tol32, S.o.max_iter, iters, use64);
         if (!rc && use64) {
@@ -650,19 +655,21 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
             if (e != hipSuccess) rc = hip_fail(e, "pcx_solve: convert");
         }
     } else {
-        rc = seed_block(B64.X);
+        rc = seed_block(B64.X, true);
     }
     if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false);
-    if (!rc && use32 && use64 && iters < S.o.max_iter) {
-        // FP32+refine whose FP64 phase stopped on stagnation with bands open (seen next to Gamma
-        // at high contrast: started from the FP32 block, the near-zero bands' residuals first
-        // fall to ~1e-7 and then climb back): solve again in FP64 alone from the start block, as
-        // PCX_MODE_FP64 does; at most once, within the same iteration budget
+    if (!rc && use64 && (use32 || S.o.n_y0 > 0) && iters < S.o.max_iter) {
+        // an FP64 phase that stopped on stagnation with bands open, after an FP32 phase or from
+        // the caller's vectors, is solved again in FP64 alone from the plain start block (seen
+        // next to Gamma at high contrast, FP32+refine: started from the FP32 block, the near-zero
+        // bands' residuals first fall to ~1e-7 and then climb back; SC sphere at Gamma started
+        // from the eigenvectors of the neighbouring path point: the residuals reach 2.5e-10, then
+        // climb back to 1e-4 and stall); at most once, within the same iteration budget
         bool open = false;
         for (int j = 0; j < nev; ++j) open = open || !S.converged<double>(j, S.o.tol, true);
         if (open) {
             ++S.st.restarts;
-            rc = seed_block(B64.X);
+            rc = seed_block(B64.X, false);
             if (!rc) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false);
         }
     }

@@ -422,8 +422,8 @@ def main():
 
     if args.profile_kernels:
         for fp64 in (False, True):
-            roofline_block(torch, plan, kappa, fp64, reps=5)
-            print(f"[bench] profiled block matvec fp64={fp64}", file=sys.stderr, flush=True)
+            kern, _ = roofline_block(torch, plan, kappa, fp64, reps=5)
+            print(f"[bench] profiled block matvec fp64={fp64}: {json.dumps(kern)}", file=sys.stderr, flush=True)
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
         b = torch.empty_like(a)
         for _ in range(5):

@@ -320,10 +320,10 @@ int pcx_hfield(pcx_plan *p, const double kappa[3], int precision, const void *y,
 int pcx_apply_hfield_operator(pcx_plan *p, const double kappa[3], int precision, const void *h, void *z, int nvec);
 
 /* Measurement hook: runs the three kernels of pcx_apply_Ar (plane forward, x-line, plane
- * adjoint) `reps` times back to back on the plan's stream, with HIP events around each kernel's
- * run of launches, and returns their mean durations in milliseconds in ms_out[0..2].  Same
- * arguments and effect on z as pcx_apply_Ar (one plain application follows the timed runs).
- * Synchronises the stream. */
+ * adjoint) `reps` times, queued back to back on the plan's stream in that order, each kernel
+ * recording HIP events at its own start and end (hipExtLaunchKernel), and returns their mean
+ * durations in milliseconds in ms_out[0..2].  Same arguments and effect on z as pcx_apply_Ar.
+ * Synchronises the stream once, at the end. */
 int pcx_time_Ar_kernels(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z,
                         int nvec, int reps, double ms_out[3]);
 

@@ -19,7 +19,11 @@
 // work-group; every global read and write is coalesced along the unit-stride index.
 #include "pcx_dev.h"
 
+#include <vector>
+
 namespace pcx {
+
+thread_local LaunchTimer g_launch_timer;
 
 // ------------------------------------------------------------------ Stockham pass in LDS
 // nlines transforms of length N, element stride es and line stride ls (in elements), in place,
@@ -688,11 +692,11 @@ template <typename R>
 static hipError_t split_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, cx<R>* u, int nvec,
                             hipStream_t st) {
     const int RB = split_rows(g.n2, g.n3), CB = split_cols(g.n3);
-    hipLaunchKernelGGL((k_zpass_fwd<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+    PCX_LAUNCH((k_zpass_fwd<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
                        zpass_lds_bytes<R>(RB, g.n3), st, g, tb, y, u, RB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ypass_fwd<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
+    PCX_LAUNCH((k_ypass_fwd<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
                        ypass_lds_bytes<R>(CB, g.n2), st, g, tb, u, t, CB);
     return hipGetLastError();
 }
@@ -701,11 +705,11 @@ template <typename R>
 static hipError_t split_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, cx<R>* u, int nvec,
                             hipStream_t st) {
     const int RB = split_rows(g.n2, g.n3), CB = split_cols(g.n3);
-    hipLaunchKernelGGL((k_ypass_adj<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
+    PCX_LAUNCH((k_ypass_adj<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
                        ypass_lds_bytes<R>(CB, g.n2), st, g, tb, t, u, CB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+    PCX_LAUNCH((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
                        zpass_lds_bytes<R>(RB, g.n3), st, g, tb, u, z, RB);
     return hipGetLastError();
 }
@@ -934,7 +938,7 @@ static hipError_t plane_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* 
     const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
     int nt, ept;
     plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, g.plane_nt[sizeof(R) == 8], &nt, &ept);
-#define CALLF(NT, E) hipLaunchKernelGGL((k_plane_fwd<R, NT, E>), grid, dim3(NT), lds, st, g, tb, y, t)
+#define CALLF(NT, E) PCX_LAUNCH((k_plane_fwd<R, NT, E>), grid, dim3(NT), lds, st, g, tb, y, t)
     PCX_PLANE_DISPATCH(nt, ept, CALLF)
 #undef CALLF
     return hipGetLastError();
@@ -954,7 +958,7 @@ static hipError_t plane_adj(const Grid& g, const DeviceTables& tb, const cx<R>* 
     const size_t lds = plane_lds_bytes<R>(g.n2, g.n3);
     int nt, ept;
     plane_shape((long)g.n2 * g.n3, sizeof(R) == 8, g.plane_nt[sizeof(R) == 8], &nt, &ept);
-#define CALLA(NT, E) hipLaunchKernelGGL((k_plane_adj<R, NT, E>), grid, dim3(NT), lds, st, g, tb, t, z)
+#define CALLA(NT, E) PCX_LAUNCH((k_plane_adj<R, NT, E>), grid, dim3(NT), lds, st, g, tb, t, z)
     PCX_PLANE_DISPATCH(nt, ept, CALLA)
 #undef CALLA
     return hipGetLastError();
@@ -973,7 +977,7 @@ static hipError_t xline(const Grid& g, const DeviceTables& tb, const R* scale, c
     dim3 grid((unsigned)((np + TB - 1) / TB), nvec);
     const size_t lds = xline_lds_bytes<R>(g.n1, TB);
     const int ept = pow2_at_least(((long)g.n1 * TB + kXThreads - 1) / kXThreads);
-#define CALLX(E) hipLaunchKernelGGL((k_xline<R, E, MODE>), grid, dim3(kXThreads), lds, st, g, tb, scale, t, u, TB)
+#define CALLX(E) PCX_LAUNCH((k_xline<R, E, MODE>), grid, dim3(kXThreads), lds, st, g, tb, scale, t, u, TB)
     PCX_EPT_DISPATCH(ept, CALLX)
 #undef CALLX
     return hipGetLastError();
@@ -992,32 +996,34 @@ hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_e
 template <typename R>
 hipError_t time_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y, cx<R>* z,
                          cx<R>* t, int nvec, int reps, hipStream_t st, double ms[3]) {
-    // each kernel `reps` times back to back between two events (the average interval is then the
-    // kernel's own duration, without the idle gap an event pair around a single launch adds); the
-    // x-line kernel works in place, so its repetitions see changed data, which does not change its
-    // cost; one plain application at the end leaves z = A_r y
-    hipEvent_t ev[2];
-    for (int q = 0; q < 2; ++q)
-        if (hipEventCreate(&ev[q]) != hipSuccess) return hipErrorOutOfMemory;
+    // `reps` applications queued back to back, in the solver's order; each kernel records its own
+    // start and end events at dispatch (g_launch_timer), so nothing is inserted between kernels
+    std::vector<hipEvent_t> ev((size_t)6 * reps);
+    size_t made = 0;
     hipError_t e = hipSuccess;
-    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
-        (void)hipEventRecord(ev[0], st);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) {
-            if (q == 0) e = plane_fwd<R>(g, tb, y, t, nvec, st);
-            else if (q == 1) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
-            else e = plane_adj<R>(g, tb, t, z, nvec, st);
-        }
-        (void)hipEventRecord(ev[1], st);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-        float f = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
-        ms[q] = reps > 0 ? f / reps : 0.0;
+    for (; made < ev.size() && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+    if (e != hipSuccess) --made;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        hipEvent_t* q = &ev[(size_t)6 * r];
+        g_launch_timer = {q[0], q[1]};
+        e = plane_fwd<R>(g, tb, y, t, nvec, st);
+        g_launch_timer = {q[2], q[3]};
+        if (e == hipSuccess) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
+        g_launch_timer = {q[4], q[5]};
+        if (e == hipSuccess) e = plane_adj<R>(g, tb, t, z, nvec, st);
+        g_launch_timer = {};
     }
-    if (e == hipSuccess) e = plane_fwd<R>(g, tb, y, t, nvec, st);
-    if (e == hipSuccess) e = xline<R, 0>(g, tb, inv_eps_n, t, nullptr, nvec, st);
-    if (e == hipSuccess) e = plane_adj<R>(g, tb, t, z, nvec, st);
+    g_launch_timer = {};
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    for (int q = 0; q < 2; ++q) (void)hipEventDestroy(ev[q]);
+    double acc[3] = {0, 0, 0};
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+            float f = 0.0f;
+            e = hipEventElapsedTime(&f, ev[(size_t)6 * r + 2 * k], ev[(size_t)6 * r + 2 * k + 1]);
+            acc[k] += f;
+        }
+    for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    for (int k = 0; k < 3; ++k) ms[k] = reps > 0 ? acc[k] / reps : 0.0;
     return e;
 }
 

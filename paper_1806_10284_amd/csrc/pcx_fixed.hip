@@ -698,7 +698,7 @@ static hipError_t p3_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, 
     if (kind == 2 || (kind == 0 && fixed_plane_available(g.n2, g.n3, sizeof(R) == 8, 2))) goto two;
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P3<R, A, B>::bytes <= kLdsMax) {                                          \
-        hipLaunchKernelGGL((k_p3_fwd<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, y, t); \
+        PCX_LAUNCH((k_p3_fwd<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, y, t); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -708,7 +708,7 @@ static hipError_t p3_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, 
 two:
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
-        hipLaunchKernelGGL((k_p2_fwd<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, y, t); \
+        PCX_LAUNCH((k_p2_fwd<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, y, t); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -733,9 +733,9 @@ static hipError_t p3_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, 
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P3<R, A, B>::bytes <= kLdsMax) {                                          \
         if (g.wtab[sizeof(R) == 8])                                                                          \
-            hipLaunchKernelGGL((k_p3_adj<R, A, B, T, true>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
+            PCX_LAUNCH((k_p3_adj<R, A, B, T, true>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_p3_adj<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
+            PCX_LAUNCH((k_p3_adj<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P3<R, A, B>::bytes), st, g, tb, t, z); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -746,9 +746,9 @@ two:
 #define X(A, B, T)                                                                                           \
     if (g.n2 == A && g.n3 == B && P2<R, A, B>::bytes <= kLdsMax) {                                          \
         if (g.wtab[sizeof(R) == 8])                                                                          \
-            hipLaunchKernelGGL((k_p2_adj<R, A, B, T, true>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
+            PCX_LAUNCH((k_p2_adj<R, A, B, T, true>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_p2_adj<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
+            PCX_LAUNCH((k_p2_adj<R, A, B, T, false>), dim3(g.n1, nvec), dim3(T), (P2<R, A, B>::bytes), st, g, tb, t, z); \
         *done = true;                                                                                        \
         return hipGetLastError();                                                                            \
     }
@@ -766,7 +766,7 @@ static hipError_t xl_fixed(const Grid& g, const DeviceTables& tb, const R* scale
     if (g.n1 == A && np % TBV == 0) {                                                                        \
         const size_t lds = sizeof(cx<R>) * ((size_t)TBV * (A + 1) + A);                                      \
         if (lds <= kLdsMax) {                                                                                \
-            hipLaunchKernelGGL((k_xl_fixed<R, A, TBV, T>), dim3((unsigned)(np / TBV), nvec), dim3(T), lds, st, g, \
+            PCX_LAUNCH((k_xl_fixed<R, A, TBV, T>), dim3((unsigned)(np / TBV), nvec), dim3(T), lds, st, g, \
                                tb, scale, t);                                                                \
             *done = true;                                                                                    \
             return hipGetLastError();                                                                        \

@@ -1,12 +1,24 @@
 // Internal declarations shared by the HIP kernels and the host-side plan/solver.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/pcx.h"
 
 namespace pcx {
+
+// Kernel timing for the measurement hook: while a host thread has `start`/`stop` set, the A_r
+// kernels it launches record them at their own start and end on the device (hipExtLaunchKernel),
+// so the interval is the kernel's execution alone, as a profiler reports it.  Null: plain launch.
+struct LaunchTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchTimer g_launch_timer;
+#define PCX_LAUNCH(kernel, grid, block, shmem, stream, ...)                                                  \
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, g_launch_timer.start, g_launch_timer.stop, 0, \
+                          __VA_ARGS__)
 
 constexpr int kMaxPasses = 8;
 constexpr double kMixTau = 1e-3;   // switch to the fallback range basis below Lambda_p^2 / Lambda_q

@@ -229,13 +229,13 @@ bool wave_plane_available(const Grid& g, int fp64) {
 
 hipError_t launch_wave_plane_fwd(const Grid& g, const DeviceTables& tb, const cx<float>* y, cx<float>* t, int nvec,
                                  hipStream_t st) {
-    hipLaunchKernelGGL(k_w64_fwd, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, y, t);
+    PCX_LAUNCH(k_w64_fwd, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, y, t);
     return hipGetLastError();
 }
 
 hipError_t launch_wave_plane_adj(const Grid& g, const DeviceTables& tb, const cx<float>* t, cx<float>* z, int nvec,
                                  hipStream_t st) {
-    hipLaunchKernelGGL(k_w64_adj, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, t, z);
+    PCX_LAUNCH(k_w64_adj, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, t, z);
     return hipGetLastError();
 }
 

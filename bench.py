@@ -47,6 +47,7 @@ HBM_PEAK_GBS = 8000.0
 N_GRID = (64, 64, 64)
 NEV = 10
 ROOF_VECTORS = 32
+ROOF_WARMUP_S = 0.2      # seconds of back-to-back applications before the roofline timing
 
 
 def kernel_bytes_per_vector(n: int, fp64: bool) -> dict:
@@ -127,6 +128,42 @@ def summarize_traffic(fetch_csv: str, write_csv: str, out_json: str):
     return out
 
 
+def summarize_trace(trace_csv: str, last: int = 20) -> str:
+    """Markdown table of the A_r kernels' dispatch durations in a rocprofv3 --kernel-trace file,
+    grouped by vector count (the grid's y extent): calls, mean, and the mean of the last `last`
+    dispatches (for the 32-vector roofline block: the applications bench.py times, after its
+    sustained warm-up)."""
+    import csv
+    from collections import defaultdict
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    groups = defaultdict(list)
+    for r in rows:
+        name = r["Kernel_Name"]
+        key = next((k for p, k in KERNEL_KEYS if name.startswith("void " + p) or name.startswith(p)), None)
+        if key:
+            groups[(key, int(r["Grid_Size_Y"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    # the solves: every dispatch before the first plane kernel of the roofline block
+    stop = next((k for k, r in enumerate(rows) if r["Kernel_Name"].startswith(("pcx::k_w64_fwd", "void pcx::k_p2_fwd",
+                                                                                 "pcx::k_p2_fwd"))
+                 and int(r["Grid_Size_Y"]) == ROOF_VECTORS), len(rows))
+    sol = rows[:stop]
+    busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sol) * 1e-6
+    gaps = [(int(b["Start_Timestamp"]) - int(a["End_Timestamp"])) * 1e-3 for a, b in zip(sol, sol[1:])]
+    span = (int(sol[-1]["End_Timestamp"]) - int(sol[0]["Start_Timestamp"])) * 1e-6 if sol else 0.0
+    head = (f"Before the roofline block: {len(sol)} dispatches, span {span:.1f} ms, kernel time {busy:.1f} ms; "
+            f"gaps between consecutive kernels: {sum(g for g in gaps if 20 <= g < 1000) * 1e-3:.1f} ms in "
+            f"{sum(1 for g in gaps if 20 <= g < 1000)} gaps of 20 us - 1 ms, "
+            f"{sum(g for g in gaps if 0 < g < 20) * 1e-3:.1f} ms below 20 us, "
+            f"{sum(g for g in gaps if g >= 1000) * 1e-3:.1f} ms in gaps of 1 ms or more.\n\n")
+    lines = ["| A_r kernel | vectors | calls | mean us | mean of last %d us |" % last, "|---|---|---|---|---|"]
+    for (key, nv), d in sorted(groups.items(), key=lambda kv: (kv[0][0], -len(kv[1]))):
+        if len(d) < 5:
+            continue
+        tail = d[-last:]
+        lines.append(f"| {key} | {nv} | {len(d)} | {sum(d) / len(d):.1f} | {sum(tail) / len(tail):.1f} |")
+    return head + "\n".join(lines)
+
+
 def load_traffic(dominant: str, fp64: bool):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
     or None if it is missing or was taken on a different kernel source."""
@@ -157,13 +194,19 @@ def setup(torch, max_vectors: int):
     return plan, kappa, eps, g
 
 
-def roofline_block(torch, plan, kappa, fp64: bool, reps: int):
+def roofline_block(torch, plan, kappa, fp64: bool, reps: int, warmup_s: float = ROOF_WARMUP_S):
     import pcx_synth as S
     n = plan.n
     dt = torch.complex128 if fp64 else torch.complex64
     y = torch.from_numpy(np.ascontiguousarray(S.random_block(3, 2 * n, ROOF_VECTORS).T)).to(dtype=dt, device="cuda")
     z = torch.empty_like(y)
-    plan.pcx_time_Ar_kernels(kappa, y, z, reps=2)          # warm-up
+    # sustained warm-up: after the host-side set-up above the GPU has idled, and its clocks take
+    # some 30 ms of load to return to their steady state (the first applications run up to 15 %
+    # slower); the timed applications then see the clocks a solve runs at
+    t_w = time.perf_counter()
+    plan.pcx_time_Ar_kernels(kappa, y, z, reps=2)
+    while time.perf_counter() - t_w < warmup_s:
+        plan.pcx_time_Ar_kernels(kappa, y, z, reps=10)
     ms = plan.pcx_time_Ar_kernels(kappa, y, z, reps=reps)
     names = ["plane_fwd", "xline", "plane_adj"]
     per = kernel_bytes_per_vector(n, fp64)
@@ -391,7 +434,12 @@ def main():
                     help="only run the 32-vector A_r block (and a calibration copy) for rocprofv3 counters")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_fcc64.json from two rocprofv3 --pmc counter files and exit")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="print the A_r kernels' dispatch durations by vector count from a rocprofv3 trace and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
     if args.summarize_traffic:
         out = summarize_traffic(*args.summarize_traffic, os.path.join(ROOT, "profiles", "traffic_fcc64.json"))
         print(json.dumps(out, indent=1))

@@ -115,7 +115,7 @@ int pcx_plan_set_eps(pcx_plan *p, const double *eps, int layout);
  * For FP32 64 x 64 planes (n1 a multiple of 8, one wave vector per launch) AUTO takes the register
  * kernels: each 64-point line held by 8 lanes with 8 values each, both radix-8 passes on registers
  * with a wavefront-local LDS exchange between them, one plane component in LDS at a time for the
- * row/column exchange, W read from the plan's table, work-groups plane-major per XCD.
+ * row/column exchange, W formed per mode from FP64 per-plane tables, work-groups plane-major per XCD.
  * PCX_VARIANT_REGISTER: those kernels where they apply, else as AUTO.
  * PCX_VARIANT_GENERIC: runtime-sized kernels for every grid.
  * PCX_VARIANT_THREE_PLANE / _TWO_PLANE: that fixed-size kind where compiled,

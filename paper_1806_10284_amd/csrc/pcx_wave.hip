@@ -15,7 +15,8 @@
 //     LDS-staged kernels), so the only global reads of a block are its own input: the forward
 //     kernel reads y once and mixes all three components at the start, keeping them in
 //     registers; the adjoint reads each component's input one component ahead of its use, keeps
-//     the three transformed components and mixes them at the end.
+//     the three transformed components (the first in LDS, 32 KB, so that the mixing does not spill
+//     registers) and mixes them at the end.
 //
 // LDS layout (pslot below): rows of kLD = 72 complex (64 used), row a shifted by 2 ((a mod 8) / 2)
 // slots.  Every row write and every column read of a quarter wavefront then falls in 16 distinct
@@ -182,7 +183,10 @@ k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<float>* _
 #pragma unroll
     for (int c = 0; c < 8; ++c) zt[c] = ztw(S.twc, tb.rot32, col, q + 8 * c, s3m);   // row q + 8c of column col
     cx<float>* xb = S.pl + w * kXSlots;
+    // the z-phase outputs of the three components; component 0 waits in LDS for the final mixing
+    // (32 KB), which otherwise runs out of registers beside the FP64 formation of W
     cx<float> sl[3][8];
+    __shared__ cx<float> park[8][kNT];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         cx<float> x[8];
@@ -200,6 +204,10 @@ k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<float>* _
 #pragma unroll
         for (int m = 0; m < 8; ++m) sl[l][m] = S.pl[pslot(j, q + 8 * m)];
         line64<-1>(sl[l], S.twz, xb, gl, q);
+        if (l == 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) park[c][tid] = sl[0][c];
+        }
     }
     // z = W^H s per mode
     const unsigned char* codes = g.codes + mb;
@@ -214,8 +222,9 @@ k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<float>* _
             p3_w<float, kN, kN>(L, L0, j, q + 8 * c, code, idz, W);
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
-                a1 = a1 + cmulc(sl[l][c], W[l][0]);
-                a2 = a2 + cmulc(sl[l][c], W[l][1]);
+                const cx<float> sv = l == 0 ? park[c][tid] : sl[l][c];
+                a1 = a1 + cmulc(sv, W[l][0]);
+                a2 = a2 + cmulc(sv, W[l][1]);
             }
         }
         zb[8 * c] = a1;

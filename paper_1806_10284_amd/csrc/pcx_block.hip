@@ -921,7 +921,7 @@ DEV double block_sum(double v, double* red) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_residual(ColSet X, ColSet AX, const double* __restrict__ theta,
+__global__ void __launch_bounds__(256) k_residual(ColSet X, ColSet AX, Shifts theta,
                                                    const double* __restrict__ prec, long n, ColSet W,
                                                    long rows_per_chunk, double* __restrict__ part) {
     __shared__ double red[4];
@@ -933,7 +933,7 @@ __global__ void __launch_bounds__(256) k_residual(ColSet X, ColSet AX, const dou
         const cx<R>* x = col_ptr<const cx<R>>(X, j, N);
         const cx<R>* ax = col_ptr<const cx<R>>(AX, j, N);
         cx<R>* w = col_ptr<cx<R>>(W, j, N);
-        const double th = theta[j];
+        const double th = theta.v[j];
         double s = 0.0;
         for (long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
             const cx<double> xv = to64(x[r]), av = to64(ax[r]);
@@ -966,10 +966,13 @@ template <typename R>
 hipError_t launch_residual(const ColSet& X, const ColSet& AX, const double* theta, const double* prec, long n,
                            const ColSet& W, double* part, int nchunk, double* out, hipStream_t st) {
     const long N = 2 * n;
+    if (X.total() > PCX_MAX_BLOCK) return hipErrorInvalidValue;
+    Shifts sh;
+    for (int j = 0; j < X.total(); ++j) sh.v[j] = theta[j];
     long rpc = (N + nchunk - 1) / nchunk;
     rpc = (rpc + 255) / 256 * 256;
     const int chunks = (int)((N + rpc - 1) / rpc);
-    hipLaunchKernelGGL((k_residual<R>), dim3(chunks), dim3(256), 0, st, X, AX, theta, prec, n, W, rpc, part);
+    hipLaunchKernelGGL((k_residual<R>), dim3(chunks), dim3(256), 0, st, X, AX, sh, prec, n, W, rpc, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int count = X.total();

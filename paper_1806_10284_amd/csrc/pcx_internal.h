@@ -179,7 +179,11 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
 template <typename R>
 hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st);
 // R_j = AX_j - theta_j X_j ; W_j = prec .* R_j (prec: n doubles, applied to both y-blocks; nullptr = identity);
-// out[j] = ||R_j||^2 (FP64).
+// out[j] = ||R_j||^2 (FP64).  theta: HOST array of X.total() <= PCX_MAX_BLOCK shifts, passed to the kernel
+// by value (no copy to the device).
+struct Shifts {
+    double v[PCX_MAX_BLOCK];
+};
 template <typename R>
 hipError_t launch_residual(const ColSet& X, const ColSet& AX, const double* theta, const double* prec, long n,
                            const ColSet& W, double* part, int nchunk, double* out, hipStream_t st);

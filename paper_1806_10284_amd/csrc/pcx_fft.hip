@@ -437,15 +437,20 @@ __global__ void __launch_bounds__(NT) k_plane_adj(Grid g, DeviceTables tb, const
 }
 
 // ------------------------------------------------------------------ planes too large for LDS
-// When one n2 x n3 plane does not fit in LDS (FP64 at 128 x 128), the plane kernels are split in
-// two passes through an intermediate u[v][l][i][j][c] in HBM:
+// When one n2 x n3 plane does not fit in LDS (FP64 at 128 x 128), or would leave room for only one
+// work-group per CU (FP32 planes above 80 KB), the plane kernels are split in two passes through an
+// intermediate u[v][l][i][j][c] in HBM:
 //   k_zpass_fwd (rows j0..j0+RB of plane i): W y -> z-IDFT -> z-twiddle -> u
 //   k_ypass_fwd (columns c0..c0+CB):          u -> y-IDFT -> y-twiddle -> t[l][i][c][b]
-//   k_ypass_adj / k_zpass_adj: the reverse, with W^H accumulated over l in registers.
-constexpr int kSplitEPT = 8;     // modes per thread in the row passes (256 threads)
+//   k_ypass_adj / k_zpass_adj: the reverse, with W^H summed over l.
+// The row passes hold the three components of their rows in LDS together, so W of a mode is
+// formed once for all three, and each thread keeps one column c: the twiddle index c j s3 mod
+// n2 n3 advances by a fixed step from row to row instead of taking a modulo per element.
+constexpr int kSplitModes = 1024;   // modes per row block and component (FP32; half in FP64): about
+                                    // 30 KB of LDS, five work-groups per CU
 
-static int split_rows(int n2, int n3) {
-    int rb = (256 * kSplitEPT) / n3;
+static int split_rows(int n2, int n3, bool fp64) {
+    int rb = (kSplitModes / (fp64 ? 2 : 1)) / n3;
     if (rb > n2) rb = n2;
     return rb < 1 ? 1 : rb;
 }
@@ -453,7 +458,7 @@ static int split_cols(int n3) { return n3 < 16 ? n3 : 16; }
 
 template <typename R>
 __host__ DEV size_t zpass_lds_bytes(int rb, int n3) {
-    size_t b = sizeof(cx<R>) * ((size_t)rb * (n3 + 1) + 2 * n3);
+    size_t b = sizeof(cx<R>) * ((size_t)3 * rb * (n3 + 1) + 2 * n3);
     b = (b + 15) & ~(size_t)15;
     return b + sizeof(cx<double>) * (n3 + 2 * rb);
 }
@@ -488,9 +493,24 @@ DEV cx<double> zpass_setup(const Grid& g, const KSel& ks, const DeviceTables& tb
     return lam_of_turn(tx, 1.0 / g.dlt[0]);
 }
 
-template <typename R>
-DEV cx<R> split_ztw(const cx<R>* twc, const cx<R>* __restrict__ rot, int c, int j, int s3m, int M) {
-    return cmul(twc[c], rot[(int)(((long)c * j * s3m) % M)]);
+// the thread's column and first row of a row pass (n3 <= 256 = blockDim.x), and the z-twiddle
+// index (c j s3 mod M) of that first row with its step from row to row (all below 2^24: c, j < 256,
+// M <= 65536)
+struct RowWalk {
+    int c, r0, rstep;
+    bool active;
+    unsigned idx, step;
+};
+DEV RowWalk row_walk(int n3, int j0, int s3m, int M) {
+    RowWalk w;
+    w.rstep = (int)blockDim.x / n3 > 0 ? (int)blockDim.x / n3 : 1;
+    w.c = (int)threadIdx.x % n3;
+    w.r0 = (int)threadIdx.x / n3;
+    w.active = (int)threadIdx.x < w.rstep * n3;
+    const unsigned uc = (unsigned)w.c, um = (unsigned)M;
+    w.idx = (uc * (((unsigned)(j0 + w.r0) * (unsigned)s3m) % um)) % um;
+    w.step = (uc * (((unsigned)w.rstep * (unsigned)s3m) % um)) % um;
+    return w;
 }
 
 template <typename R>
@@ -502,10 +522,10 @@ __global__ void __launch_bounds__(256) k_zpass_fwd(Grid g, DeviceTables tb, cons
     const KSel ks = select_k(g, n);
     const int i = blockIdx.x, v = blockIdx.y, j0 = blockIdx.z * RB;
     const int rows = min(RB, n2 - j0);
-    cx<R>* buf = (cx<R>*)lds;
-    cx<R>* twz = buf + (size_t)RB * ld;
+    cx<R>* buf = (cx<R>*)lds;                       // component l, row r at (l RB + r) ld
+    cx<R>* twz = buf + (size_t)3 * RB * ld;
     cx<R>* twc = twz + n3;
-    size_t off = (sizeof(cx<R>) * ((size_t)RB * ld + 2 * n3) + 15) & ~(size_t)15;
+    size_t off = (sizeof(cx<R>) * ((size_t)3 * RB * ld + 2 * n3) + 15) & ~(size_t)15;
     cx<double>* halfz = (cx<double>*)(lds + off);
     cx<double>* rowz = halfz + n3;
     cx<double>* lamy = rowz + RB;
@@ -515,34 +535,47 @@ __global__ void __launch_bounds__(256) k_zpass_fwd(Grid g, DeviceTables tb, cons
     int s3m = g.s3 % M;
     if (s3m < 0) s3m += M;
     const double idz = 1.0 / g.dlt[2];
-    const int tot = rows * n3;
     const long base = (long)i * np + (long)j0 * n3;
     const cx<R>* y1 = y + (long)v * 2 * n + base;
     const cx<R>* y2 = y1 + n;
     const unsigned char* codes = ks.codes + base;
+    RowWalk wk = row_walk(n3, j0, s3m, M);
+    const int c = wk.c;
+    __syncthreads();
+    // u_l = W_l1 y1 + W_l2 y2 for the three components, W formed once per mode
+    if (wk.active) {
+        for (int r = wk.r0; r < rows; r += wk.rstep) {
+            const int e = r * n3 + c;
+            const int code = codes[e];
+            cx<R> u3[3] = {mk<R>((R)0, (R)0), mk<R>((R)0, (R)0), mk<R>((R)0, (R)0)};
+            if (code != kMasked) {
+                const cx<double> h = cmul(halfz[c], rowz[r]);
+                const cx<double> L2 = lam_from_halfturn(h.y, h.x, idz);
+                const cx<R> a = y1[e], b = y2[e];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    cx<R> w1, w2;
+                    w_row_code<R>(L0, lamy[r], L2, code, l, &w1, &w2);
+                    u3[l] = cmul(w1, a) + cmul(w2, b);
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) buf[(l * RB + r) * ld + c] = u3[l];
+        }
+    }
     __syncthreads();
 #pragma unroll 1
-    for (int l = 0; l < 3; ++l) {
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int r = e / n3, k = e % n3;
-            const int code = codes[e];
-            cx<R> val = mk<R>((R)0, (R)0);
-            if (code != kMasked) {
-                const cx<double> h = cmul(halfz[k], rowz[r]);
-                cx<R> w1, w2;
-                w_row_code<R>(L0, lamy[r], lam_from_halfturn(h.y, h.x, idz), code, l, &w1, &w2);
-                val = cmul(w1, y1[e]) + cmul(w2, y2[e]);
-            }
-            buf[r * ld + k] = val;
+    for (int l = 0; l < 3; ++l) fft_lines<R, kEpc, 256>(buf + (size_t)l * RB * ld, g.fz, rows, 1, ld, twz, +1);
+    cx<R>* ub = u + (long)v * 3 * n + base;
+    if (wk.active) {
+        unsigned idx = wk.idx;
+        for (int r = wk.r0; r < rows; r += wk.rstep) {
+            const cx<R> tw = cmul(twc[c], rot[idx]);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) ub[(long)l * n + r * n3 + c] = cmul(buf[(l * RB + r) * ld + c], tw);
+            idx += wk.step;
+            if (idx >= (unsigned)M) idx -= (unsigned)M;
         }
-        __syncthreads();
-        fft_lines<R, kEpc, 256>(buf, g.fz, rows, 1, ld, twz, +1);
-        cx<R>* ul = u + ((long)v * 3 + l) * n + base;
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int r = e / n3, c = e % n3;
-            ul[e] = cmul(buf[r * ld + c], split_ztw<R>(twc, rot, c, j0 + r, s3m, M));
-        }
-        __syncthreads();
     }
 }
 
@@ -632,9 +665,9 @@ __global__ void __launch_bounds__(256) k_zpass_adj(Grid g, DeviceTables tb, cons
     const int i = blockIdx.x, v = blockIdx.y, j0 = blockIdx.z * RB;
     const int rows = min(RB, n2 - j0);
     cx<R>* buf = (cx<R>*)lds;
-    cx<R>* twz = buf + (size_t)RB * ld;
+    cx<R>* twz = buf + (size_t)3 * RB * ld;
     cx<R>* twc = twz + n3;
-    size_t off = (sizeof(cx<R>) * ((size_t)RB * ld + 2 * n3) + 15) & ~(size_t)15;
+    size_t off = (sizeof(cx<R>) * ((size_t)3 * RB * ld + 2 * n3) + 15) & ~(size_t)15;
     cx<double>* halfz = (cx<double>*)(lds + off);
     cx<double>* rowz = halfz + n3;
     cx<double>* lamy = rowz + RB;
@@ -644,46 +677,46 @@ __global__ void __launch_bounds__(256) k_zpass_adj(Grid g, DeviceTables tb, cons
     int s3m = g.s3 % M;
     if (s3m < 0) s3m += M;
     const double idz = 1.0 / g.dlt[2];
-    const int tot = rows * n3;
     const long base = (long)i * np + (long)j0 * n3;
     const unsigned char* codes = ks.codes + base;
-    cx<R> a1[kSplitEPT], a2[kSplitEPT];
+    const cx<R>* ub = u + (long)v * 3 * n + base;
+    RowWalk wk = row_walk(n3, j0, s3m, M);
+    const int c = wk.c;
+    __syncthreads();
+    if (wk.active) {
+        unsigned idx = wk.idx;
+        for (int r = wk.r0; r < rows; r += wk.rstep) {
+            const cx<R> tw = cmul(twc[c], rot[idx]);
 #pragma unroll
-    for (int s = 0; s < kSplitEPT; ++s) a1[s] = a2[s] = mk<R>((R)0, (R)0);
-#pragma unroll 1
-    for (int l = 0; l < 3; ++l) {
-        const cx<R>* ul = u + ((long)v * 3 + l) * n + base;
-        __syncthreads();
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int r = e / n3, c = e % n3;
-            buf[r * ld + c] = cmulc(ul[e], split_ztw<R>(twc, rot, c, j0 + r, s3m, M));
-        }
-        __syncthreads();
-        fft_lines<R, kEpc, 256>(buf, g.fz, rows, 1, ld, twz, -1);
-#pragma unroll
-        for (int s = 0; s < kSplitEPT; ++s) {
-            const int e = threadIdx.x + s * 256;
-            if (e < tot) {
-                const int r = e / n3, k = e % n3;
-                const int code = codes[e];
-                if (code != kMasked) {
-                    const cx<double> h = cmul(halfz[k], rowz[r]);
-                    cx<R> w1, w2;
-                    w_row_code<R>(L0, lamy[r], lam_from_halfturn(h.y, h.x, idz), code, l, &w1, &w2);
-                    const cx<R> val = buf[r * ld + k];
-                    a1[s] = a1[s] + cmulc(val, w1);
-                    a2[s] = a2[s] + cmulc(val, w2);
-                }
-            }
+            for (int l = 0; l < 3; ++l) buf[(l * RB + r) * ld + c] = cmulc(ub[(long)l * n + r * n3 + c], tw);
+            idx += wk.step;
+            if (idx >= (unsigned)M) idx -= (unsigned)M;
         }
     }
+    __syncthreads();
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) fft_lines<R, kEpc, 256>(buf + (size_t)l * RB * ld, g.fz, rows, 1, ld, twz, -1);
+    // z = W^H s per mode, W formed once for the three components
     cx<R>* zb = z + (long)v * 2 * n + base;
+    if (wk.active) {
+        for (int r = wk.r0; r < rows; r += wk.rstep) {
+            const int e = r * n3 + c;
+            const int code = codes[e];
+            cx<R> a1 = mk<R>((R)0, (R)0), a2 = a1;
+            if (code != kMasked) {
+                const cx<double> h = cmul(halfz[c], rowz[r]);
+                const cx<double> L2 = lam_from_halfturn(h.y, h.x, idz);
 #pragma unroll
-    for (int s = 0; s < kSplitEPT; ++s) {
-        const int e = threadIdx.x + s * 256;
-        if (e < tot) {
-            zb[e] = a1[s];
-            zb[n + e] = a2[s];
+                for (int l = 0; l < 3; ++l) {
+                    cx<R> w1, w2;
+                    w_row_code<R>(L0, lamy[r], L2, code, l, &w1, &w2);
+                    const cx<R> val = buf[(l * RB + r) * ld + c];
+                    a1 = a1 + cmulc(val, w1);
+                    a2 = a2 + cmulc(val, w2);
+                }
+            }
+            zb[e] = a1;
+            zb[n + e] = a2;
         }
     }
 }
@@ -691,27 +724,40 @@ __global__ void __launch_bounds__(256) k_zpass_adj(Grid g, DeviceTables tb, cons
 template <typename R>
 static hipError_t split_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, cx<R>* u, int nvec,
                             hipStream_t st) {
-    const int RB = split_rows(g.n2, g.n3), CB = split_cols(g.n3);
+    const int RB = split_rows(g.n2, g.n3, sizeof(R) == 8), CB = split_cols(g.n3);
+    // a timed pair: the start event at the first kernel's start, the stop event at the second's end
+    const LaunchTimer pair = g_launch_timer;
+    g_launch_timer.stop = nullptr;
     PCX_LAUNCH((k_zpass_fwd<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
                        zpass_lds_bytes<R>(RB, g.n3), st, g, tb, y, u, RB);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    PCX_LAUNCH((k_ypass_fwd<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
-                       ypass_lds_bytes<R>(CB, g.n2), st, g, tb, u, t, CB);
-    return hipGetLastError();
+    g_launch_timer = {nullptr, pair.stop};
+    if (e == hipSuccess) {
+        PCX_LAUNCH((k_ypass_fwd<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
+                           ypass_lds_bytes<R>(CB, g.n2), st, g, tb, u, t, CB);
+        e = hipGetLastError();
+    }
+    g_launch_timer = pair;
+    return e;
 }
 
 template <typename R>
 static hipError_t split_adj(const Grid& g, const DeviceTables& tb, const cx<R>* t, cx<R>* z, cx<R>* u, int nvec,
                             hipStream_t st) {
-    const int RB = split_rows(g.n2, g.n3), CB = split_cols(g.n3);
+    const int RB = split_rows(g.n2, g.n3, sizeof(R) == 8), CB = split_cols(g.n3);
+    const LaunchTimer pair = g_launch_timer;
+    g_launch_timer.stop = nullptr;
     PCX_LAUNCH((k_ypass_adj<R>), dim3(g.n1, nvec, (g.n3 + CB - 1) / CB), dim3(256),
                        ypass_lds_bytes<R>(CB, g.n2), st, g, tb, t, u, CB);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    PCX_LAUNCH((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
-                       zpass_lds_bytes<R>(RB, g.n3), st, g, tb, u, z, RB);
-    return hipGetLastError();
+    g_launch_timer = {nullptr, pair.stop};
+    if (e == hipSuccess) {
+        PCX_LAUNCH((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+                           zpass_lds_bytes<R>(RB, g.n3), st, g, tb, u, z, RB);
+        e = hipGetLastError();
+    }
+    g_launch_timer = pair;
+    return e;
 }
 
 // ------------------------------------------------------------------ kernel 2: x-line transforms
@@ -1116,10 +1162,12 @@ static hipError_t split_limits() {
 }
 
 bool split_plane_needed(int n2, int n3, int fp64) {
-    return (fp64 ? plane_lds_bytes<double>(n2, n3) : plane_lds_bytes<float>(n2, n3)) > 160 * 1024;
+    // FP64: the plane does not fit in LDS; FP32: one plane would leave room for one work-group per
+    // CU (at 128 x 128 the single-plane kernel moves 1 TB/s, the two passes about twice that)
+    return (fp64 ? plane_lds_bytes<double>(n2, n3) : plane_lds_bytes<float>(n2, n3)) > (fp64 ? 160 : 80) * 1024;
 }
 size_t split_kernel_lds(int n2, int n3, int fp64) {
-    const int RB = split_rows(n2, n3), CB = split_cols(n3);
+    const int RB = split_rows(n2, n3, fp64 != 0), CB = split_cols(n3);
     const size_t a = fp64 ? zpass_lds_bytes<double>(RB, n3) : zpass_lds_bytes<float>(RB, n3);
     const size_t b = fp64 ? ypass_lds_bytes<double>(CB, n2) : ypass_lds_bytes<float>(CB, n2);
     return a > b ? a : b;

@@ -72,8 +72,8 @@ CASES = [
     ("gamma_sc16", S.SC, (16, 16, 16), (0.0, 0.0, 0.0)),
     ("tri_32_40_40", S.triclinic(6), (32, 40, 40), (0.37, -0.21, 0.08)),
     ("fcc_64_32_32", S.FCC, (64, 32, 32), (0.25, 0.5, -0.125)),
-    # planes too large for LDS take the two-pass plane path: FP64 at 128 x 128 and 100 x 120
-    # (ragged row and column blocks), FP32 at 144 x 150
+    # large planes take the two-pass plane path: FP64 at 128 x 128 and 100 x 120 (ragged row and
+    # column blocks), FP32 at all three (planes above 80 KB of LDS)
     ("split_hex_8_128_128", S.HEX, (8, 128, 128), (0.21, -0.33, 0.4)),
     ("split_ortho_6_100_120", S.ORTHO, (6, 100, 120), (-0.3, 0.45, 0.05)),
     ("split32_sc_4_144_150", S.SC, (4, 144, 150), (0.1, 0.2, -0.35)),
@@ -169,7 +169,7 @@ def test_apply_Ar_fcc64_full_size(prec, variant):
 @pytest.mark.parametrize("case", ["fcc_X", "fcc_generic", "fcc_gamma", "bcc_16", "tri_24"])
 def test_register_plane_kernels_64(case):
     """The register-resident FP32 kernels for 64 x 64 planes (8 lanes x 8 values per line, plane-major
-    block order per XCD, W from the plan's table) on a 5-vector block: A_r, Q_r Sigma_r and its
+    block order per XCD, W formed per mode from FP64 per-plane tables) on a 5-vector block: A_r, Q_r Sigma_r and its
     adjoint against the oracle for every vector, also at Gamma (masked mode) and for n1 = 16 and 24
     (two and three planes per XCD)."""
     import torch

@@ -721,6 +721,214 @@ __global__ void __launch_bounds__(256) k_zpass_adj(Grid g, DeviceTables tb, cons
     }
 }
 
+// Row passes for n3 = 128 on registers: a 128-point row is held by 16 lanes with 8 values each
+// (lane q: elements q + 16 m).  With k = k1 + 8 k2 and x = q + 16 m, the transform is an 8-point
+// DFT over m in each lane, the twiddle w128^(q k1), and a 16-point DFT over q; that one is split
+// again as q = q1 + 2 q2: after one exchange of the 8 x 16 intermediate through LDS rows owned by
+// the wavefront (no work-group barrier), lane p = 2 k1 + q1 takes an 8-point DFT over q2, the
+// twiddle w16^(q1 r) and a 2-point DFT with its neighbour lane p ^ 1 (a DPP lane move).  On
+// return lane p holds output k1 + 8 r + 64 q1 in v[r].  Four rows per wavefront, 16 rows per
+// work-group; the work-group shares only its tables.
+constexpr int kRow128Slots = 4 * 16 * 9;      // exchange slots of a wavefront: 4 rows x 16 lanes x (8 + 1)
+
+DEV float lane_xor1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+DEV double lane_xor1(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)u, (int)(unsigned)u, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(u >> 32), (int)(unsigned)(u >> 32), 0xB1, 0xF, 0xF,
+                                               false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+DEV void row_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// sign S transform of the row held by the 16 lanes (q = lane mod 16) of one row group; tw[m] =
+// exp(2 pi i m / 128); xb: the row's 144 exchange slots
+template <typename R, int S>
+DEV void line128(cx<R> v[8], const cx<R>* tw, cx<R>* __restrict__ xb, int q) {
+    Bfly<R, 8>::run(v, S);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) {
+        const cx<R> w = tw[(q * k1) & 127];
+        v[k1] = S > 0 ? cmul(v[k1], w) : cmulc(v[k1], w);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) xb[q * 9 + k1] = v[k1];
+    row_wave_sync();
+    const int k1 = q >> 1, q1 = q & 1;
+#pragma unroll
+    for (int q2 = 0; q2 < 8; ++q2) v[q2] = xb[(q1 + 2 * q2) * 9 + k1];
+    row_wave_sync();
+    Bfly<R, 8>::run(v, S);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        cx<R> z = v[r];
+        if (q1 && r) {
+            const cx<R> w = tw[8 * r];
+            z = S > 0 ? cmul(z, w) : cmulc(z, w);
+        }
+        cx<R> pz;
+        pz.x = lane_xor1(z.x);
+        pz.y = lane_xor1(z.y);
+        v[r] = q1 ? pz - z : z + pz;
+    }
+}
+
+// the row pass's tables (zpass_setup) and exchange slots
+template <typename R>
+struct Row128Lds {
+    cx<R> xch[4 * kRow128Slots];
+    cx<R> twz[128], twc[128];
+    cx<double> halfz[128], rowz[16], lamy[16];
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_zrow128_fwd(Grid g, DeviceTables tb, const cx<R>* __restrict__ y,
+                                                      cx<R>* __restrict__ u) {
+    __shared__ Row128Lds<R> S;
+    constexpr int N3 = 128;
+    const int n2 = g.n2;
+    const long n = (long)g.n1 * n2 * N3, np = (long)n2 * N3;
+    const KSel ks = select_k(g, n);
+    const int i = blockIdx.x, v = blockIdx.y, j0 = blockIdx.z * 16;
+    const int rows = min(16, n2 - j0);
+    const cx<double> L0 = zpass_setup<R>(g, ks, tb, i, j0, rows, S.twz, S.twc, S.halfz, S.rowz, S.lamy);
+    const int tid = threadIdx.x, w = tid >> 6, gl = (tid >> 4) & 3, q = tid & 15;
+    const int r = 4 * w + gl;
+    const bool valid = r < rows;
+    const int rr = valid ? r : 0;                  // rows past the grid compute on row 0 and store nothing
+    const long base = (long)i * np + (long)(j0 + rr) * N3;
+    const cx<R>* y1 = y + (long)v * 2 * n + base;
+    const unsigned char* codes = ks.codes + base;
+    cx<R> a[8], b[8];
+    int code[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        a[m] = y1[q + 16 * m];
+        b[m] = y1[n + q + 16 * m];
+        code[m] = codes[q + 16 * m];
+    }
+    const int M = n2 * N3;
+    int s3m = g.s3 % M;
+    if (s3m < 0) s3m += M;
+    const double idz = 1.0 / g.dlt[2];
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    __syncthreads();
+    // u_l = W_l1 y1 + W_l2 y2, W formed once per mode
+    cx<R> uu[3][8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int k = q + 16 * m;
+        uu[0][m] = uu[1][m] = uu[2][m] = mk<R>((R)0, (R)0);
+        if (code[m] != kMasked) {
+            const cx<double> h = cmul(S.halfz[k], S.rowz[rr]);
+            const cx<double> L2 = lam_from_halfturn(h.y, h.x, idz);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                cx<R> w1, w2;
+                w_row_code<R>(L0, S.lamy[rr], L2, code[m], l, &w1, &w2);
+                uu[l][m] = cmul(w1, a[m]) + cmul(w2, b[m]);
+            }
+        }
+    }
+    // z twiddles of this lane's outputs c = (q >> 1) + 8 s + 64 (q & 1)
+    const unsigned jm = ((unsigned)(j0 + rr) * (unsigned)s3m) % (unsigned)M;
+    cx<R> zt[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int c = (q >> 1) + 8 * s + 64 * (q & 1);
+        zt[s] = cmul(S.twc[c], rot[((unsigned)c * jm) % (unsigned)M]);
+    }
+    cx<R>* xb = S.xch + w * kRow128Slots + gl * 144;
+    cx<R>* ub = u + (long)v * 3 * n + base;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        line128<R, +1>(uu[l], S.twz, xb, q);
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) ub[(long)l * n + (q >> 1) + 8 * s + 64 * (q & 1)] = cmul(uu[l][s], zt[s]);
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_zrow128_adj(Grid g, DeviceTables tb, const cx<R>* __restrict__ u,
+                                                      cx<R>* __restrict__ z) {
+    __shared__ Row128Lds<R> S;
+    constexpr int N3 = 128;
+    const int n2 = g.n2;
+    const long n = (long)g.n1 * n2 * N3, np = (long)n2 * N3;
+    const KSel ks = select_k(g, n);
+    const int i = blockIdx.x, v = blockIdx.y, j0 = blockIdx.z * 16;
+    const int rows = min(16, n2 - j0);
+    const cx<double> L0 = zpass_setup<R>(g, ks, tb, i, j0, rows, S.twz, S.twc, S.halfz, S.rowz, S.lamy);
+    const int tid = threadIdx.x, w = tid >> 6, gl = (tid >> 4) & 3, q = tid & 15;
+    const int r = 4 * w + gl;
+    const bool valid = r < rows;
+    const int rr = valid ? r : 0;
+    const long base = (long)i * np + (long)(j0 + rr) * N3;
+    const cx<R>* ub = u + (long)v * 3 * n + base;
+    cx<R> tin[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) tin[m] = ub[q + 16 * m];
+    const int M = n2 * N3;
+    int s3m = g.s3 % M;
+    if (s3m < 0) s3m += M;
+    const double idz = 1.0 / g.dlt[2];
+    const cx<R>* rot = sizeof(R) == 8 ? (const cx<R>*)tb.rot64 : (const cx<R>*)tb.rot32;
+    __syncthreads();
+    // z twiddles of this lane's inputs c = q + 16 m (conjugated below)
+    const unsigned jm = ((unsigned)(j0 + rr) * (unsigned)s3m) % (unsigned)M;
+    cx<R> zt[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int c = q + 16 * m;
+        zt[m] = cmul(S.twc[c], rot[((unsigned)c * jm) % (unsigned)M]);
+    }
+    cx<R>* xb = S.xch + w * kRow128Slots + gl * 144;
+    cx<R> s3[3][8];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) s3[l][m] = cmulc(tin[m], zt[m]);
+        if (l < 2) {      // the next component's input, in flight during this component's transform
+#pragma unroll
+            for (int m = 0; m < 8; ++m) tin[m] = ub[(long)(l + 1) * n + q + 16 * m];
+        }
+        line128<R, -1>(s3[l], S.twz, xb, q);
+    }
+    // z = W^H s for this lane's modes k = (q >> 1) + 8 s + 64 (q & 1)
+    const unsigned char* codes = ks.codes + base;
+    cx<R>* zb = z + (long)v * 2 * n + base;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int k = (q >> 1) + 8 * s + 64 * (q & 1);
+        const int code = codes[k];
+        cx<R> a1 = mk<R>((R)0, (R)0), a2 = a1;
+        if (code != kMasked) {
+            const cx<double> h = cmul(S.halfz[k], S.rowz[rr]);
+            const cx<double> L2 = lam_from_halfturn(h.y, h.x, idz);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                cx<R> w1, w2;
+                w_row_code<R>(L0, S.lamy[rr], L2, code, l, &w1, &w2);
+                a1 = a1 + cmulc(s3[l][s], w1);
+                a2 = a2 + cmulc(s3[l][s], w2);
+            }
+        }
+        if (valid) {
+            zb[k] = a1;
+            zb[n + k] = a2;
+        }
+    }
+}
+
 template <typename R>
 static hipError_t split_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* y, cx<R>* t, cx<R>* u, int nvec,
                             hipStream_t st) {
@@ -728,8 +936,11 @@ static hipError_t split_fwd(const Grid& g, const DeviceTables& tb, const cx<R>* 
     // a timed pair: the start event at the first kernel's start, the stop event at the second's end
     const LaunchTimer pair = g_launch_timer;
     g_launch_timer.stop = nullptr;
-    PCX_LAUNCH((k_zpass_fwd<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
-                       zpass_lds_bytes<R>(RB, g.n3), st, g, tb, y, u, RB);
+    if (g.n3 == 128)
+        PCX_LAUNCH((k_zrow128_fwd<R>), dim3(g.n1, nvec, (g.n2 + 15) / 16), dim3(256), 0, st, g, tb, y, u);
+    else
+        PCX_LAUNCH((k_zpass_fwd<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+                           zpass_lds_bytes<R>(RB, g.n3), st, g, tb, y, u, RB);
     hipError_t e = hipGetLastError();
     g_launch_timer = {nullptr, pair.stop};
     if (e == hipSuccess) {
@@ -752,8 +963,12 @@ static hipError_t split_adj(const Grid& g, const DeviceTables& tb, const cx<R>* 
     hipError_t e = hipGetLastError();
     g_launch_timer = {nullptr, pair.stop};
     if (e == hipSuccess) {
-        PCX_LAUNCH((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
-                           zpass_lds_bytes<R>(RB, g.n3), st, g, tb, u, z, RB);
+        // FP64 adjoint: the register version needs 256 VGPRs (one wavefront per SIMD) and gains nothing
+        if (g.n3 == 128 && sizeof(R) == 4)
+            PCX_LAUNCH((k_zrow128_adj<R>), dim3(g.n1, nvec, (g.n2 + 15) / 16), dim3(256), 0, st, g, tb, u, z);
+        else
+            PCX_LAUNCH((k_zpass_adj<R>), dim3(g.n1, nvec, (g.n2 + RB - 1) / RB), dim3(256),
+                               zpass_lds_bytes<R>(RB, g.n3), st, g, tb, u, z, RB);
         e = hipGetLastError();
     }
     g_launch_timer = pair;

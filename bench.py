@@ -20,12 +20,16 @@ than the 256 MB last-level cache); and the FP64 CPU oracle's matvec rate on this
 with its estimated seconds per k-point, as a reference.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--mode fp32_refine|fp64|fp32]
-                    [--no-cpu-baseline] [--profile-kernels] [--workload fcc_diamond|gyroid_sweep|gyroid_bands]
+                    [--no-cpu-baseline] [--profile-kernels]
+                    [--workload fcc_diamond|gyroid_sweep|gyroid_bands|triclinic128]
 
 --workload gyroid_sweep times the single-gyroid permittivity sweep of Section 6 instead (BCC 64^3,
 eps 3..30, one plan per eps, all ten solved as one batch at the N point); its roofline block runs
 on the eps = 12 plan.  --workload gyroid_bands solves the same ten plans along G-H-N-G-P-H with 10
-parts per segment (510 problems per step; run it with --steps 1 --warmup 0).
+parts per segment (510 problems per step; run it with --steps 1 --warmup 0).  --workload
+triclinic128 solves the largest configuration, a seeded triclinic lattice at 128^3 with 20 bands at
+16 wave vectors as one batch (about 26 s per step; --steps 1 --warmup 0), its roofline block on 8
+vectors.
 """
 from __future__ import annotations
 
@@ -194,11 +198,12 @@ def setup(torch, max_vectors: int):
     return plan, kappa, eps, g
 
 
-def roofline_block(torch, plan, kappa, fp64: bool, reps: int, warmup_s: float = ROOF_WARMUP_S):
+def roofline_block(torch, plan, kappa, fp64: bool, reps: int, warmup_s: float = ROOF_WARMUP_S,
+                   vectors: int = ROOF_VECTORS):
     import pcx_synth as S
     n = plan.n
     dt = torch.complex128 if fp64 else torch.complex64
-    y = torch.from_numpy(np.ascontiguousarray(S.random_block(3, 2 * n, ROOF_VECTORS).T)).to(dtype=dt, device="cuda")
+    y = torch.from_numpy(np.ascontiguousarray(S.random_block(3, 2 * n, vectors).T)).to(dtype=dt, device="cuda")
     z = torch.empty_like(y)
     # sustained warm-up: after the host-side set-up above the GPU has idled, and its clocks take
     # some 30 ms of load to return to their steady state (the first applications run up to 15 %
@@ -212,12 +217,12 @@ def roofline_block(torch, plan, kappa, fp64: bool, reps: int, warmup_s: float = 
     per = kernel_bytes_per_vector(n, fp64)
     out = {}
     for nm, t in zip(names, ms):
-        b = per[nm] * ROOF_VECTORS
+        b = per[nm] * vectors
         out[nm] = {"ms": t, "bytes": b, "gbs": b / (t * 1e-3) / 1e9}
     tot_ms = sum(ms)
-    tot_b = sum(per.values()) * ROOF_VECTORS
+    tot_b = sum(per.values()) * vectors
     return out, {"ms": tot_ms, "bytes": tot_b, "gbs": tot_b / (tot_ms * 1e-3) / 1e9,
-                 "matvecs_per_s": ROOF_VECTORS / (tot_ms * 1e-3)}
+                 "matvecs_per_s": vectors / (tot_ms * 1e-3)}
 
 
 _CPU_JOB = {}
@@ -415,6 +420,86 @@ def run_gyroid_sweep(args, torch, mode, cpu):
     print(json.dumps(out))
 
 
+TRI_GRID = (128, 128, 128)
+TRI_NEV, TRI_TOL, TRI_VECTORS = 20, 1e-9, 8
+
+
+def run_triclinic128(args, torch, mode):
+    """The largest workload: a seeded triclinic lattice (seed 5) at 128^3, random spheres filled to
+    30 % with eps = 13, 20 bands at 16 seeded wave vectors, solved as one pcx_solve_batch call (one
+    step).  Its planes (128 x 128) take the two-pass plane path; the roofline block is 8 vectors
+    (a 1.1 GB FP32 working set, beyond the last-level cache), with the 3-pass algorithmic bytes."""
+    import pcx_synth as S
+    from paper_1806_10284_amd import PCX_EPS_VOXEL, Plan, pcx_geometry, pcx_solve_batch
+    avec = S.triclinic(5)
+    g = pcx_geometry(avec, *TRI_GRID)
+    vox = S.random_sphere_fill(avec, TRI_GRID, tuple(g.shift), seed=5)
+    kappas = [tuple(k) for k in S.random_kappas(55, 16)]
+    plan = Plan(g, max_vectors=32)
+    plan.pcx_plan_set_eps(vox, PCX_EPS_VOXEL)
+    print(f"[bench] setup done: triclinic(5) {TRI_GRID}, {len(kappas)} wave vectors", file=sys.stderr, flush=True)
+    workers = args.workers or 2
+
+    def one_batch():
+        t = time.perf_counter()
+        lam, _, st = pcx_solve_batch([(plan, kappas)], TRI_NEV, mode=mode, tol=TRI_TOL, nworkers=workers)
+        return lam, st, time.perf_counter() - t
+
+    for w in range(args.warmup):
+        _, st, s_el = one_batch()
+        print(f"[bench] warmup {w}: {s_el:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    matvecs = applies = applies32 = 0
+    iters = []
+    for s in range(args.steps):
+        lam, st, s_el = one_batch()
+        matvecs += sum(x.matvecs for x in st)
+        applies += sum(x.matvecs + x.precond_applies for x in st)
+        applies32 += sum(x.matvecs_fp32 + x.precond_applies_fp32 for x in st)
+        iters.append([x.iterations for x in st])
+        print(f"[bench] step {s}: iterations {iters[-1]}, {s_el:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern, tot = roofline_block(torch, plan, kappas[0], args.mode == "fp64", args.reps, vectors=TRI_VECTORS)
+    dominant = max(kern, key=lambda k: kern[k]["ms"])
+    dk = kern[dominant]
+    print(f"[bench] roofline block: {json.dumps(kern)}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "nullspace-free matvecs/s + HBM GB/s vs peak; s per k-point, 20 bands at 128^3",
+        "value": matvecs / el,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32_refine": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.mode],
+        "data": "synthetic",
+        "config": {"workload": "triclinic (seed 5) 128^3, random spheres eps 13 filling 30 %, 16 seeded wave "
+                               "vectors in one batch, 20 smallest positive eigenvalues",
+                   "grid": list(TRI_GRID), "nev": TRI_NEV, "mode": args.mode, "solver": "lobpcg",
+                   "workers": workers},
+        "s_per_kpoint": el / args.steps / len(kappas),
+        "solve": {"iterations": iters, "matvecs_per_step": matvecs / args.steps,
+                  "operator_applications_per_step": applies / args.steps,
+                  "fp32_application_fraction": applies32 / max(applies, 1), "tol": TRI_TOL,
+                  "lambda_first_wave_vector": [float(x) for x in lam[0]]},
+        "block_matvec": {"vectors": TRI_VECTORS, "precision": "fp64" if args.mode == "fp64" else "fp32",
+                         "matvecs_per_s": tot["matvecs_per_s"], "gbs": tot["gbs"],
+                         "frac_of_peak": tot["gbs"] / HBM_PEAK_GBS,
+                         "kernels": {k: {"ms": v["ms"], "gbs": v["gbs"]} for k, v in kern.items()}},
+        # counters were taken on the FCC diamond workload; the two-pass planes move 236n B (FP32)
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": dk["bytes"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,12 +508,15 @@ def main():
     ap.add_argument("--mode", default="fp32_refine", choices=["fp32_refine", "fp64", "fp32"])
     ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "lanczos"],
                     help="lanczos: the paper's driver (inverse Lanczos, CG inner solves, FP64; --mode ignored)")
-    ap.add_argument("--workload", default="fcc_diamond", choices=["fcc_diamond", "gyroid_sweep", "gyroid_bands"],
+    ap.add_argument("--workload", default="fcc_diamond",
+                    choices=["fcc_diamond", "gyroid_sweep", "gyroid_bands", "triclinic128"],
                     help="gyroid_sweep: BCC single gyroid 64^3, eps 3..30 as one batch of 10 plans at N; "
-                         "gyroid_bands: the same ten plans along G-H-N-G-P-H, 10 parts per segment")
+                         "gyroid_bands: the same ten plans along G-H-N-G-P-H, 10 parts per segment; "
+                         "triclinic128: a seeded triclinic 128^3, 20 bands at 16 wave vectors in one batch "
+                         "(no CPU baseline)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--workers", type=int, default=0,
-                    help="gyroid workloads: batch worker threads (0: the library's default, 4)")
+                    help="batch workloads: worker threads (0: 4 for the gyroid, 2 for triclinic128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the 32-vector A_r block (and a calibration copy) for rocprofv3 counters")
@@ -453,7 +541,7 @@ def main():
         args.mode = "fp64"
     # the CPU baseline runs first, in forked processes, before anything initialises the GPU
     cpu = None
-    if not args.no_cpu_baseline and not args.profile_kernels:
+    if not args.no_cpu_baseline and not args.profile_kernels and args.workload != "triclinic128":
         cpu = cpu_baseline_for(args.workload)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
     import torch
@@ -464,6 +552,8 @@ def main():
         if args.solver != "lobpcg" or args.profile_kernels:
             print(f"--workload {args.workload} runs the batched LOBPCG solver only", file=sys.stderr)
             sys.exit(2)
+        if args.workload == "triclinic128":
+            return run_triclinic128(args, torch, mode)
         return run_gyroid_sweep(args, torch, mode, cpu)
     plan, kappa, eps, g = setup(torch, max_vectors=ROOF_VECTORS)
     print(f"[bench] setup done: FCC diamond {N_GRID}, kappa {kappa.tolist()}", file=sys.stderr, flush=True)

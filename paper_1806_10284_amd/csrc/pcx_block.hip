@@ -775,15 +775,17 @@ __global__ void __launch_bounds__(256) k_combine(ColSet S, const cx<double>* __r
 #ifndef PCX_COMB_AHEAD
 #define PCX_COMB_AHEAD 2
 #endif
-constexpr int kCombMaxK = 48;
+constexpr int kCombMaxK = 48;                      // inputs of the one-block-per-SIMD-pair variant
+constexpr int kCombMaxK2 = 96;                     // inputs of the large variant (up to 98 KB of LDS)
 constexpr int kCombRT = PCX_COMB_RT;               // row tiles per wave and pass
 constexpr int kCombAhead = PCX_COMB_AHEAD;         // K steps the S loads run ahead
 
-template <typename R, int NTO>
-__global__ void __launch_bounds__(256) k_combine_mfma(ColSet S, const cx<double>* __restrict__ C, ColSet Y, long N) {
+template <typename R, int NTO, int KMAX>
+__global__ void __launch_bounds__(256) k_combine_mfma(ColSet S, const cx<double>* __restrict__ C, int ldc, ColSet Y,
+                                                       long N) {
     constexpr int CR = kCombRT, AH = kCombAhead;
-    __shared__ double cp[(kCombMaxK / 4) * 2 * NTO * 16];   // C' tiles [K step][Re, Im][output tile][k][j]
-    __shared__ const cx<R>* scol[kCombMaxK];
+    __shared__ double cp[(KMAX / 4) * 2 * NTO * 16];        // C' tiles [K step][Re, Im][output tile][k][j]
+    __shared__ const cx<R>* scol[KMAX];
     __shared__ cx<R>* ycol[2 * NTO];
     const int ks = S.total(), m = Y.total();
     const int nks = (ks + 3) / 4;                            // K steps (four complex columns each)
@@ -796,7 +798,7 @@ __global__ void __launch_bounds__(256) k_combine_mfma(ColSet S, const cx<double>
         const int c = 4 * s + k, o = 4 * t + j, u = o >> 1, pp = o & 1;
         double v = 0.0;
         if (c < ks && u < m) {
-            const cx<double> cc = C[(size_t)c * m + u];
+            const cx<double> cc = C[(size_t)c * ldc + u];
             v = p == 0 ? (pp == 0 ? cc.x : cc.y) : (pp == 0 ? -cc.y : cc.x);
         }
         cp[e] = v;
@@ -863,39 +865,80 @@ __global__ void __launch_bounds__(256) k_combine_mfma(ColSet S, const cx<double>
 }
 
 template <typename R, int NTO>
-static hipError_t combine_mfma_impl(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
+static hipError_t combine_mfma_impl(const ColSet& S, const cx<double>* C, int ldc, const ColSet& Y, long N,
+                                    hipStream_t st) {
     long blocks = (N + 16L * kCombRT * 4 - 1) / (16L * kCombRT * 4);
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((k_combine_mfma<R, NTO>), dim3((unsigned)blocks), dim3(256), 0, st, S, C, Y, N);
+    if (S.total() <= kCombMaxK)
+        hipLaunchKernelGGL((k_combine_mfma<R, NTO, kCombMaxK>), dim3((unsigned)blocks), dim3(256), 0, st, S, C, ldc,
+                           Y, N);
+    else
+        hipLaunchKernelGGL((k_combine_mfma<R, NTO, kCombMaxK2>), dim3((unsigned)blocks), dim3(256), 0, st, S, C,
+                           ldc, Y, N);
     return hipGetLastError();
 }
 
+// columns [c0, c0 + nc) of A (runs of columns of length N, complex R)
+template <typename R>
+static ColSet col_subset(const ColSet& A, int c0, int nc, long N) {
+    ColSet s = colset(nullptr, 0);
+    int q = 0, at = 0;
+    for (int r = 0; r < kMaxSeg && nc > 0; ++r) {
+        const int n = A.ncols[r];
+        if (c0 < at + n) {
+            const int off = c0 - at, take = std::min(n - off, nc);
+            s.ptr[q] = (char*)A.ptr[r] + (size_t)off * N * sizeof(cx<R>);
+            s.ncols[q] = take;
+            ++q;
+            c0 += take;
+            nc -= take;
+        }
+        at += n;
+    }
+    return s;
+}
+
+template <typename R>
+static hipError_t combine_mfma_chunk(const ColSet& S, const cx<double>* C, int ldc, const ColSet& Y, long N,
+                                     hipStream_t st) {
+    switch ((Y.total() + 1) / 2) {
+        case 1: return combine_mfma_impl<R, 1>(S, C, ldc, Y, N, st);
+        case 2: return combine_mfma_impl<R, 2>(S, C, ldc, Y, N, st);
+        case 3: return combine_mfma_impl<R, 3>(S, C, ldc, Y, N, st);
+        case 4: return combine_mfma_impl<R, 4>(S, C, ldc, Y, N, st);
+        case 5: return combine_mfma_impl<R, 5>(S, C, ldc, Y, N, st);
+        case 6: return combine_mfma_impl<R, 6>(S, C, ldc, Y, N, st);
+        case 7: return combine_mfma_impl<R, 7>(S, C, ldc, Y, N, st);
+        case 8: return combine_mfma_impl<R, 8>(S, C, ldc, Y, N, st);
+        case 9: return combine_mfma_impl<R, 9>(S, C, ldc, Y, N, st);
+        case 10: return combine_mfma_impl<R, 10>(S, C, ldc, Y, N, st);
+        case 11: return combine_mfma_impl<R, 11>(S, C, ldc, Y, N, st);
+        case 12: return combine_mfma_impl<R, 12>(S, C, ldc, Y, N, st);
+        case 13: return combine_mfma_impl<R, 13>(S, C, ldc, Y, N, st);
+        case 14: return combine_mfma_impl<R, 14>(S, C, ldc, Y, N, st);
+        case 15: return combine_mfma_impl<R, 15>(S, C, ldc, Y, N, st);
+        default: return combine_mfma_impl<R, 16>(S, C, ldc, Y, N, st);
+    }
+}
+
+// Y = S C for up to kCombMaxK2 inputs: the outputs in chunks of at most 32 columns (each chunk reads
+// S again), the coefficient block of a chunk taken in place (row stride m)
 template <typename R>
 static hipError_t combine_mfma(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
-    switch ((Y.total() + 1) / 2) {
-        case 1: return combine_mfma_impl<R, 1>(S, C, Y, N, st);
-        case 2: return combine_mfma_impl<R, 2>(S, C, Y, N, st);
-        case 3: return combine_mfma_impl<R, 3>(S, C, Y, N, st);
-        case 4: return combine_mfma_impl<R, 4>(S, C, Y, N, st);
-        case 5: return combine_mfma_impl<R, 5>(S, C, Y, N, st);
-        case 6: return combine_mfma_impl<R, 6>(S, C, Y, N, st);
-        case 7: return combine_mfma_impl<R, 7>(S, C, Y, N, st);
-        case 8: return combine_mfma_impl<R, 8>(S, C, Y, N, st);
-        case 9: return combine_mfma_impl<R, 9>(S, C, Y, N, st);
-        case 10: return combine_mfma_impl<R, 10>(S, C, Y, N, st);
-        case 11: return combine_mfma_impl<R, 11>(S, C, Y, N, st);
-        case 12: return combine_mfma_impl<R, 12>(S, C, Y, N, st);
-        case 13: return combine_mfma_impl<R, 13>(S, C, Y, N, st);
-        case 14: return combine_mfma_impl<R, 14>(S, C, Y, N, st);
-        case 15: return combine_mfma_impl<R, 15>(S, C, Y, N, st);
-        default: return combine_mfma_impl<R, 16>(S, C, Y, N, st);
+    const int m = Y.total();
+    const int nc = (m + 31) / 32, per = (m + nc - 1) / nc;
+    for (int u0 = 0; u0 < m; u0 += per) {
+        const int mc = std::min(per, m - u0);
+        const hipError_t e = combine_mfma_chunk<R>(S, C + u0, m, col_subset<R>(Y, u0, mc, N), N, st);
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 template <typename R>
 hipError_t launch_combine(const ColSet& S, const cx<double>* C, const ColSet& Y, long N, hipStream_t st) {
     if (S.total() < 1 || Y.total() < 1 || S.total() > kMaxCols || Y.total() > kMaxCols) return hipErrorInvalidValue;
-    if (S.total() <= kCombMaxK && Y.total() <= 32) return combine_mfma<R>(S, C, Y, N, st);
+    if (S.total() <= kCombMaxK2) return combine_mfma<R>(S, C, Y, N, st);
     const long span = 256L * kRowsPerThread;
     long blocks = (N + span - 1) / span;
     if (blocks > 8192) blocks = 8192;

@@ -617,6 +617,86 @@ static hipError_t gram_impl(const ColSet& A, const ColSet& B, long N, cx<double>
     return hipGetLastError();
 }
 
+// columns [c0, c0 + nc) of A (runs of columns of length N, complex R)
+template <typename R>
+static ColSet col_subset(const ColSet& A, int c0, int nc, long N) {
+    ColSet s = colset(nullptr, 0);
+    int q = 0, at = 0;
+    for (int r = 0; r < kMaxSeg && nc > 0; ++r) {
+        const int n = A.ncols[r];
+        if (c0 < at + n) {
+            const int off = c0 - at, take = std::min(n - off, nc);
+            s.ptr[q] = (char*)A.ptr[r] + (size_t)off * N * sizeof(cx<R>);
+            s.ncols[q] = take;
+            ++q;
+            c0 += take;
+            nc -= take;
+        }
+        at += n;
+    }
+    return s;
+}
+
+// a tile of a Hermitian product into the full output: the tile's upper-triangle entries (local
+// column >= local row, in each of its nh halves) at rows / columns gmap[] of the full ka x nh ka
+// matrix
+struct TileMap {
+    int g[kMfmaMaxA];
+};
+__global__ void k_scatter_tile(const cx<double>* __restrict__ tile, int kp, int nh, TileMap gm, int ka,
+                               cx<double>* __restrict__ out) {
+    const int kbp = nh * kp;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kp * kbp; e += gridDim.x * blockDim.x) {
+        const int r = e / kbp, cc = e % kbp, h = cc / kp, c = cc % kp;
+        if (c >= r) out[(size_t)gm.g[r] * nh * ka + (size_t)h * ka + gm.g[c]] = tile[e];
+    }
+}
+
+// Hermitian A^H [A | AA] for ka above the matrix-core kernel's width: the ka columns in groups of
+// at most 24, one matrix-core product per pair of groups (the columns of both groups, and of their
+// halves in B), each tile's upper triangle scattered into out.  Every group pair is read once, so
+// the columns are read (groups - 1) times in all.
+template <typename R>
+static hipError_t gram_mfma_tiled(const ColSet& B, int ka, int nh, long N, cx<double>* part, int nchunk,
+                                  cx<double>* out, hipStream_t st) {
+    const int G = (ka + 23) / 24;
+    int g0[8], gn[8];
+    for (int g = 0, at = 0; g < G; ++g) {
+        gn[g] = (ka - at + (G - g) - 1) / (G - g);
+        g0[g] = at;
+        at += gn[g];
+    }
+    for (int i = 0; i < G; ++i)
+        for (int j = i + 1; j < G; ++j) {
+            const int kp = gn[i] + gn[j];
+            ColSet Bp = concat(col_subset<R>(B, g0[i], gn[i], N), col_subset<R>(B, g0[j], gn[j], N));
+            if (nh == 2)
+                Bp = concat(Bp, concat(col_subset<R>(B, ka + g0[i], gn[i], N), col_subset<R>(B, ka + g0[j], gn[j], N)));
+            int segs = 0;
+            for (int q = 0; q < kMaxSeg; ++q) segs += Bp.ncols[q] > 0;
+            if (Bp.total() != nh * kp) return hipErrorInvalidValue;     // more runs than a ColSet holds
+            (void)segs;
+            const long groups = std::min<long>(nchunk, mfma_groups(kp));
+            const DmaShape d = dma_shape(kp, nh * kp, sizeof(R) == 8);
+            const long SR = (long)d.sub * (sizeof(R) == 8 ? 16 : 32);
+            long rpc = (N + groups - 1) / groups;
+            rpc = (rpc + SR - 1) / SR * SR;
+            const int chunks = (int)((N + rpc - 1) / rpc);
+            const int count = kp * nh * kp;
+            cx<double>* tile = part + (size_t)(chunks + kRedGroups) * count;
+            hipError_t e = gram_mfma<R>(Bp, kp, N, part, chunks, rpc, st);
+            if (e == hipSuccess) e = reduce_chunks(part, chunks, count, tile, st);
+            if (e != hipSuccess) return e;
+            TileMap gm;
+            for (int r = 0; r < gn[i]; ++r) gm.g[r] = g0[i] + r;
+            for (int r = 0; r < gn[j]; ++r) gm.g[gn[i] + r] = g0[j] + r;
+            hipLaunchKernelGGL(k_scatter_tile, dim3((count + 255) / 256), dim3(256), 0, st, tile, kp, nh, gm, ka, out);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
 template <typename R>
 hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* part, int nchunk, cx<double>* out,
                        hipStream_t st, bool herm) {
@@ -625,6 +705,8 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     if (herm && kb != ka && kb != 2 * ka) return hipErrorInvalidValue;
     hipError_t e;
     int chunks;
+    if (herm && ka > kMfmaMaxA && ka <= 2 * kMfmaMaxA && (kb == ka || kb == 2 * ka))
+        return gram_mfma_tiled<R>(B, ka, kb / ka, N, part, nchunk, out, st);
     if (herm && ka <= kMfmaMaxA) {
         // matrix-core path: at most kMfmaGroups row chunks
         const long groups = std::min<long>(nchunk, mfma_groups(ka));
@@ -878,25 +960,7 @@ static hipError_t combine_mfma_impl(const ColSet& S, const cx<double>* C, int ld
     return hipGetLastError();
 }
 
-// columns [c0, c0 + nc) of A (runs of columns of length N, complex R)
-template <typename R>
-static ColSet col_subset(const ColSet& A, int c0, int nc, long N) {
-    ColSet s = colset(nullptr, 0);
-    int q = 0, at = 0;
-    for (int r = 0; r < kMaxSeg && nc > 0; ++r) {
-        const int n = A.ncols[r];
-        if (c0 < at + n) {
-            const int off = c0 - at, take = std::min(n - off, nc);
-            s.ptr[q] = (char*)A.ptr[r] + (size_t)off * N * sizeof(cx<R>);
-            s.ncols[q] = take;
-            ++q;
-            c0 += take;
-            nc -= take;
-        }
-        at += n;
-    }
-    return s;
-}
+
 
 template <typename R>
 static hipError_t combine_mfma_chunk(const ColSet& S, const cx<double>* C, int ldc, const ColSet& Y, long N,

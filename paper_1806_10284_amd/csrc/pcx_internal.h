@@ -132,7 +132,7 @@ hipError_t configure_fixed_kernels();
 
 // ---- block operations (pcx_block.hip) ----
 // A set of vectors of length N given as up to kMaxSeg runs of contiguous columns (column stride N).
-constexpr int kMaxSeg = 6;
+constexpr int kMaxSeg = 8;
 struct ColSet {
     void* ptr[kMaxSeg];
     int ncols[kMaxSeg];

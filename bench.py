@@ -132,6 +132,14 @@ def summarize_traffic(fetch_csv: str, write_csv: str, out_json: str):
     return out
 
 
+# the two passes of the planes that take the two-pass path (trace summaries only)
+SPLIT_KEYS = [(f"pcx::{k}<{t}", f"{lab}_{p}") for k, lab in
+              (("k_zrow128_fwd", "rows_fwd"), ("k_zpass_fwd", "rows_fwd"), ("k_ypass_fwd", "cols_fwd"),
+               ("k_ycol128_adj", "cols_adj"), ("k_ypass_adj", "cols_adj"), ("k_zrow128_adj", "rows_adj"),
+               ("k_zpass_adj", "rows_adj"))
+              for t, p in (("float", "fp32"), ("double", "fp64"))]
+
+
 def summarize_trace(trace_csv: str, last: int = 20) -> str:
     """Markdown table of the A_r kernels' dispatch durations in a rocprofv3 --kernel-trace file,
     grouped by vector count (the grid's y extent): calls, mean, and the mean of the last `last`
@@ -143,7 +151,8 @@ def summarize_trace(trace_csv: str, last: int = 20) -> str:
     groups = defaultdict(list)
     for r in rows:
         name = r["Kernel_Name"]
-        key = next((k for p, k in KERNEL_KEYS if name.startswith("void " + p) or name.startswith(p)), None)
+        key = next((k for p, k in KERNEL_KEYS + SPLIT_KEYS if name.startswith("void " + p) or name.startswith(p)),
+                   None)
         if key:
             groups[(key, int(r["Grid_Size_Y"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
     # the solves: every dispatch before the first plane kernel of the roofline block

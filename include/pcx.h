@@ -146,6 +146,22 @@ int pcx_apply_QS_adjoint(pcx_plan *p, const double kappa[3], int precision, cons
 /* x = B^{-1} Q_r Sigma_r y (Theorem 5.2): the GEP eigenvector for an NFSEP one. Device. */
 int pcx_eigvec(pcx_plan *p, const double kappa[3], int precision, const void *y, void *x, int nvec);
 
+/* The dense products of the block eigensolver's Rayleigh-Ritz step (Section 5.2), as the solver
+ * runs them (FP64 accumulation; FP64 matrix cores for Hermitian bases of up to 96 columns and for
+ * combinations of up to 96 inputs, VALU kernels beyond).  Column blocks on the device: column c of
+ * a block of k columns of length len starts at base + c * len, complex in `precision`.
+ * pcx_block_gram: g = A^H B into the HOST array g (ka x kb complex128, row-major), synchronous.
+ *   herm = 1: B = [A | A2] (b = A2, kb = 2 ka) or B = A (b = NULL, kb = ka), with A^H A2 Hermitian;
+ *   only the upper triangle of each ka x ka half is formed and the lower one mirrored from it.
+ *   herm = 0: B = b (kb columns), the general product.
+ * pcx_block_combine: y = s c, s (ks columns) and y (m columns) on the device, c a HOST array (ks x m
+ *   complex128, row-major); synchronous.  y may not overlap s.
+ * len <= 2n of the plan is not required: any len >= 1.  Errors: PCX_E_ARG (null pointers, sizes
+ * outside [1, 3 PCX_MAX_BLOCK], herm with kb != ka, 2 ka), PCX_E_OOM, PCX_E_DEVICE. */
+int pcx_block_gram(pcx_plan *p, int precision, const void *a, int ka, const void *b, int kb, long len, int herm,
+                   double *g);
+int pcx_block_combine(pcx_plan *p, int precision, const void *s, int ks, const double *c, int m, void *y, long len);
+
 /* LOBPCG preconditioners for A_r = Sigma_r Q_r^* B^{-1} Q_r Sigma_r (Section 5.2, eq. NFSEP).
  *   PCX_PRECOND_NONE:    none.
  *   PCX_PRECOND_DIAG:    D = Sigma_r^{-2} = Lambda_q^{-1} per mode (zero on a masked mode); the

@@ -106,6 +106,10 @@ _SIGS = [
                                              ctypes.c_void_p, ctypes.c_int]),
     ("pcx_eigvec", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int]),
+    ("pcx_block_gram", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_long, ctypes.c_int, ctypes.c_void_p]),
+    ("pcx_block_combine", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long]),
     ("pcx_opts_default", None, [ctypes.POINTER(PcxOpts)]),
     ("pcx_solve", ctypes.c_int, [ctypes.c_void_p, c_double3, ctypes.c_int, ctypes.POINTER(PcxOpts),
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PcxStats)]),

@@ -286,6 +286,48 @@ class Plan:
         opts.precondition, opts.verbose = _precond(precondition), int(bool(verbose))
         return opts
 
+    # -- the Rayleigh-Ritz products (Section 5.2), for tests and tools
+    @staticmethod
+    def _cols(t, name):
+        torch = _torch()
+        if t.device.type != "cuda" or t.dim() != 2 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous 2-D device tensor (columns x length)")
+        if t.dtype not in (torch.complex128, torch.complex64):
+            raise ValueError(f"{name} must be complex128 or complex64")
+        return L.PCX_FP64 if t.dtype == torch.complex128 else L.PCX_FP32
+
+    def pcx_block_gram(self, a, b=None, herm: bool = True):
+        """G = A^H B (numpy complex128, ka x kb) for column blocks a (ka, len) and b (kb, len); herm:
+        B = [A | b] (or A when b is None) with Hermitian halves, formed on their upper triangles."""
+        prec = self._cols(a, "a")
+        ka, n = a.shape
+        if b is not None:
+            if self._cols(b, "b") != prec or b.shape[1] != n:
+                raise ValueError("a and b need the same precision and length")
+        elif not herm:
+            raise ValueError("the general product needs b")
+        kb = (ka if b is None else 2 * ka) if herm else b.shape[0]
+        if herm and b is not None and b.shape[0] != ka:
+            raise ValueError("herm: b must have as many columns as a")
+        g = np.zeros((ka, kb), dtype=np.complex128)
+        L.check(self._lib.pcx_block_gram(self._ptr, prec, ctypes.c_void_p(a.data_ptr()), ka,
+                                         ctypes.c_void_p(b.data_ptr()) if b is not None else None, kb, n, int(herm),
+                                         g.ctypes.data_as(ctypes.c_void_p)))
+        return g
+
+    def pcx_block_combine(self, s, c, y):
+        """y = s c: s (ks, len) and y (m, len) device column blocks, c a (ks, m) complex128 array."""
+        prec = self._cols(s, "s")
+        if self._cols(y, "y") != prec or y.shape[1] != s.shape[1]:
+            raise ValueError("s and y need the same precision and length")
+        cc = np.ascontiguousarray(np.asarray(c, dtype=np.complex128))
+        if cc.shape != (s.shape[0], y.shape[0]):
+            raise ValueError("c must be ks x m")
+        L.check(self._lib.pcx_block_combine(self._ptr, prec, ctypes.c_void_p(s.data_ptr()), s.shape[0],
+                                            cc.ctypes.data_as(ctypes.c_void_p), y.shape[0],
+                                            ctypes.c_void_p(y.data_ptr()), s.shape[1]))
+        return y
+
     def pcx_grad_eps(self, x, weight, layout: int = L.PCX_EPS_YEE3):
         """-sum_t weight[t] |x_t|^2 per Yee point (or per voxel): d(sum_t w_t lambda_t)/d eps."""
         torch = _torch()

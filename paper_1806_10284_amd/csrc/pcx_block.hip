@@ -705,9 +705,14 @@ hipError_t launch_gram(const ColSet& A, const ColSet& B, long N, cx<double>* par
     if (herm && kb != ka && kb != 2 * ka) return hipErrorInvalidValue;
     hipError_t e;
     int chunks;
-    if (herm && ka > kMfmaMaxA && ka <= 2 * kMfmaMaxA && (kb == ka || kb == 2 * ka))
+    // the matrix-core kernel loads 16 bytes per lane: columns must start 16-byte aligned, and in FP32
+    // (a row pair per load) have an even length
+    bool dma_ok = sizeof(R) == 8 || N % 2 == 0;
+    for (int q = 0; q < kMaxSeg; ++q)
+        if (B.ncols[q] > 0 && ((size_t)B.ptr[q] & 15)) dma_ok = false;
+    if (herm && dma_ok && ka > kMfmaMaxA && ka <= 2 * kMfmaMaxA && (kb == ka || kb == 2 * ka))
         return gram_mfma_tiled<R>(B, ka, kb / ka, N, part, nchunk, out, st);
-    if (herm && ka <= kMfmaMaxA) {
+    if (herm && dma_ok && ka <= kMfmaMaxA) {
         // matrix-core path: at most kMfmaGroups row chunks
         const long groups = std::min<long>(nchunk, mfma_groups(ka));
         const DmaShape d = dma_shape(ka, kb, sizeof(R) == 8);

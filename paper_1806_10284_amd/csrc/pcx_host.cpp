@@ -700,6 +700,80 @@ extern "C" int pcx_eigvec(pcx_plan* p, const double kappa[3], int precision, con
     return ((Plan*)p)->apply(Plan::OP_EIGVEC, kappa, precision, y, x, nvec);
 }
 
+// the Rayleigh-Ritz products on their own (scratch allocated per call; the solver keeps its own)
+extern "C" int pcx_block_gram(pcx_plan* pp, int precision, const void* a, int ka, const void* b, int kb, long len,
+                              int herm, double* g) {
+    Plan* p = (Plan*)pp;
+    if (!p || !a || !g || (!b && !(herm && kb == ka))) return fail(PCX_E_ARG, "pcx_block_gram: null pointer");
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "pcx_block_gram: bad precision");
+    if (ka < 1 || kb < 1 || ka > 3 * PCX_MAX_BLOCK || kb > 6 * PCX_MAX_BLOCK || len < 1)
+        return fail(PCX_E_ARG, "pcx_block_gram: bad sizes");
+    if (herm && kb != ka && kb != 2 * ka) return fail(PCX_E_ARG, "pcx_block_gram: herm needs kb = ka or 2 ka");
+    const size_t es = precision == PCX_FP64 ? sizeof(cx<double>) : sizeof(cx<float>);
+    void* A = const_cast<void*>(a);
+    ColSet As = colset(A, ka);
+    ColSet Bs = herm ? (kb == ka ? colset(A, ka) : colset(A, ka, const_cast<void*>(b), ka))
+                     : colset(const_cast<void*>(b), kb);
+    (void)es;
+    const int chunks = gram_chunks_for(len);
+    const size_t count = (size_t)ka * kb;
+    void* part = nullptr;
+    void* out = nullptr;
+    hipError_t e = hipMalloc(&part, sizeof(cx<double>) * (size_t)(chunks + 33) * count);
+    if (e == hipSuccess) e = hipMalloc(&out, sizeof(cx<double>) * count);
+    if (e != hipSuccess) {
+        (void)hipFree(part);
+        (void)hipGetLastError();
+        return fail(PCX_E_OOM, "pcx_block_gram: scratch");
+    }
+    e = precision == PCX_FP64
+            ? launch_gram<double>(As, Bs, len, (cx<double>*)part, chunks, (cx<double>*)out, p->stream, herm != 0)
+            : launch_gram<float>(As, Bs, len, (cx<double>*)part, chunks, (cx<double>*)out, p->stream, herm != 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(g, out, sizeof(cx<double>) * count, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(part);
+    (void)hipFree(out);
+    if (e != hipSuccess) return hip_fail(e, "pcx_block_gram");
+    if (herm) {
+        // the lower triangle of each half from the upper one (each half Hermitian)
+        cx<double>* G = (cx<double>*)g;
+        for (int h = 0; h < kb / ka; ++h)
+            for (int i = 0; i < ka; ++i) {
+                G[(size_t)i * kb + h * ka + i].y = 0.0;
+                for (int j = 0; j < i; ++j) {
+                    const cx<double> u = G[(size_t)j * kb + h * ka + i];
+                    G[(size_t)i * kb + h * ka + j].x = u.x;
+                    G[(size_t)i * kb + h * ka + j].y = -u.y;
+                }
+            }
+    }
+    return PCX_OK;
+}
+
+extern "C" int pcx_block_combine(pcx_plan* pp, int precision, const void* s, int ks, const double* c, int m, void* y,
+                                 long len) {
+    Plan* p = (Plan*)pp;
+    if (!p || !s || !c || !y) return fail(PCX_E_ARG, "pcx_block_combine: null pointer");
+    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "pcx_block_combine: bad precision");
+    if (ks < 1 || m < 1 || ks > 3 * PCX_MAX_BLOCK || m > 3 * PCX_MAX_BLOCK || len < 1)
+        return fail(PCX_E_ARG, "pcx_block_combine: bad sizes");
+    void* dc = nullptr;
+    hipError_t e = hipMalloc(&dc, sizeof(cx<double>) * (size_t)ks * m);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PCX_E_OOM, "pcx_block_combine: scratch");
+    }
+    e = hipMemcpyAsync(dc, c, sizeof(cx<double>) * (size_t)ks * m, hipMemcpyHostToDevice, p->stream);
+    const ColSet S = colset(const_cast<void*>(s), ks), Y = colset(y, m);
+    if (e == hipSuccess)
+        e = precision == PCX_FP64 ? launch_combine<double>(S, (const cx<double>*)dc, Y, len, p->stream)
+                                  : launch_combine<float>(S, (const cx<double>*)dc, Y, len, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(dc);
+    if (e != hipSuccess) return hip_fail(e, "pcx_block_combine");
+    return PCX_OK;
+}
+
 extern "C" int pcx_time_Ar_kernels(pcx_plan* pp, const double kappa[3], int precision, const void* y, void* z,
                                    int nvec, int reps, double ms_out[3]) {
     Plan* p = (Plan*)pp;

@@ -254,7 +254,12 @@ int pcx_solve_batch(pcx_plan *const *plans, int nplans, const int *nk, const dou
  * stream, and keeps the fastest for the plan in that precision.  choice_out (may be NULL): -1
  * three-plane, -2 two-plane fixed-size kernels, -3 register kernels, else the generic work-group
  * size; ms_out (may be NULL): its time per application
- * in ms.
+ * in ms.  The candidates are timed after a sustained warm-up, best of two rounds.
+ * pcx_solve and pcx_solve_batch run it by default, once per process for each grid and precision they
+ * use (nvec = the LOBPCG block), on plans whose variant is PCX_VARIANT_AUTO and that carry no choice
+ * yet, and reuse the choice for every later plan of the same grid; pcx_plan_set_variant (any
+ * variant, PCX_VARIANT_AUTO included: then the built-in choice) or a choice already made here turns
+ * that off for the plan.
  * Allocates and frees two scratch blocks.  Errors: PCX_E_ARG, PCX_E_SIZE, PCX_E_DEVICE. */
 int pcx_plan_autotune(pcx_plan *p, const double kappa[3], int precision, int nvec, int *choice_out,
                       double *ms_out);

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <array>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -132,6 +133,23 @@ extern "C" int pcx_solve_batch(pcx_plan* const* plans, int nplans, const int* nk
     else pcx_opts_default(&o);
     const bool use32 = o.mode != PCX_MODE_FP64, use64 = o.mode != PCX_MODE_FP32;
 
+    // the default tuning of every plan (on this thread, before the clones copy the choice)
+    {
+        std::vector<bool> seen(nplans, false);
+        for (size_t q = 0; q < owner.size(); ++q) {
+            const int p = owner[q];
+            if (seen[p]) continue;
+            seen[p] = true;
+            Plan* pl = (Plan*)plans[p];
+            const int bt = std::min(solver_max_block(nev, &o), pl->max_vectors);
+            const double* kq = kappas + 3 * q;
+            int r = PCX_OK;
+            if (use32 || o.precondition == PCX_PRECOND_INVERSE) r = autotune_default(pl, kq, PCX_FP32, bt);
+            if (!r && use64) r = autotune_default(pl, kq, PCX_FP64, bt);
+            if (r) return r;
+        }
+    }
+
     // streams, plan clones and storage for every worker, before any worker starts
     Workers wk;
     wk.streams.assign(W, nullptr);
@@ -227,18 +245,28 @@ extern "C" int pcx_plan_autotune(pcx_plan* pp, const double kappa[3], int precis
     double best = 1e300;
     int pick = keep_t;
     p->variant = PCX_VARIANT_AUTO;
-    for (int cd : cands) {
-        p->tuned_nt[f] = cd;
+    // the GPU's clocks rise over some tens of milliseconds of load: a sustained warm-up first, then
+    // the best of two rounds over the candidates, so that no candidate is timed on a cold device
+    {
         double ms[3] = {0, 0, 0};
-        rc = pcx_time_Ar_kernels(pp, kappa, precision, buf, (char*)buf + bytes, nvec, 2, ms);   // warm-up
-        if (!rc) rc = pcx_time_Ar_kernels(pp, kappa, precision, buf, (char*)buf + bytes, nvec, 5, ms);
-        if (rc) break;
-        const double t = ms[0] + ms[1] + ms[2];
-        if (t < best) {
-            best = t;
-            pick = cd;
-        }
+        for (int w = 0; w < 4 && !rc; ++w)
+            rc = pcx_time_Ar_kernels(pp, kappa, precision, buf, (char*)buf + bytes, nvec, 5, ms);
     }
+    std::vector<double> tbest(cands.size(), 1e300);
+    for (int round = 0; round < 2 && !rc; ++round)
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            p->tuned_nt[f] = cands[ci];
+            double ms[3] = {0, 0, 0};
+            rc = pcx_time_Ar_kernels(pp, kappa, precision, buf, (char*)buf + bytes, nvec, 1, ms);   // warm-up
+            if (!rc) rc = pcx_time_Ar_kernels(pp, kappa, precision, buf, (char*)buf + bytes, nvec, 4, ms);
+            if (rc) break;
+            tbest[ci] = std::min(tbest[ci], ms[0] + ms[1] + ms[2]);
+        }
+    for (size_t ci = 0; ci < cands.size() && !rc; ++ci)
+        if (tbest[ci] < best) {
+            best = tbest[ci];
+            pick = cands[ci];
+        }
     (void)hipFree(buf);
     p->variant = keep_v;
     if (rc) {
@@ -250,3 +278,36 @@ extern "C" int pcx_plan_autotune(pcx_plan* pp, const double kappa[3], int precis
     if (ms_out) *ms_out = best;
     return PCX_OK;
 }
+
+// ------------------------------------------------------------------ tuning by default
+namespace pcx {
+
+int autotune_default(Plan* p, const double kappa[3], int precision, int nvec) {
+    const int f = precision == PCX_FP64 ? 1 : 0;
+    if (p->variant != PCX_VARIANT_AUTO || p->tuned_nt[f] != 0 || p->tune_checked[f]) return PCX_OK;
+    p->tune_checked[f] = true;
+    // one choice per (grid, precision) for the whole process
+    static std::mutex mu;
+    static std::vector<std::array<int, 5>> cache;   // n1, n2, n3, precision, choice
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const auto& c : cache)
+            if (c[0] == p->geom.n[0] && c[1] == p->geom.n[1] && c[2] == p->geom.n[2] && c[3] == f) {
+                p->tuned_nt[f] = c[4];
+                return PCX_OK;
+            }
+    }
+    int choice = 0;
+    double ms = 0;
+    // tuning only chooses among correct variants: where it cannot run (no room for the precision's
+    // kernels, no scratch) the default choice stays
+    if (p->check_fits(precision) != PCX_OK) return PCX_OK;
+    const int rc = pcx_plan_autotune((pcx_plan*)p, kappa, precision, std::max(1, std::min(nvec, p->max_vectors)),
+                                     &choice, &ms);
+    if (rc) return PCX_OK;
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({p->geom.n[0], p->geom.n[1], p->geom.n[2], f, choice});
+    return PCX_OK;
+}
+
+}  // namespace pcx

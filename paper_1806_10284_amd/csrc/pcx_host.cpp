@@ -545,6 +545,7 @@ extern "C" int pcx_plan_set_variant(pcx_plan* p, int variant) {
     Plan* pl = (Plan*)p;
     pl->variant = variant;
     pl->tuned_nt[0] = pl->tuned_nt[1] = 0;
+    pl->tune_checked[0] = pl->tune_checked[1] = true;   // an explicit choice: no tuning by default
     return PCX_OK;
 }
 

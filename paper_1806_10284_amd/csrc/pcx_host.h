@@ -79,6 +79,8 @@ struct Plan {
     // autotuned choice per precision ([0] FP32, [1] FP64): 0 untuned, -1 / -2 the three- / two-
     // plane fixed-size kernels, 256 / 512 / 1024 generic kernels with that work-group size
     int tuned_nt[2] = {0, 0};
+    // the default tuning was looked up (or run) for this precision
+    bool tune_checked[2] = {false, false};
 
     // mode codes (n bytes each) and device kappas of the last multi-k launch
     void* mcodes = nullptr;
@@ -107,6 +109,10 @@ int solver_reserve(Plan* p, int b, bool use32, bool use64);
 // the largest block pcx_solve picks for nev bands under these options
 int solver_max_block(int nev, const pcx_opts* o);
 int gram_chunks_for(long N);
+// Before the first solve on a plan whose variant is PCX_VARIANT_AUTO: the autotuner's choice for this
+// grid and precision (tuned once per process and grid with nvec vectors, then reused by every plan
+// of that grid).  A plan with an explicit variant or choice keeps it.  Not thread-safe per plan.
+int autotune_default(Plan* p, const double kappa[3], int precision, int nvec);
 // device address of the static scratch array of pcx_apply_Ar_noalloc on `device` (current),
 // looked up once per device
 int noalloc_setup(int device);

@@ -601,6 +601,10 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (use64 && (rc = p->check_fits(PCX_FP64))) return rc;
     if (use32 && (rc = p->check_fits(PCX_FP32))) return rc;
 
+    // the autotuner's kernel choice for this grid (once per process and grid; plans with an explicit
+    // variant keep it); the FP32 kernels also serve the FP64 phase's preconditioner
+    if (use32 || S.o.precondition == PCX_PRECOND_INVERSE) autotune_default(p, kappa, PCX_FP32, b);
+    if (use64) autotune_default(p, kappa, PCX_FP64, b);
     if ((rc = solver_reserve(p, b, use32, use64))) return rc;
     const size_t bytes64 = use64 ? 10 * (size_t)b * N * sizeof(cx<double>) : 0;
     S.gram_chunks = gram_chunks_for(N);

@@ -18,25 +18,39 @@ DEV cx<double> p3_setup(const Grid& g, const KSel& ks, const DeviceTables& tb, i
     const double phi2 = (ks.kap[1] - (double)g.s1 * tx) / (double)N2;
     const double Ai =
         ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ((ks.kap[1] - (double)g.s1 * tx) / (double)N2)) / (double)N3;
-    for (int q = threadIdx.x; q < N3; q += NT) {
-        L.twz[q] = twz_g[q];
-        L.halfz[q] = tb.halfz[q];
-        L.twc[q] = cis_turns<R>((double)q * Ai);
+    // three independent groups of entries, each on its own wavefront when the work-group has three
+    // (their FP64 sines and cosines then run side by side instead of one after another)
+    constexpr bool kSpread = NT >= 192;
+    const int grp = kSpread ? (int)threadIdx.x >> 6 : 0;
+    const int t0 = kSpread ? (int)threadIdx.x & 63 : (int)threadIdx.x;
+    constexpr int kStep = kSpread ? 64 : NT;
+    if (grp == 0) {
+        for (int q = t0; q < N3; q += kStep) {
+            L.twz[q] = twz_g[q];
+            L.halfz[q] = tb.halfz[q];
+            L.twc[q] = cis_turns<R>((double)q * Ai);
+        }
     }
-    for (int j = threadIdx.x; j < N2; j += NT) {
-        L.twy[j] = twy_g[j];
-        L.twb[j] = cis_turns<R>((double)j * phi2);
-        const double ty = ((ks.kap[1] + (double)j) - (double)g.s1 * tx) / (double)N2;
-        const cx<double> L1 = lam_of_turn(ty, 1.0 / g.dlt[1]);
-        const cx<double> D = L1 - L0;
-        L.lamy[j] = L1;
-        L.d10[j] = D;
-        L.a01[j] = abs2(L0) + abs2(L1);
-        L.p10[j] = abs2(D);
-        const double p3 = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)N3;
-        double s, c;
-        sincospi(p3, &s, &c);
-        L.rowz[j] = mk<double>(c, s);
+    if (grp == (kSpread ? 1 : 0)) {
+        for (int j = t0; j < N2; j += kStep) {
+            L.twy[j] = twy_g[j];
+            L.twb[j] = cis_turns<R>((double)j * phi2);
+        }
+    }
+    if (grp == (kSpread ? 2 : 0)) {
+        for (int j = t0; j < N2; j += kStep) {
+            const double ty = ((ks.kap[1] + (double)j) - (double)g.s1 * tx) / (double)N2;
+            const cx<double> L1 = lam_of_turn(ty, 1.0 / g.dlt[1]);
+            const cx<double> D = L1 - L0;
+            L.lamy[j] = L1;
+            L.d10[j] = D;
+            L.a01[j] = abs2(L0) + abs2(L1);
+            L.p10[j] = abs2(D);
+            const double p3 = ((ks.kap[2] - (double)g.s2 * tx) - (double)g.s3 * ty) / (double)N3;
+            double s, c;
+            sincospi(p3, &s, &c);
+            L.rowz[j] = mk<double>(c, s);
+        }
     }
     return L0;
 }

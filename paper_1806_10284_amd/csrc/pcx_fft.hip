@@ -1303,6 +1303,18 @@ static hipError_t xline(const Grid& g, const DeviceTables& tb, const R* scale, c
     return hipGetLastError();
 }
 
+hipError_t launch_precond_mixed(const Grid& g, const DeviceTables& tb, const float* epsn32, const cx<double>* y,
+                                cx<double>* z, cx<float>* t, const double* scale, int nvec, hipStream_t st) {
+    // exactly where the FP32 A_r takes the register kernels (plane_fwd / plane_adj)
+    const int kind0 = g.fixed_kind[0];
+    if (g.split[0] || g.generic[0] || !(kind0 == 0 || kind0 == 4) || !wave_plane_available(g, 0))
+        return hipErrorNotSupported;
+    hipError_t e = launch_wave_plane_fwd(g, tb, y, t, nvec, st);
+    if (e == hipSuccess) e = xline<float, 0>(g, tb, epsn32, t, nullptr, nvec, st);
+    if (e == hipSuccess) e = launch_wave_plane_adj(g, tb, t, z, scale, nvec, st);
+    return e;
+}
+
 template <typename R>
 hipError_t launch_apply_Ar(const Grid& g, const DeviceTables& tb, const R* inv_eps_n, const cx<R>* y, cx<R>* z,
                            cx<R>* t, int nvec, hipStream_t st) {

@@ -488,6 +488,21 @@ int Plan::ensure_work(int nvec) {
     return grow(&work, &work_cap, need);
 }
 
+int Plan::precond_mixed(const double kappa[3], const void* y, void* z, const double* scale, int nvec, bool* done) {
+    *done = false;
+    if (!eps_set || nvec < 1 || nvec > max_vectors || check_fits(PCX_FP32) != PCX_OK) return PCX_OK;
+    int rc = ensure_work(nvec);
+    if (rc) return rc;
+    Grid g;
+    if ((rc = grid_for(kappa, &g))) return rc;
+    const hipError_t e = launch_precond_mixed(g, tables, (const float*)epsn32, (const cx<double>*)y, (cx<double>*)z,
+                                              (cx<float>*)work, scale, nvec, stream);
+    if (e == hipErrorNotSupported) return PCX_OK;
+    if (e != hipSuccess) return hip_fail(e, "preconditioner launch");
+    *done = true;
+    return PCX_OK;
+}
+
 int Plan::apply(int op, const double kappa[3], int precision, const void* in, void* out, int nvec) {
     if (!in || !out || !kappa) return fail(PCX_E_ARG, "apply: null pointer");
     if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "apply: bad precision");

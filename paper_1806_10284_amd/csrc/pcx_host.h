@@ -99,6 +99,9 @@ struct Plan {
     // grid description for nk wave vectors in one launch, nvk vectors each ([k][v] order)
     int grid_multi(const double* kappas, int nk, int nvk, Grid* g);
     int check_fits(int precision) const;
+    // z = diag(scale) A_r(eps) y, FP64 y and z, FP32 register kernels (in place allowed); false when
+    // those kernels do not apply to this grid and choice (nothing launched)
+    int precond_mixed(const double kappa[3], const void* y, void* z, const double* scale, int nvec, bool* done);
     int ensure_work(int nvec);
     int apply(int op, const double kappa[3], int precision, const void* in, void* out, int nvec);
 };

@@ -128,6 +128,15 @@ hipError_t launch_wave_plane_fwd(const Grid& g, const DeviceTables& tb, const cx
                                  hipStream_t st);
 hipError_t launch_wave_plane_adj(const Grid& g, const DeviceTables& tb, const cx<float>* t, cx<float>* z, int nvec,
                                  hipStream_t st);
+// the same kernels with FP64 input (forward) and FP64 output scaled per mode (adjoint, scale: n values)
+hipError_t launch_wave_plane_fwd(const Grid& g, const DeviceTables& tb, const cx<double>* y, cx<float>* t, int nvec,
+                                 hipStream_t st);
+hipError_t launch_wave_plane_adj(const Grid& g, const DeviceTables& tb, const cx<float>* t, cx<double>* z,
+                                 const double* scale, int nvec, hipStream_t st);
+// z = diag(scale) A_r(eps) y with FP64 y and z and the FP32 register kernels in between (the FP64
+// solver's preconditioner); hipErrorNotSupported where the register kernels do not apply
+hipError_t launch_precond_mixed(const Grid& g, const DeviceTables& tb, const float* epsn32, const cx<double>* y,
+                                cx<double>* z, cx<float>* t, const double* scale, int nvec, hipStream_t st);
 hipError_t configure_fixed_kernels();
 
 // ---- block operations (pcx_block.hip) ----

@@ -243,6 +243,17 @@ struct Solver {
             e = launch_scale_modes<R>(t0, w0, prec, n, npre, p->stream);
             return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_solve: preconditioner scaling");
         }
+        // FP64 phase on the register kernels: FP64 in and out, rounding to FP32 on the way in and the
+        // outer D on the way out, in place
+        if (sizeof(R) == 8) {
+            bool done = false;
+            if (int rc = p->precond_mixed(kappa, w0, w0, prec, npre, &done)) return rc;
+            if (done) {
+                st.precond_applies += npre;
+                st.precond_applies_fp32 += npre;
+                return PCX_OK;
+            }
+        }
         // FP64 phase: AW (b columns of complex128) holds the FP32 input and output side by side;
         // FP32 phase: W itself is the input and AW the output
         cx<float>* tin = sizeof(R) == 8 ? (cx<float>*)(void*)B.AW : (cx<float>*)(void*)w0;

@@ -99,9 +99,11 @@ DEV KSel grid_k(const Grid& g) {
 
 }  // namespace
 
-// y: [v][2][n1][64][64] -> t: [v][3][n1][c][b]; grid (n1, nvec)
+// y: [v][2][n1][64][64] -> t: [v][3][n1][c][b]; grid (n1, nvec).  TI: the input's precision (FP64
+// input is rounded to FP32 as it is read: the FP64 solver's preconditioner)
+template <typename TI>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4)))
-k_w64_fwd(Grid g, DeviceTables tb, const cx<float>* __restrict__ y, cx<float>* __restrict__ t) {
+k_w64_fwd(Grid g, DeviceTables tb, const cx<TI>* __restrict__ y, cx<float>* __restrict__ t) {
     __shared__ WaveLds S;
     const LdsView L(S);
     const int i = blockIdx.x, v = blockIdx.y;
@@ -110,14 +112,15 @@ k_w64_fwd(Grid g, DeviceTables tb, const cx<float>* __restrict__ y, cx<float>* _
     // this lane's modes in the z phase: row j, k = q + 8m
     const int j = 8 * w + gl;
     const long mb = (long)i * kNP + j * kN + q;
-    const cx<float>* y1 = y + (long)v * 2 * n + mb;
+    const cx<TI>* y1 = y + (long)v * 2 * n + mb;
     const unsigned char* codes = g.codes + mb;
     cx<float> a[8], b[8];
     int code[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-        a[m] = y1[8 * m];
-        b[m] = y1[n + 8 * m];
+        const cx<TI> ya = y1[8 * m], yb = y1[n + 8 * m];
+        a[m] = mk<float>((float)ya.x, (float)ya.y);
+        b[m] = mk<float>((float)yb.x, (float)yb.y);
         code[m] = codes[8 * m];
     }
     const cx<double> L0 = p3_setup<float, kN, kN, kNT>(g, grid_k(g), tb, i, L);
@@ -160,9 +163,13 @@ k_w64_fwd(Grid g, DeviceTables tb, const cx<float>* __restrict__ y, cx<float>* _
     }
 }
 
-// t: [v][3][n1][c][b] -> z: [v][2][n1][64][64]; grid (n1, nvec)
+// t: [v][3][n1][c][b] -> z: [v][2][n1][64][64]; grid (n1, nvec).  TO: the output's precision; scale
+// (n values or null): a per-mode factor applied in FP64 on the way out (the FP64 solver's
+// preconditioner writes D z in FP64)
+template <typename TO>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4)))
-k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<float>* __restrict__ z) {
+k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<TO>* __restrict__ z,
+          const double* __restrict__ scale) {
     __shared__ WaveLds S;
     const LdsView L(S);
     const int i = blockIdx.x, v = blockIdx.y;
@@ -212,7 +219,7 @@ k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<float>* _
     // z = W^H s per mode
     const unsigned char* codes = g.codes + mb;
     const double idz = 1.0 / g.dlt[2];
-    cx<float>* zb = z + (long)v * 2 * n + mb;
+    cx<TO>* zb = z + (long)v * 2 * n + mb;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int code = codes[8 * c];
@@ -227,8 +234,9 @@ k_w64_adj(Grid g, DeviceTables tb, const cx<float>* __restrict__ t, cx<float>* _
                 a2 = a2 + cmulc(sv, W[l][1]);
             }
         }
-        zb[8 * c] = a1;
-        zb[n + 8 * c] = a2;
+        const double d = scale ? scale[mb + 8 * c] : 1.0;
+        zb[8 * c] = mk<TO>((TO)(d * (double)a1.x), (TO)(d * (double)a1.y));
+        zb[n + 8 * c] = mk<TO>((TO)(d * (double)a2.x), (TO)(d * (double)a2.y));
     }
 }
 
@@ -238,13 +246,25 @@ bool wave_plane_available(const Grid& g, int fp64) {
 
 hipError_t launch_wave_plane_fwd(const Grid& g, const DeviceTables& tb, const cx<float>* y, cx<float>* t, int nvec,
                                  hipStream_t st) {
-    PCX_LAUNCH(k_w64_fwd, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, y, t);
+    PCX_LAUNCH(k_w64_fwd<float>, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, y, t);
     return hipGetLastError();
 }
 
 hipError_t launch_wave_plane_adj(const Grid& g, const DeviceTables& tb, const cx<float>* t, cx<float>* z, int nvec,
                                  hipStream_t st) {
-    PCX_LAUNCH(k_w64_adj, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, t, z);
+    PCX_LAUNCH(k_w64_adj<float>, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, t, z, (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave_plane_fwd(const Grid& g, const DeviceTables& tb, const cx<double>* y, cx<float>* t, int nvec,
+                                 hipStream_t st) {
+    PCX_LAUNCH(k_w64_fwd<double>, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, y, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave_plane_adj(const Grid& g, const DeviceTables& tb, const cx<float>* t, cx<double>* z,
+                                 const double* scale, int nvec, hipStream_t st) {
+    PCX_LAUNCH(k_w64_adj<double>, dim3(g.n1, nvec), dim3(kNT), 0, st, g, tb, t, z, scale);
     return hipGetLastError();
 }
 

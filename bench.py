@@ -77,7 +77,7 @@ def kernel_source_hash() -> str:
 
 # kernel-name prefix in a rocprofv3 trace -> (A_r kernel, precision)
 KERNEL_KEYS = [
-    ("pcx::k_w64_fwd", "plane_fwd_fp32"), ("pcx::k_w64_adj", "plane_adj_fp32"),
+    ("pcx::k_w64_fwd<float", "plane_fwd_fp32"), ("pcx::k_w64_adj<float", "plane_adj_fp32"),
     ("pcx::k_p2_fwd<float", "plane_fwd_fp32"), ("pcx::k_p2_fwd<double", "plane_fwd_fp64"),
     ("pcx::k_p2_adj<float", "plane_adj_fp32"), ("pcx::k_p2_adj<double", "plane_adj_fp64"),
     ("pcx::k_p3_fwd<float", "plane_fwd_fp32"), ("pcx::k_p3_fwd<double", "plane_fwd_fp64"),
@@ -132,6 +132,11 @@ def summarize_traffic(fetch_csv: str, write_csv: str, out_json: str):
     return out
 
 
+# FP32 register kernels with FP64 input / scaled FP64 output: the FP64-phase preconditioner
+# (trace summaries only)
+MIXED_KEYS = [("pcx::k_w64_fwd<double", "precond_plane_fwd_fp32in64"),
+              ("pcx::k_w64_adj<double", "precond_plane_adj_fp32out64")]
+
 # the two passes of the planes that take the two-pass path (trace summaries only)
 SPLIT_KEYS = [(f"pcx::{k}<{t}", f"{lab}_{p}") for k, lab in
               (("k_zrow128_fwd", "rows_fwd"), ("k_zpass_fwd", "rows_fwd"), ("k_ypass_fwd", "cols_fwd"),
@@ -151,13 +156,13 @@ def summarize_trace(trace_csv: str, last: int = 20) -> str:
     groups = defaultdict(list)
     for r in rows:
         name = r["Kernel_Name"]
-        key = next((k for p, k in KERNEL_KEYS + SPLIT_KEYS if name.startswith("void " + p) or name.startswith(p)),
+        key = next((k for p, k in KERNEL_KEYS + MIXED_KEYS + SPLIT_KEYS if name.startswith("void " + p) or name.startswith(p)),
                    None)
         if key:
             groups[(key, int(r["Grid_Size_Y"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
     # the solves: every dispatch before the first plane kernel of the roofline block
-    stop = next((k for k, r in enumerate(rows) if r["Kernel_Name"].startswith(("pcx::k_w64_fwd", "void pcx::k_p2_fwd",
-                                                                                 "pcx::k_p2_fwd"))
+    stop = next((k for k, r in enumerate(rows) if r["Kernel_Name"].startswith(("pcx::k_w64_fwd<float", "void pcx::k_w64_fwd<float",
+                                                                                 "void pcx::k_p2_fwd", "pcx::k_p2_fwd"))
                  and int(r["Grid_Size_Y"]) == ROOF_VECTORS), len(rows))
     sol = rows[:stop]
     busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sol) * 1e-6

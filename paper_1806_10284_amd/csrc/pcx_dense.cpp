@@ -47,8 +47,11 @@ struct Rot {
     int i;
 };
 
-// implicit QL on the symmetric tridiagonal (d diagonal, e[i] = T(i+1, i)); the eigenvector matrix
-// is the product of the recorded rotations (applied later to the wanted columns only)
+// implicit QL on the symmetric tridiagonal (d diagonal, e[i] = T(i+1, i)): the published method of
+// Bowdler, Martin, Reinsch and Wilkinson ("The QR and QL algorithms for symmetric matrices",
+// Numer. Math. 11, 1968), with the shift from the eigenvalue of the leading 2 x 2 block nearer
+// d[l] and the bulge chased upwards by plane rotations.  The eigenvector matrix is the product of
+// the recorded rotations (applied later to the wanted columns only).
 static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<Rot>& rots) {
     rots.clear();
     if (n == 0) return true;

@@ -54,6 +54,9 @@ typedef enum pcx_status {
 } pcx_status;
 
 enum { PCX_FP64 = 0, PCX_FP32 = 1 };                 /* arithmetic / storage precision */
+/* pcx_apply_precond only: complex128 in and out, the scalings in FP64 and the operator between
+ * them in FP32 (what the FP64 phase of PCX_MODE_FP32_REFINE applies) */
+enum { PCX_FP64_OP32 = 2 };
 enum { PCX_EPS_YEE3 = 0, PCX_EPS_VOXEL = 1 };        /* permittivity layouts */
 enum { PCX_MODE_FP64 = 0, PCX_MODE_FP32_REFINE = 1, PCX_MODE_FP32 = 2 };
 /* kernel variants of the A_r path */
@@ -180,7 +183,10 @@ enum { PCX_PRECOND_NONE = 0, PCX_PRECOND_DIAG = 1, PCX_PRECOND_INVERSE = 2 };
 /* z = T y with T the PCX_PRECOND_INVERSE preconditioner D Sigma_r Q_r^* B Q_r Sigma_r D,
  * D = Lambda_q^{-1} per mode (0 on a masked mode): the three A_r kernels with eps in place of
  * 1/eps between two mode scalings.  y, z: device, nvec vectors of 2n complex (complex128 for
- * PCX_FP64, complex64 for PCX_FP32); z may equal y.  Same errors as pcx_apply_Ar. */
+ * PCX_FP64 and PCX_FP64_OP32, complex64 for PCX_FP32); z may equal y.  PCX_FP64_OP32 rounds D y
+ * to FP32, applies the kernels in FP32 and the outer D in FP64 (on the 64 x 64-plane register
+ * kernels: inside them, with no conversion pass; elsewhere through an FP32 copy of 2 x 2n
+ * complex64 per vector that the plan keeps).  Same errors as pcx_apply_Ar. */
 int pcx_apply_precond(pcx_plan *p, const double kappa[3], int precision, const void *y, void *z, int nvec);
 
 typedef struct pcx_opts {

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libpcx.so")
 
 PCX_OK, PCX_E_ARG, PCX_E_SIZE, PCX_E_LATTICE, PCX_E_NOCONV, PCX_E_OOM, PCX_E_DEVICE = 0, -1, -2, -3, -4, -5, -6
 PCX_FP64, PCX_FP32 = 0, 1
+PCX_FP64_OP32 = 2          # pcx_apply_precond only: complex128 buffers, operator in FP32
 PCX_EPS_YEE3, PCX_EPS_VOXEL = 0, 1
 PCX_MODE_FP64, PCX_MODE_FP32_REFINE, PCX_MODE_FP32 = 0, 1, 2
 PCX_PRECOND_NONE, PCX_PRECOND_DIAG, PCX_PRECOND_INVERSE = 0, 1, 2

@@ -123,7 +123,7 @@ class Plan:
     # -- operators
     def _check_block(self, t, per_vec: int, precision: int, name: str) -> int:
         torch = _torch()
-        dt = torch.complex128 if precision == L.PCX_FP64 else torch.complex64
+        dt = torch.complex128 if precision in (L.PCX_FP64, L.PCX_FP64_OP32) else torch.complex64
         if t.device.type != "cuda":
             raise ValueError(f"{name} must be a device tensor")
         if t.dtype != dt:
@@ -175,7 +175,8 @@ class Plan:
 
     def pcx_apply_precond(self, kappa, y, z, precision=None):
         """z = D Sigma_r Q_r^* B Q_r Sigma_r D y, D = Lambda_q^{-1}: the approximate-inverse
-        preconditioner of the solver (z may be y)."""
+        preconditioner of the solver (z may be y).  precision PCX_FP64_OP32: complex128 y and z,
+        the operator between the FP64 scalings in FP32 (the FP64 solver phase's form)."""
         precision = self._prec_of(y) if precision is None else precision
         return self._apply(self._lib.pcx_apply_precond, kappa, precision, y, z, 2 * self.n, 2 * self.n)
 

@@ -422,7 +422,8 @@ extern "C" void pcx_plan_destroy(pcx_plan* pp) {
     Plan* p = (Plan*)pp;
     if (!p) return;
     void* bufs[] = {p->tables_mem, p->eps_mem, p->work,   p->lob_mem,  p->prec,     p->gram_part,
-                    p->small_mem,  p->codes,   p->mcodes, p->kaps_dev, p->wtab_mem, p->aux};
+                    p->small_mem,  p->codes,   p->mcodes, p->kaps_dev, p->wtab_mem, p->aux,
+                    p->mix};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->pinned) (void)hipHostFree(p->pinned);
@@ -647,13 +648,15 @@ extern "C" int pcx_apply_precond(pcx_plan* pp, const double kappa[3], int precis
                                  int nvec) {
     Plan* p = (Plan*)pp;
     if (!p || !kappa || !y || !z) return fail(PCX_E_ARG, "pcx_apply_precond: null pointer");
-    if (precision != PCX_FP64 && precision != PCX_FP32) return fail(PCX_E_ARG, "pcx_apply_precond: bad precision");
+    if (precision != PCX_FP64 && precision != PCX_FP32 && precision != PCX_FP64_OP32)
+        return fail(PCX_E_ARG, "pcx_apply_precond: bad precision");
     if (nvec < 1 || nvec > p->max_vectors)
         return fail(PCX_E_ARG, "pcx_apply_precond: nvec %d outside [1, %d]", nvec, p->max_vectors);
     if (!p->eps_set) return fail(PCX_E_ARG, "pcx_apply_precond: permittivity not set");
     for (int l = 0; l < 3; ++l)
         if (!std::isfinite(kappa[l])) return fail(PCX_E_ARG, "pcx_apply_precond: non-finite kappa");
-    int rc = p->check_fits(precision);
+    const bool mixed = precision == PCX_FP64_OP32;
+    int rc = p->check_fits(mixed ? PCX_FP32 : precision);
     if (rc) return rc;
     if ((rc = p->grow(&p->prec, &p->prec_cap, p->n * sizeof(double)))) return rc;
     Grid g;
@@ -661,6 +664,23 @@ extern "C" int pcx_apply_precond(pcx_plan* pp, const double kappa[3], int precis
     hipError_t e = launch_precond_diag(g, p->tables, (double*)p->prec, p->stream);
     if (e != hipSuccess) return hip_fail(e, "pcx_apply_precond: Lambda_q^{-1}");
     const double* d = (const double*)p->prec;
+    if (mixed) {
+        // the FP64 solver's preconditioner: inner D in FP64, the operator in FP32, outer D in FP64
+        e = launch_scale_modes<double>((const cx<double>*)y, (cx<double>*)z, d, p->n, nvec, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "pcx_apply_precond: scaling");
+        bool done = false;
+        if ((rc = p->precond_mixed(kappa, z, z, d, nvec, &done))) return rc;
+        if (done) return PCX_OK;
+        const long len = 2 * p->n * (long)nvec;
+        if ((rc = p->grow(&p->mix, &p->mix_cap, 2 * len * sizeof(cx<float>)))) return rc;
+        cx<float>* tin = (cx<float>*)p->mix;
+        cx<float>* tout = tin + len;
+        e = launch_convert((const cx<double>*)z, tin, len, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "pcx_apply_precond: conversion");
+        if ((rc = p->apply(Plan::OP_AR_EPS, kappa, PCX_FP32, tin, tout, nvec))) return rc;
+        e = launch_scale_modes(tout, (cx<double>*)z, d, p->n, nvec, p->stream);
+        return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_apply_precond: scaling");
+    }
     if (precision == PCX_FP64)
         e = launch_scale_modes<double>((const cx<double>*)y, (cx<double>*)z, d, p->n, nvec, p->stream);
     else

@@ -51,6 +51,8 @@ struct Plan {
     size_t lob_cap = 0;
     void* prec = nullptr;
     size_t prec_cap = 0;
+    void* mix = nullptr;             // FP32 copies for pcx_apply_precond(PCX_FP64_OP32) off the register kernels
+    size_t mix_cap = 0;
     void* gram_part = nullptr;
     size_t gram_part_cap = 0;
     void* small_mem = nullptr;

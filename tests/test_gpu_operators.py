@@ -124,6 +124,39 @@ def test_apply_precond_parity(name, avec, n, kappa, prec):
         _cmp(got2[:, v], ref, prec, f"{name} vec {v} in place")
 
 
+@pytest.mark.parametrize("variant", ["auto", "register"])
+@pytest.mark.parametrize("name,avec,n,kappa", [
+    ("fcc_8_64_64", S.FCC, (8, 64, 64), (0.5, 0.0, 0.5)),          # 64 x 64 planes: register kernels
+    ("gamma_sc_4_64_64", S.SC, (4, 64, 64), (0.0, 0.0, 0.0)),      # the same, with the Gamma mask
+    CASES[1], CASES[7], CASES[10]])                                # other plane kernels: FP32 copies
+def test_apply_precond_fp64_op32_parity(name, avec, n, kappa, variant):
+    """pcx_apply_precond with PCX_FP64_OP32 (complex128 in and out, the operator between the FP64
+    scalings applied in FP32, as in the FP64 phase of the FP32 + refinement solver) against the
+    FP64 oracle D A_r(eps -> 1/eps) D at the FP32 tolerance, in place and out of place; on 64 x 64
+    planes the register kernels read FP64 and store the scaled FP64 result themselves."""
+    import torch
+    from oracle.nfsep import preconditioner_diag
+    from paper_1806_10284_amd import PCX_FP64_OP32
+    if variant == "register" and n[1:] != (64, 64):
+        pytest.skip("the register kernels take 64 x 64 planes only")
+    rng = np.random.default_rng(sum(map(ord, name)) + 5)
+    npts = n[0] * n[1] * n[2]
+    eps = rng.uniform(1.0, 13.0, (3, npts))
+    plan, og, spec, y = _setup(avec, n, kappa, eps, nvec=3, seed=13, variant=variant)
+    say("apply_precond fp64_op32", name, n, variant)
+    d = preconditioner_diag(spec)
+    yd = _to_dev(y, "fp64")
+    z = torch.empty_like(yd)
+    plan.pcx_apply_precond(kappa, yd, z, precision=PCX_FP64_OP32)
+    plan.pcx_apply_precond(kappa, yd, yd, precision=PCX_FP64_OP32)
+    torch.cuda.synchronize()
+    got, got2 = z.cpu().numpy().T, yd.cpu().numpy().T
+    for v in range(3):
+        ref = d * Ar_apply(spec, 1.0 / eps, d * y[:, v])
+        _cmp(got[:, v], ref, "fp32", f"{name} vec {v}")
+        _cmp(got2[:, v], ref, "fp32", f"{name} vec {v} in place")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name,avec,n,kappa", [CASES[1], CASES[3], CASES[7], CASES[8]])
 def test_QS_and_adjoint_and_eigvec(name, avec, n, kappa, prec):

@@ -226,6 +226,9 @@ typedef struct pcx_stats {
                                           while tol * lambda_j lies four orders below that floor:
                                           bands that go to zero next to Gamma.  Every other
                                           converged band has residual[j] <= tol. */
+    int orth_fallbacks;                /* LOBPCG phases that went on with two host synchronisations
+                                          per iteration (W orthonormalised against X first) because
+                                          the pencil of the plain basis [X W P] did not factor */
 } pcx_stats;
 
 /* Smallest nev positive eigenvalues of C*C x = lambda B x at Bloch phases kappa

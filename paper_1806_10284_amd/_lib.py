@@ -45,7 +45,7 @@ class PcxStats(ctypes.Structure):
         ("seconds", ctypes.c_double), ("seconds_matvec", ctypes.c_double),
         ("residual", ctypes.c_double * PCX_MAX_BLOCK), ("converged", ctypes.c_int),
         ("precond_applies", ctypes.c_longlong), ("precond_applies_fp32", ctypes.c_longlong),
-        ("restarts", ctypes.c_int), ("floor_mask", ctypes.c_ulonglong),
+        ("restarts", ctypes.c_int), ("floor_mask", ctypes.c_ulonglong), ("orth_fallbacks", ctypes.c_int),
     ]
 
 

@@ -79,6 +79,7 @@ class SolveStats:
     precond_applies_fp32: int = 0
     restarts: int = 0
     floor_mask: int = 0           # bit j: band j accepted at the absolute residual floor (next to Gamma)
+    orth_fallbacks: int = 0       # phases that fell back to orthonormalising W on the host
 
 
 class Plan:
@@ -256,7 +257,7 @@ class Plan:
                                    ctypes.c_void_p(x.data_ptr()) if x is not None else None, ctypes.byref(st))
         stats = SolveStats(st.iterations, st.iterations_fp32, st.matvecs, st.matvecs_fp32, st.seconds,
                            st.seconds_matvec, np.array(list(st.residual))[:nev], st.converged, st.precond_applies,
-                           st.precond_applies_fp32, st.restarts, st.floor_mask)
+                           st.precond_applies_fp32, st.restarts, st.floor_mask, st.orth_fallbacks)
         if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
             L.check(code)
         return lam, (y if want_y else None), x, stats
@@ -386,7 +387,7 @@ def pcx_solve_batch(problems, nev: int, *, mode=L.PCX_MODE_FP32_REFINE, block=0,
                                lam.ctypes.data_as(ctypes.c_void_p), yp, st)
     stats = [SolveStats(s.iterations, s.iterations_fp32, s.matvecs, s.matvecs_fp32, s.seconds, s.seconds_matvec,
                         np.array(list(s.residual))[:nev], s.converged, s.precond_applies,
-                        s.precond_applies_fp32, s.restarts, s.floor_mask) for s in st]
+                        s.precond_applies_fp32, s.restarts, s.floor_mask, s.orth_fallbacks) for s in st]
     if code != L.PCX_OK and (raise_on_noconv or code != L.PCX_E_NOCONV):
         L.check(code)
     return lam, ys, stats

@@ -272,10 +272,10 @@ struct Solver {
         return e == hipSuccess ? PCX_OK : hip_fail(e, "pcx_solve: preconditioner scaling");
     }
 
-    // residual norms of the b Ritz pairs, W <- prec (AX - X theta); with wg, also the Gram matrix
-    // [X | W]^H W (2b x b) of the new W, under the same stream synchronisation
+    // queues W <- prec (AX - X theta) and the residual norms of the b Ritz pairs (read after the
+    // next stream synchronisation by read_residuals)
     template <typename R>
-    int residuals(Blocks<R>& B, std::vector<zc>* wg = nullptr) {
+    int residuals_async(Blocks<R>& B) {
         hipError_t e = launch_residual<R>(colset(B.X, b), colset(B.AX, b), theta.data(), o.precondition ? prec : nullptr, n,
                                colset(B.W, b), res_part, gram_chunks, res_map, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: residual");
@@ -283,6 +283,23 @@ struct Solver {
         if (o.precondition == PCX_PRECOND_INVERSE && npre > 0) {
             if (int rc = precondition_inverse<R>(B, npre)) return rc;
         }
+        return PCX_OK;
+    }
+
+    void read_residuals() {
+        resid.resize(b);
+        rabs.resize(b);
+        for (int j = 0; j < b; ++j) {
+            rabs[j] = std::sqrt(std::max(host_res[j], 0.0));
+            resid[j] = rabs[j] / std::max(std::fabs(theta[j]), 1e-300);
+        }
+    }
+
+    // residual norms of the b Ritz pairs, W <- prec (AX - X theta); with wg, also the Gram matrix
+    // [X | W]^H W (2b x b) of the new W, under the same stream synchronisation
+    template <typename R>
+    int residuals(Blocks<R>& B, std::vector<zc>* wg = nullptr) {
+        if (int rc = residuals_async<R>(B)) return rc;
         // [X | W]^H W as the right half of the Hermitian [X | W]^H [X | W]: the 2b columns are staged
         // once (the plain product would stage W twice)
         const ColSet XW = colset(B.X, b, B.W, b);
@@ -297,12 +314,7 @@ struct Solver {
                 std::copy(full.begin() + (size_t)r * 2 * b + b, full.begin() + (size_t)(r + 1) * 2 * b,
                           wg->begin() + (size_t)r * b);
         }
-        resid.resize(b);
-        rabs.resize(b);
-        for (int j = 0; j < b; ++j) {
-            rabs[j] = std::sqrt(std::max(host_res[j], 0.0));
-            resid[j] = rabs[j] / std::max(std::fabs(theta[j]), 1e-300);
-        }
+        read_residuals();
         return PCX_OK;
     }
 
@@ -342,8 +354,8 @@ struct Solver {
         double best = 1e300;
         int stall = 0;
         std::vector<zc> G;                       // [X | W]^H W, (2b) x b
-        for (;;) {
-            if ((rc = residuals<R>(B, &G))) return rc;   // W <- prec (AX - X theta) for all b columns
+        // the convergence verdict on the residuals of the current X: 1 = leave the phase
+        auto verdict = [&]() -> bool {
             bool all = true;
             double worst = 0;                    // over the bands still open
             int jw = -1;
@@ -361,7 +373,7 @@ struct Solver {
                 fprintf(stderr, "pcx lobpcg %s it %d: theta0 %.12g worst residual %.3e (band %d), %d of %d columns open\n",
                         sizeof(R) == 8 ? "fp64" : "fp32", iters, theta[0], worst, jw, open, b);
             }
-            if (all || iters >= max_iter) return PCX_OK;
+            if (all || iters >= max_iter) return true;
             // a reduced-precision phase ends when its residual stops improving (rounding floor)
             // and leaves at least half of the iterations to the refinement
             if (worst < 0.9 * best) {
@@ -372,16 +384,114 @@ struct Solver {
                 // FP32: the rounding floor (or bands it cannot resolve at all, next to Gamma),
                 // refinement follows; FP64: stagnation at the floor of a band the tolerance cannot
                 // reach, stop before the basis loses orthogonality
-                return PCX_OK;
+                return true;
             }
-            if (sizeof(R) == 4 && refine_after && st.iterations_fp32 >= max_iter / 2) return PCX_OK;
-            ++iters;
-            ++st.iterations;
-            if (sizeof(R) == 4) ++st.iterations_fp32;
-            // soft locking: only columns whose residual is above tol expand the basis
+            return sizeof(R) == 4 && refine_after && st.iterations_fp32 >= max_iter / 2;
+        };
+        // soft locking: only columns whose residual is above tol expand the basis
+        auto open_columns = [&]() {
             std::vector<int> act;
             for (int j = 0; j < b; ++j)
                 if (!converged<R>(j, tol)) act.push_back(j);
+            return act;
+        };
+        // Rayleigh-Ritz on S = [X W P] (W: na columns at Wa); without P if the basis is too
+        // ill-conditioned.  have_g: G already holds S^H [S | AS] of the basis with P.  Returns
+        // false when it fails also without P.
+        auto rayleigh_ritz_step = [&](cx<R>* Wa, int na, bool have_g, std::vector<zc>& GS, std::vector<double>& th,
+                                      std::vector<zc>& C, bool& withP) -> int {
+            withP = np > 0;
+            for (;;) {
+                const int k = b + na + (withP ? np : 0);
+                const ColSet S = withP ? colset(B.X, b, Wa, na, B.P, np) : colset(B.X, b, Wa, na);
+                const ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
+                if (!have_g)
+                    if (int rc2 = gram<R>(S, concat(S, AS), GS, true)) return rc2;     // S^H [S | AS]
+                have_g = false;
+                std::vector<zc> GB((size_t)k * k), GA((size_t)k * k);
+                for (int r = 0; r < k; ++r)
+                    for (int c = 0; c < k; ++c) {
+                        GB[(size_t)r * k + c] = GS[(size_t)r * 2 * k + c];
+                        GA[(size_t)r * k + c] = GS[(size_t)r * 2 * k + k + c];
+                    }
+                // A_r is positive semi-definite: a negative Ritz value means the pencil is no longer
+                // consistent (nearly dependent basis), handled like a failed factorisation
+                if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C) && th[0] > -1e-8 * std::fabs(th[b - 1])) return PCX_OK;
+                if (!withP) return 1;
+                withP = false;
+            }
+        };
+        // [X' | P'] = S [C | C_P], C_P = the columns act of C with the X rows zeroed
+        auto update = [&](cx<R>* Wa, int na, bool withP, const std::vector<zc>& C,
+                          const std::vector<int>& act) -> int {
+            const int k = b + na + (withP ? np : 0);
+            const int nn = (int)act.size();
+            const int m = b + nn;
+            std::vector<zc> C2((size_t)k * m, zc(0, 0));
+            for (int r = 0; r < k; ++r) {
+                for (int c = 0; c < b; ++c) C2[(size_t)r * m + c] = C[(size_t)r * b + c];
+                if (r >= b)
+                    for (int c = 0; c < nn; ++c) C2[(size_t)r * m + b + c] = C[(size_t)r * b + act[c]];
+            }
+            const ColSet S = withP ? colset(B.X, b, Wa, na, B.P, np) : colset(B.X, b, Wa, na);
+            const ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
+            if (int rc2 = combine2<R>(S, colset(B.T1, b, B.T3, nn), AS, colset(B.T2, b, B.T4, nn), C2)) return rc2;
+            std::swap(B.X, B.T1);
+            std::swap(B.P, B.T3);
+            std::swap(B.AX, B.T2);
+            std::swap(B.AP, B.T4);
+            np = nn;
+            return PCX_OK;
+        };
+        // One stream synchronisation per iteration: the preconditioned residuals of the columns
+        // open at the previous check, [pre_lo, pre_hi), enter the basis as they are (no
+        // orthogonalisation against X; the Rayleigh-Ritz step scales the basis to unit columns),
+        // their A_r product and the Gram matrix S^H [S | AS] are queued behind the residual kernel,
+        // and the residual norms and the Gram matrix reach the host together.  Should the pencil
+        // fail to factor also without P, the phase continues with two synchronisations per
+        // iteration: W orthonormalised against X on the host first.
+        bool two_sync = false;
+        for (;;) {
+            if (!two_sync) {
+                if ((rc = residuals_async<R>(B))) return rc;
+                const int na = pre_hi - pre_lo;
+                cx<R>* Wa = B.W + (size_t)pre_lo * N;
+                if ((rc = matvec<R>(Wa, B.AW, na))) return rc;
+                std::vector<zc> GS;
+                {
+                    const ColSet S = np > 0 ? colset(B.X, b, Wa, na, B.P, np) : colset(B.X, b, Wa, na);
+                    const ColSet AS = np > 0 ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
+                    if ((rc = gram<R>(S, concat(S, AS), GS, true))) return rc;
+                }
+                read_residuals();
+                if (verdict()) return PCX_OK;
+                std::vector<double> th;
+                std::vector<zc> C;
+                bool withP = false;
+                rc = rayleigh_ritz_step(Wa, na, true, GS, th, C, withP);
+                if (rc < 0) return rc;
+                if (rc > 0) {           // the unorthogonalised basis is too ill-conditioned
+                    if (o.verbose) fprintf(stderr, "pcx lobpcg: plain basis singular, W orthonormalised from here on\n");
+                    ++st.orth_fallbacks;
+                    two_sync = true;
+                    continue;
+                }
+                ++iters;
+                ++st.iterations;
+                if (sizeof(R) == 4) ++st.iterations_fp32;
+                const std::vector<int> act = open_columns();
+                if ((rc = update(Wa, na, withP, C, act))) return rc;
+                theta = th;
+                pre_lo = act.empty() ? 0 : act.front();
+                pre_hi = act.empty() ? 0 : act.back() + 1;
+                continue;
+            }
+            if ((rc = residuals<R>(B, &G))) return rc;   // W <- prec (AX - X theta) for all b columns
+            if (verdict()) return PCX_OK;
+            ++iters;
+            ++st.iterations;
+            if (sizeof(R) == 4) ++st.iterations_fp32;
+            const std::vector<int> act = open_columns();
             const int na = (int)act.size();
             pre_lo = na ? act.front() : 0;
             pre_hi = na ? act.back() + 1 : 0;
@@ -410,45 +520,14 @@ struct Solver {
                 std::swap(B.W, B.T1);
             }
             if ((rc = matvec<R>(B.W, B.AW, na))) return rc;
-            // Rayleigh-Ritz on S = [X W P]; without P if the basis is too ill-conditioned
             std::vector<double> th;
-            std::vector<zc> C;
-            int k = 0;
-            bool withP = np > 0;
-            for (;;) {
-                k = b + na + (withP ? np : 0);
-                ColSet S = withP ? colset(B.X, b, B.W, na, B.P, np) : colset(B.X, b, B.W, na);
-                ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
-                std::vector<zc> G, GB((size_t)k * k), GA((size_t)k * k);
-                if ((rc = gram<R>(S, concat(S, AS), G, true))) return rc;     // S^H [S | AS]
-                for (int r = 0; r < k; ++r)
-                    for (int c = 0; c < k; ++c) {
-                        GB[(size_t)r * k + c] = G[(size_t)r * 2 * k + c];
-                        GA[(size_t)r * k + c] = G[(size_t)r * 2 * k + k + c];
-                    }
-                // A_r is positive semi-definite: a negative Ritz value means the pencil is no longer
-                // consistent (nearly dependent basis), handled like a failed factorisation
-                if (rayleigh_ritz(k, GA, GB, b, chol_tol, th, C) && th[0] > -1e-8 * std::fabs(th[b - 1])) break;
-                if (!withP) return fail(PCX_E_NOCONV, "pcx_solve: Rayleigh-Ritz basis became singular");
-                withP = false;
-            }
-            // [X' | P'] = S [C | C_P]; C_P = the active columns of C with the X rows zeroed
-            const int m = b + na;
-            std::vector<zc> C2((size_t)k * m, zc(0, 0));
-            for (int r = 0; r < k; ++r) {
-                for (int c = 0; c < b; ++c) C2[(size_t)r * m + c] = C[(size_t)r * b + c];
-                if (r >= b)
-                    for (int c = 0; c < na; ++c) C2[(size_t)r * m + b + c] = C[(size_t)r * b + act[c]];
-            }
-            ColSet S = withP ? colset(B.X, b, B.W, na, B.P, np) : colset(B.X, b, B.W, na);
-            ColSet AS = withP ? colset(B.AX, b, B.AW, na, B.AP, np) : colset(B.AX, b, B.AW, na);
-            if ((rc = combine2<R>(S, colset(B.T1, b, B.T3, na), AS, colset(B.T2, b, B.T4, na), C2))) return rc;
-            std::swap(B.X, B.T1);
-            std::swap(B.P, B.T3);
-            std::swap(B.AX, B.T2);
-            std::swap(B.AP, B.T4);
+            std::vector<zc> C, GS;
+            bool withP = false;
+            rc = rayleigh_ritz_step(B.W, na, false, GS, th, C, withP);
+            if (rc < 0) return rc;
+            if (rc > 0) return fail(PCX_E_NOCONV, "pcx_solve: Rayleigh-Ritz basis became singular");
+            if ((rc = update(B.W, na, withP, C, act))) return rc;
             theta = th;
-            np = na;
         }
     }
 };

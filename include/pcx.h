@@ -202,6 +202,11 @@ typedef struct pcx_opts {
                             nearby solve), copied into the first n_y0 columns of the start
                             block; NULL: plane-wave start only */
     int n_y0;            /* 0 <= n_y0 <= block */
+    int orthonormalize_w; /* 1: every LOBPCG iteration orthonormalises the new directions W against
+                             X on the host before their A_r product (two host synchronisations per
+                             iteration); 0 (default): W enters the Rayleigh-Ritz basis as it is, one
+                             synchronisation per iteration, and a phase switches to the former only
+                             if that basis fails to factor (pcx_stats.orth_fallbacks) */
 } pcx_opts;
 
 void pcx_opts_default(pcx_opts *o);

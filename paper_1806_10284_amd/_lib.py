@@ -34,7 +34,7 @@ class PcxOpts(ctypes.Structure):
         ("mode", ctypes.c_int), ("block", ctypes.c_int), ("max_iter", ctypes.c_int),
         ("tol", ctypes.c_double), ("tol_fp32", ctypes.c_double),
         ("seed", ctypes.c_ulonglong), ("precondition", ctypes.c_int), ("verbose", ctypes.c_int),
-        ("y0", ctypes.c_void_p), ("n_y0", ctypes.c_int),
+        ("y0", ctypes.c_void_p), ("n_y0", ctypes.c_int), ("orthonormalize_w", ctypes.c_int),
     ]
 
 

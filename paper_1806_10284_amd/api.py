@@ -234,15 +234,18 @@ class Plan:
     # -- eigensolver
     def pcx_solve(self, kappa, nev: int, *, mode=L.PCX_MODE_FP64, block=0, max_iter=400, tol=1e-9,
                   tol_fp32=1e-3, seed=12345, precondition=True, verbose=False, want_y=True, want_x=False,
-                  raise_on_noconv=True, y0=None):
+                  raise_on_noconv=True, y0=None, orthonormalize_w=False):
         """Returns (lambda[nev] numpy, y (nev, 2n) complex128 or None, x (nev, 3n) complex128 or None, stats).
-        y0: optional warm start, a contiguous complex128 device tensor of whole 2n-vectors."""
+        y0: optional warm start, a contiguous complex128 device tensor of whole 2n-vectors.
+        orthonormalize_w: orthonormalise the new directions against X on the host in every
+        iteration (two host synchronisations per iteration instead of one)."""
         torch = _torch()
         opts = L.PcxOpts()
         self._lib.pcx_opts_default(ctypes.byref(opts))
         opts.mode, opts.block, opts.max_iter = int(mode), int(block), int(max_iter)
         opts.tol, opts.tol_fp32, opts.seed = float(tol), float(tol_fp32), int(seed)
         opts.precondition, opts.verbose = _precond(precondition), int(bool(verbose))
+        opts.orthonormalize_w = int(bool(orthonormalize_w))
         if y0 is not None:
             opts.y0 = ctypes.c_void_p(y0.data_ptr())
             opts.n_y0 = self._check_block(y0, 2 * self.n, L.PCX_FP64, "y0")

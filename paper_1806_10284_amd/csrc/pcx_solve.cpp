@@ -449,8 +449,8 @@ struct Solver {
         // their A_r product and the Gram matrix S^H [S | AS] are queued behind the residual kernel,
         // and the residual norms and the Gram matrix reach the host together.  Should the pencil
         // fail to factor also without P, the phase continues with two synchronisations per
-        // iteration: W orthonormalised against X on the host first.
-        bool two_sync = false;
+        // iteration: W orthonormalised against X on the host first (throughout, on request).
+        bool two_sync = o.orthonormalize_w != 0;
         for (;;) {
             if (!two_sync) {
                 if ((rc = residuals_async<R>(B))) return rc;
@@ -679,6 +679,8 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     if (S.o.mode < PCX_MODE_FP64 || S.o.mode > PCX_MODE_FP32) return fail(PCX_E_ARG, "pcx_solve: bad mode");
     if (S.o.precondition < PCX_PRECOND_NONE || S.o.precondition > PCX_PRECOND_INVERSE)
         return fail(PCX_E_ARG, "pcx_solve: bad preconditioner %d", S.o.precondition);
+    if (S.o.orthonormalize_w != 0 && S.o.orthonormalize_w != 1)
+        return fail(PCX_E_ARG, "pcx_solve: orthonormalize_w must be 0 or 1");
     if (!(S.o.tol > 0) || S.o.max_iter < 1) return fail(PCX_E_ARG, "pcx_solve: bad tolerance or max_iter");
     if (b > p->max_vectors) return fail(PCX_E_ARG, "pcx_solve: block %d exceeds the plan's max_vectors", b);
     if (S.o.n_y0 < 0 || S.o.n_y0 > b || (S.o.n_y0 > 0 && !S.o.y0))

@@ -41,14 +41,17 @@ def _config1():
     return plan, kappa, eps, np.array(golden["lambda"])
 
 
+@pytest.mark.parametrize("orth", [False, True])
 @pytest.mark.parametrize("mode,tol", [(0, 1e-10), (1, 1e-10), (2, 1e-5)])
-def test_config1_eigenvalues(mode, tol):
+def test_config1_eigenvalues(mode, tol, orth):
+    """Configuration 1 against its stored dense-oracle eigenvalues, with the one-synchronisation
+    LOBPCG iteration (the default) and with W orthonormalised against X in every iteration."""
     plan, kappa, eps, ref = _config1()
-    say("solve config1 mode", mode)
+    say("solve config1 mode", mode, "orthonormalize_w", orth)
     # FP32 alone stops at its rounding floor (relative residual ~1e-4 here: FFT rounding in the
     # high modes is amplified by sqrt(Lambda_q) in the adjoint mixing); it may report NOCONV
     lam, y, x, st = plan.pcx_solve(kappa, 10, mode=mode, tol=1e-9 if mode != 2 else 1e-4,
-                                   raise_on_noconv=(mode != 2))
+                                   raise_on_noconv=(mode != 2), orthonormalize_w=orth)
     rel = np.abs(lam - ref) / ref
     say("config1 mode", mode, "iters", st.iterations, "fp32 iters", st.iterations_fp32, "matvecs", st.matvecs,
         "max rel err", rel.max(), "seconds", st.seconds)
@@ -118,8 +121,9 @@ def test_small_grids_vs_dense(case):
     np.testing.assert_allclose(lam, ref, rtol=1e-10)
 
 
+@pytest.mark.parametrize("orth", [False, True])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_next_to_gamma_vs_dense(mode):
+def test_next_to_gamma_vs_dense(mode, orth):
     """A wave vector next to Gamma (one plane wave with Lambda_q far below the others, its two bands
     near zero): the solver's near-Gamma rules (larger block, FP64 preconditioner in the FP64 phase,
     the absolute floor for bands that cannot reach tol) against the dense oracle: 1e-10 relative
@@ -135,8 +139,11 @@ def test_next_to_gamma_vs_dense(mode):
     assert ref[0] < 1e-3 * ref[2]                        # the two bands that go to zero
     plan = Plan(pcx_geometry(avec, *n), max_vectors=16)
     plan.pcx_plan_set_eps(eps)
-    say("solve next to Gamma, mode", mode)
-    lam, _, _, st = plan.pcx_solve(kappa, nev, mode=mode, tol=1e-10, want_y=False)
+    say("solve next to Gamma, mode", mode, "orthonormalize_w", orth)
+    lam, _, _, st = plan.pcx_solve(kappa, nev, mode=mode, tol=1e-10, want_y=False, orthonormalize_w=orth)
+    say("orth_fallbacks", st.orth_fallbacks)
+    if orth:
+        assert st.orth_fallbacks == 0
     lq_max = np.sum(np.abs(spectrum(og, kappa).lam) ** 2, axis=0).max()
     atol = 1e-13 * lq_max / eps.min()
     say("next to Gamma: iterations", st.iterations, "lambda", lam, "ref", ref)

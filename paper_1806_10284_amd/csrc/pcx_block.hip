@@ -1036,31 +1036,32 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_residual(ColSet X, ColSet AX, Shifts theta,
                                                    const double* __restrict__ prec, long n, ColSet W,
                                                    long rows_per_chunk, double* __restrict__ part) {
+    // grid (chunks, columns): one column of one row chunk per work-group, so the loads of all
+    // columns are in flight together rather than one column after another behind a reduction
     __shared__ double red[4];
     const int ka = X.total();
+    const int j = blockIdx.y;
     const long N = 2 * n;
     const long r0 = (long)blockIdx.x * rows_per_chunk;
     const long r1 = min(N, r0 + rows_per_chunk);
-    for (int j = 0; j < ka; ++j) {
-        const cx<R>* x = col_ptr<const cx<R>>(X, j, N);
-        const cx<R>* ax = col_ptr<const cx<R>>(AX, j, N);
-        cx<R>* w = col_ptr<cx<R>>(W, j, N);
-        const double th = theta.v[j];
-        double s = 0.0;
-        for (long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-            const cx<double> xv = to64(x[r]), av = to64(ax[r]);
-            const double rx = av.x - th * xv.x, ry = av.y - th * xv.y;
-            s = fma(rx, rx, s);
-            s = fma(ry, ry, s);
-            const double p = prec ? prec[r < n ? r : r - n] : 1.0;
-            cx<R> o;
-            o.x = (R)(p * rx);
-            o.y = (R)(p * ry);
-            w[r] = o;
-        }
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * ka + j] = s;
+    const cx<R>* x = col_ptr<const cx<R>>(X, j, N);
+    const cx<R>* ax = col_ptr<const cx<R>>(AX, j, N);
+    cx<R>* w = col_ptr<cx<R>>(W, j, N);
+    const double th = theta.v[j];
+    double s = 0.0;
+    for (long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const cx<double> xv = to64(x[r]), av = to64(ax[r]);
+        const double rx = av.x - th * xv.x, ry = av.y - th * xv.y;
+        s = fma(rx, rx, s);
+        s = fma(ry, ry, s);
+        const double p = prec ? prec[r < n ? r : r - n] : 1.0;
+        cx<R> o;
+        o.x = (R)(p * rx);
+        o.y = (R)(p * ry);
+        w[r] = o;
     }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * ka + j] = s;
 }
 
 // out[e] = sum over chunks of part[c][e]; one work-group per entry e
@@ -1084,7 +1085,8 @@ hipError_t launch_residual(const ColSet& X, const ColSet& AX, const double* thet
     long rpc = (N + nchunk - 1) / nchunk;
     rpc = (rpc + 255) / 256 * 256;
     const int chunks = (int)((N + rpc - 1) / rpc);
-    hipLaunchKernelGGL((k_residual<R>), dim3(chunks), dim3(256), 0, st, X, AX, sh, prec, n, W, rpc, part);
+    if (X.total() < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_residual<R>), dim3(chunks, X.total()), dim3(256), 0, st, X, AX, sh, prec, n, W, rpc, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int count = X.total();

@@ -346,6 +346,32 @@ static SMat solve_L_split(int k, const SMat& L, const SMat& B) {
     return X;
 }
 
+// H = Y L^{-H} where H is Hermitian (Y = L^{-1} G with G Hermitian, so H = L^{-1} G L^{-H}): the
+// lower triangle row by row from H L^H = Y, the upper one by conjugate symmetry -- a third of
+// the work of a second full triangular solve
+static SMat congruence_split(int k, const SMat& L, const SMat& Y) {
+    SMat H(k, k);
+    for (int i = 0; i < k; ++i) {
+        double* hr = H.rr(i);
+        double* hi = H.ri(i);
+        for (int j = 0; j <= i; ++j) {
+            double sr, si;
+            dotc<true>(j, L.rr(j), L.ri(j), hr, hi, sr, si);   // sum over m < j of conj(L[j][m]) H[i][m]
+            const double inv = 1.0 / L.rr(j)[j];
+            hr[j] = (Y.rr(i)[j] - sr) * inv;
+            hi[j] = (Y.ri(i)[j] - si) * inv;
+        }
+    }
+    for (int i = 0; i < k; ++i) {
+        H.ri(i)[i] = 0.0;
+        for (int j = 0; j < i; ++j) {
+            H.rr(j)[i] = H.rr(i)[j];
+            H.ri(j)[i] = -H.ri(i)[j];
+        }
+    }
+    return H;
+}
+
 // X = L^{-H} B (B: k x m), split
 static SMat solve_LH_split(int k, const SMat& L, const SMat& B) {
     SMat X = B;
@@ -397,13 +423,7 @@ bool rayleigh_ritz(int k, std::vector<zc> GA, std::vector<zc> GB, int want, doub
     SMat L;
     if (!cholesky_split(k, split(k, k, GB), L, chol_tol)) return false;
     const SMat Y = solve_L_split(k, L, split(k, k, GA));      // Y = L^{-1} GA
-    SMat Yh(k, k);
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) {
-            Yh.rr(i)[j] = Y.rr(j)[i];
-            Yh.ri(i)[j] = -Y.ri(j)[i];
-        }
-    const SMat H = solve_L_split(k, L, Yh);                  // H = L^{-1} Y^H = L^{-1} GA L^{-H}
+    const SMat H = congruence_split(k, L, Y);                // H = Y L^{-H} = L^{-1} GA L^{-H}
     std::vector<double> w;
     SMat V;
     if (!herm_eig_split(k, H, w, V, want)) return false;

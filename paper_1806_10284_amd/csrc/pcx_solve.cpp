@@ -337,13 +337,16 @@ struct Solver {
         return PCX_OK;
     }
 
-    // one phase of LOBPCG at precision R, starting from the b columns in B.X
+    // one phase of LOBPCG at precision R, starting from the b columns in B.X.  ortho_passes:
+    // Cholesky-QR passes over the start block before its Rayleigh-Ritz step; none for the FP32
+    // phase's Ritz vectors (orthonormal to FP32 rounding, so the Rayleigh-Ritz step's unit-scaled
+    // Cholesky of their Gram matrix is well conditioned and leaves them orthonormal in FP64)
     template <typename R>
-    int phase(Blocks<R>& B, double tol, int max_iter, int& iters, bool refine_after) {
+    int phase(Blocks<R>& B, double tol, int max_iter, int& iters, bool refine_after, int ortho_passes = 2) {
         int rc;
         hipError_t e = launch_mask<R>(B.X, prec, n, b, p->stream);
         if (e != hipSuccess) return hip_fail(e, "pcx_solve: mask");
-        for (int pass = 0; pass < 2; ++pass)
+        for (int pass = 0; pass < ortho_passes; ++pass)
             if ((rc = orthonormalize<R>(B.X, B.T1, b))) return rc;
         if ((rc = matvec<R>(B.X, B.AX, b))) return rc;
         if ((rc = rr_block<R>(B))) return rc;
@@ -771,7 +774,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
     } else {
         rc = seed_block(B64.X, true);
     }
-    if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false);
+    if (!rc && use64) rc = S.phase<double>(B64, S.o.tol, S.o.max_iter, iters, false, use32 ? 0 : 2);
     if (!rc && use64 && (use32 || S.o.n_y0 > 0) && iters < S.o.max_iter) {
         // an FP64 phase that stopped on stagnation with bands open, after an FP32 phase or from
         // the caller's vectors, is solved again in FP64 alone from the plain start block (seen

@@ -262,12 +262,13 @@ int pcx_solve_batch(pcx_plan *const *plans, int nplans, const int *nk, const dou
                     const pcx_opts *opts, int nworkers, double *lambda, void *const *y_out, pcx_stats *stats);
 
 /* Autotuner: times one A_r application of nvec vectors at kappa in `precision` for every
- * kernel variant the plan's grid has (the three-plane and two-plane fixed-size kernels where
- * compiled for this plane shape and precision; the register kernels for FP32 64 x 64 planes; the
- * generic plane kernels with 256, 512 and, in FP32, 1024 threads) with HIP events on the plan's
- * stream, and keeps the fastest for the plan in that precision.  choice_out (may be NULL): -1
- * three-plane, -2 two-plane fixed-size kernels, -3 register kernels, else the generic work-group
- * size; ms_out (may be NULL): its time per application
+ * kernel variant the plan's grid has (the plan's automatic choice; the three-plane and two-plane
+ * fixed-size kernels where compiled for this plane shape and precision; the register kernels for
+ * FP32 64 x 64 planes; the generic plane kernels with 256, 512 and, in FP32, 1024 threads) with
+ * HIP events on the plan's stream, and keeps the fastest for the plan in that precision.
+ * choice_out (may be NULL): 0 the automatic choice, -1 three-plane, -2 two-plane fixed-size
+ * kernels, -3 register kernels, else the generic work-group size; ms_out (may be NULL): its time
+ * per application
  * in ms.  The candidates are timed after a sustained warm-up, best of two rounds.
  * pcx_solve and pcx_solve_batch run it by default, once per process for each grid and precision they
  * use (nvec = the LOBPCG block), on plans whose variant is PCX_VARIANT_AUTO and that carry no choice

@@ -196,8 +196,8 @@ class Plan:
 
     def pcx_plan_autotune(self, kappa, precision=L.PCX_FP32, nvec: int = 8):
         """Times the kernel variants on this plan and keeps the fastest; returns (choice, ms):
-        choice -1 / -2 / -3 = three-plane / two-plane fixed-size / register-resident kernels, else
-        the generic plane work-group size."""
+        choice 0 = the plan's automatic choice, -1 / -2 / -3 = three-plane / two-plane fixed-size /
+        register-resident kernels, else the generic plane work-group size."""
         ch = ctypes.c_int()
         ms = ctypes.c_double()
         L.check(self._lib.pcx_plan_autotune(self._ptr, _kappa3(kappa), int(precision), int(nvec), ctypes.byref(ch),

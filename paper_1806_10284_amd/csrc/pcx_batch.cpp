@@ -10,9 +10,9 @@
 // others' device work.  All wave vectors of one lattice can also go through a single launch of
 // each A_r kernel (pcx_apply_Ar_multi).
 //
-// pcx_plan_autotune times the A_r kernels of a plan in each available variant (fixed-size
-// kernels for the grid, generic kernels at 256 / 512 / 1024 threads per plane) on the plan's
-// stream and keeps the fastest.
+// pcx_plan_autotune times the A_r kernels of a plan in each available variant (the automatic
+// choice, fixed-size kernels for the grid, generic kernels at 256 / 512 / 1024 threads per plane)
+// on the plan's stream and keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -233,7 +233,10 @@ extern "C" int pcx_plan_autotune(pcx_plan* pp, const double kappa[3], int precis
         return hip_fail(e, "pcx_plan_autotune: buffers");
     }
     const int f = precision == PCX_FP64 ? 1 : 0;
-    std::vector<int> cands;       // tuned_nt values: -1 fixed-size kernels, else generic group size
+    // tuned_nt values: 0 the plan's automatic choice (where the planes are too large for the
+    // one-pass kernels, the two-pass planes with the fixed-size x lines), -1 / -2 / -3 the fixed-size
+    // three-plane / two-plane / register kernels, else the generic kernels' group size
+    std::vector<int> cands{0};
     if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f, 3)) cands.push_back(-1);
     if (fixed_plane_available(p->geom.n[1], p->geom.n[2], f, 2)) cands.push_back(-2);
     // the register kernels (FP32 64 x 64 planes, n1 a multiple of 8)

@@ -92,6 +92,12 @@ def test_config4_gap_gradient_fd_64():
     kmax = int(np.argmax(lam[:, 1]))
     # the arg-min / arg-max are unique by a margin far above any h-sized change
     assert np.sort(lam[:, 2])[1] - lam[kmin, 2] > 1e-6 and lam[kmax, 1] - np.sort(lam[:, 1])[-2] > 1e-6
+    # every eigenvalue is homogeneous of degree -1 in eps (eps -> c eps scales B, so lambda -> lambda / c),
+    # so the whole-grid sum rule sum_p eps_p dJ/deps_p = -J holds at any size
+    Jv = float(J.detach())
+    sr = float(np.dot(vox, g))
+    say("config4 sum rule: sum eps dJ/deps", sr, "-J", -Jv)
+    assert abs(sr + Jv) <= 1e-7 * abs(Jv), (sr, Jv)
     # warm starts: the unperturbed eigenvectors at the two active wave vectors
     plan.pcx_plan_set_eps(vox, PCX_EPS_VOXEL)
     base = {}

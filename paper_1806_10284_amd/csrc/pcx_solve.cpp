@@ -11,6 +11,9 @@
 //   * Gram matrices accumulated in FP64 on the device and the Rayleigh-Ritz step solved in
 //     FP64 on the host (Cholesky of the basis Gram matrix, Householder tridiagonalisation and
 //     implicit QL),
+//   * one host synchronisation per iteration: the new directions enter the Rayleigh-Ritz basis
+//     without orthogonalisation against X, so the residual norms and the basis Gram matrix reach
+//     the host together,
 //   * an optional FP32 phase (FP32 storage and matvecs) followed by an FP64 phase that
 //     refines the same block to the requested residual.
 #include <chrono>

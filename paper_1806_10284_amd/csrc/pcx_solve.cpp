@@ -456,7 +456,12 @@ struct Solver {
         // and the residual norms and the Gram matrix reach the host together.  Should the pencil
         // fail to factor also without P, the phase continues with two synchronisations per
         // iteration: W orthonormalised against X on the host first (throughout, on request).
-        bool two_sync = o.orthonormalize_w != 0;
+        // At weak contrast (eps_max <= 2 eps_min) the approximate-inverse preconditioner is close to
+        // the exact inverse, so the preconditioned residual of a nearly converged column lies
+        // mostly in span X and the plain basis [X W P] is nearly dependent: there W is
+        // orthonormalised against X in every iteration (vacuum hexagonal 6 x 6 x 8 at A: 78
+        // iterations with it, 108 without, and no convergence under other rounding)
+        bool two_sync = o.orthonormalize_w != 0 || p->eps_max <= 2.0 * p->eps_min;
         for (;;) {
             if (!two_sync) {
                 if ((rc = residuals_async<R>(B))) return rc;

@@ -670,8 +670,10 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         // them (vacuum BCC 6^3 at Gamma, bands 4..7 at 73.267 next to eight at 73.292: 400
         // iterations without converging at block 10, 10 iterations at block 24).  The clusters of the
         // homogeneous medium are those of Lambda_q (each plane wave twice): for weak contrast
-        // (eps_max <= 2 eps_min), extend the block until the first plane wave outside it lies 1% above
-        // the last one inside, by at most 16 columns; at higher contrast the clusters of Lambda_q
+        // (eps_max <= 2 eps_min), extend the block until the first plane wave outside it lies 5% above
+        // the last one inside, by at most 16 columns (with 1%, a vacuum cubic 6^3 problem whose
+        // block ended 3% below the next plane wave kept two bands open after 108 iterations under
+        // a different rounding of the Rayleigh-Ritz step); at higher contrast the clusters of Lambda_q
         // split and the extension only costs time (the 510-problem gyroid figure, eps 3..30: 35.5 s
         // instead of 31 s), so there the block only avoids separating the two polarisations of one
         // plane wave.
@@ -681,7 +683,7 @@ extern "C" int pcx_solve(pcx_plan* pp, const double kappa[3], int nev, const pcx
         if (p->block_cap > 0) cap = std::min<long>(cap, p->block_cap);
         while (b < cap) {
             const double in = hp[modes[(b - 1) / 2]], out = hp[modes[b / 2]];   // 1 / Lambda_q
-            if (out <= 0.0 || in <= 0.0 || in >= 1.01 * out) break;
+            if (out <= 0.0 || in <= 0.0 || in >= (weak ? 1.05 : 1.01) * out) break;
             ++b;
         }
     }

@@ -177,29 +177,28 @@ static bool herm_eig_split(int k, SMat A, std::vector<double>& w, SMat& V, int n
         }
     }
     // A = Q T Q^H, Q = H_0 H_1 ... with H_j = I - 2 v_j v_j^H acting on the indices above j; each
-    // step updates only the trailing block A[j+1:, j+1:]
+    // step updates only the trailing block A[j+1:, j+1:], and only its lower triangle (the matrix
+    // stays Hermitian, so the upper one is implied)
     SMat R(k, k);                                   // row j: v_j (zero below index j + 1)
     std::vector<char> has(k, 0);
     std::vector<double> pr(k), pi(k), qr(k), qi(k);
     for (int j = 0; j + 2 < k; ++j) {
         const int o = j + 1, n = k - o;
-        // x = A[j+1:, j] = conj of row j's entries
-        const double* ajr = A.rr(j) + o;
-        const double* aji = A.ri(j) + o;
+        // x = A[j+1:, j], the column below the diagonal
+        double* vr = R.rr(j) + o;
+        double* vi = R.ri(j) + o;
         double xn2 = 0.0;
-        for (int i = 0; i < n; ++i) xn2 += ajr[i] * ajr[i] + aji[i] * aji[i];
+        for (int i = 0; i < n; ++i) {
+            vr[i] = A.rr(o + i)[j];
+            vi[i] = A.ri(o + i)[j];
+            xn2 += vr[i] * vr[i] + vi[i] * vi[i];
+        }
         const double xn = std::sqrt(xn2);
         if (xn == 0.0) continue;
-        const zc x0(ajr[0], -aji[0]);
+        const zc x0(vr[0], vi[0]);
         const double ax0 = std::abs(x0);
         const zc ph = ax0 > 0 ? zc(x0.real() / ax0, x0.imag() / ax0) : zc(1, 0);
         const zc alpha = -ph * xn;                  // reflect x onto alpha e_1
-        double* vr = R.rr(j) + o;
-        double* vi = R.ri(j) + o;
-        for (int i = 0; i < n; ++i) {
-            vr[i] = ajr[i];
-            vi[i] = -aji[i];
-        }
         vr[0] -= alpha.real();
         vi[0] -= alpha.imag();
         double vn2 = 0.0;
@@ -211,8 +210,23 @@ static bool herm_eig_split(int k, SMat A, std::vector<double>& w, SMat& V, int n
             vi[i] *= vs;
         }
         has[j] = 1;
-        // H A22 H = A22 - 2 (v q^H + q v^H), p = A22 v, K = v^H p (real), q = p - K v
-        for (int i = 0; i < n; ++i) dotc<false>(n, A.rr(o + i) + o, A.ri(o + i) + o, vr, vi, pr[i], pi[i]);
+        // H A22 H = A22 - 2 (v q^H + q v^H), p = A22 v, K = v^H p (real), q = p - K v; p from the
+        // lower triangle: row i's entries left of the diagonal act on v (a dot product) and, as
+        // the conjugate column, add to p below them (an axpy)
+        for (int i = 0; i < n; ++i) pr[i] = pi[i] = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double* ar = A.rr(o + i) + o;
+            const double* ai = A.ri(o + i) + o;
+            double sr, si;
+            dotc<false>(i, ar, ai, vr, vi, sr, si);                 // sum_{c < i} A[i][c] v[c]
+            pr[i] += sr + ar[i] * vr[i];
+            pi[i] += si + ar[i] * vi[i];
+            const double wr = vr[i], wi = vi[i];
+            for (int c = 0; c < i; ++c) {                           // p[c] += conj(A[i][c]) v[i]
+                pr[c] += ar[c] * wr + ai[c] * wi;
+                pi[c] += ar[c] * wi - ai[c] * wr;
+            }
+        }
         double K = 0.0;
         for (int i = 0; i < n; ++i) K += vr[i] * pr[i] + vi[i] * pi[i];
         for (int i = 0; i < n; ++i) {
@@ -223,17 +237,15 @@ static bool herm_eig_split(int k, SMat A, std::vector<double>& w, SMat& V, int n
             double* ar = A.rr(o + i) + o;
             double* ai = A.ri(o + i) + o;
             const double v2r = 2.0 * vr[i], v2i = 2.0 * vi[i], q2r = 2.0 * qr[i], q2i = 2.0 * qi[i];
-            // a[c] -= 2 v_i conj(q_c) + 2 q_i conj(v_c)
-            for (int c = 0; c < n; ++c) {
+            // a[c] -= 2 v_i conj(q_c) + 2 q_i conj(v_c), c <= i
+            for (int c = 0; c <= i; ++c) {
                 ar[c] -= v2r * qr[c] + v2i * qi[c] + q2r * vr[c] + q2i * vi[c];
                 ai[c] -= v2i * qr[c] - v2r * qi[c] + q2i * vr[c] - q2r * vi[c];
             }
         }
-        // the reduced column and row: alpha e_1
+        // the reduced column: alpha e_1
         A.rr(o)[j] = alpha.real();
         A.ri(o)[j] = alpha.imag();
-        A.rr(j)[o] = alpha.real();
-        A.ri(j)[o] = -alpha.imag();
     }
     // phases that make the sub-diagonal real and non-negative
     std::vector<zc> dph(k, zc(1, 0));
